@@ -1,0 +1,219 @@
+"""Oracle for the collapse-time path (TEST INFRASTRUCTURE ONLY).
+
+A plain FP64 CPU implementation of what the path computes, in C
+(collapse_oracle.c) behind ctypes, plus a numpy FP64 multilayer perceptron for
+the surrogate's gradient checks (mlp.py).  Only the test suite, the smoke
+check and the CPU-baseline leg of the benchmark may import it.  It shares no
+code with the HIP library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "collapse_oracle.c")
+_LIB = os.path.join(_HERE, "liborc_collapse.so")
+
+CLASSIC = 0
+TABULATED = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (strict IEEE FP64, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_eig3.argtypes = [_D, _D]
+        L.orc_lpt_axis.argtypes = [_D, ctypes.c_int, _D, _D]
+        L.orc_collapse_D.argtypes = [_D, ctypes.POINTER(ctypes.c_int)]
+        L.orc_collapse_D.restype = ctypes.c_double
+        L.orc_classic_F.argtypes = [_D]
+        L.orc_classic_F.restype = ctypes.c_double
+        L.orc_spline_natural.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc_spline_natural.restype = ctypes.c_int
+        L.orc_spline_eval.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double]
+        L.orc_spline_eval.restype = ctypes.c_double
+        L.orc_growth_invert.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double]
+        L.orc_growth_invert.restype = ctypes.c_double
+        L.orc_table_F.argtypes = [ctypes.c_int] * 3 + [_D] * 5 + [_D]
+        L.orc_table_F.restype = ctypes.c_double
+        L.orc_table_build.argtypes = [ctypes.c_int] * 3 + [_D] * 3
+        L.orc_table_build.restype = ctypes.c_int
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_update_radius.argtypes = ([ctypes.c_int64] + [_D] * 6 + [ctypes.c_int32, ctypes.c_int, ctypes.c_int]
+                                        + [_D] * 3 + [ctypes.c_int] * 3 + [_D] * 5
+                                        + [ctypes.c_int, _D, _I32, _D])
+        L.orc_points.argtypes = [ctypes.c_int64, _D, _D, _D]
+        L.orc_growth_unnorm.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_growth_unnorm.restype = ctypes.c_double
+        L.orc_growth_D.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_growth_D.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def threads() -> int:
+    return lib().orc_threads()
+
+
+def eig3(h):
+    """Sorted (descending) eigenvalues of one Hessian h = (xx,yy,zz,xy,xz,yz)."""
+    h = _f64(h)
+    lam = np.empty(3)
+    lib().orc_eig3(_p(h), _p(lam))
+    return lam
+
+
+def lpt_axis(lam, axis=0):
+    """(b_i, c_i): second- and third-order LPT coefficients of axis i."""
+    lam = _f64(lam)
+    b, c = ctypes.c_double(), ctypes.c_double()
+    lib().orc_lpt_axis(_p(lam), int(axis), ctypes.byref(b), ctypes.byref(c))
+    return b.value, c.value
+
+
+def collapse_D(lam):
+    """Growth factor at collapse for sorted eigenvalues, or None."""
+    lam = _f64(lam)
+    found = ctypes.c_int()
+    D = lib().orc_collapse_D(_p(lam), ctypes.byref(found))
+    return D if found.value else None
+
+
+def classic_F(lam):
+    lam = _f64(lam)
+    return lib().orc_classic_F(_p(lam))
+
+
+def spline_natural(x, y):
+    x, y = _f64(x), _f64(y)
+    M = np.empty_like(x)
+    if lib().orc_spline_natural(len(x), _p(x), _p(y), _p(M)) != 0:
+        raise ValueError("knots must be strictly increasing and at least 2")
+    return M
+
+
+def spline_eval(x, y, M, q):
+    x, y, M = _f64(x), _f64(y), _f64(M)
+    L = lib()
+    return np.array([L.orc_spline_eval(len(x), _p(x), _p(y), _p(M), float(v)) for v in np.atleast_1d(q)])
+
+
+def growth_invert(D, a, M, Dc):
+    D, a, M = _f64(D), _f64(a), _f64(M)
+    L = lib()
+    return np.array([L.orc_growth_invert(len(D), _p(D), _p(a), _p(M), float(v)) for v in np.atleast_1d(Dc)])
+
+
+def table_build(dk, F):
+    """F shaped (nx, ny, nd) -> second derivatives of each delta row."""
+    F = _f64(F)
+    dk = _f64(dk)
+    nx, ny, nd = F.shape
+    M = np.empty_like(F)
+    if lib().orc_table_build(nx, ny, nd, _p(dk), _p(F), _p(M)) != 0:
+        raise ValueError("bad table knots")
+    return M
+
+
+def table_F(xk, yk, dk, F, M, lam):
+    xk, yk, dk, F, M, lam = map(_f64, (xk, yk, dk, F, M, lam))
+    nx, ny, nd = F.shape
+    return lib().orc_table_F(nx, ny, nd, _p(xk), _p(yk), _p(dk), _p(F), _p(M), _p(lam))
+
+
+def points(h6):
+    """Per point: sorted eigenvalues (n, 3) and Classic F (n,).  h6 is (6, n)."""
+    h6 = _f64(h6)
+    n = h6.shape[1]
+    lam = np.empty((n, 3))
+    F = np.empty(n)
+    lib().orc_points(n, _p(h6), _p(lam), _p(F))
+    return lam, F
+
+
+class Growth:
+    """Inverse growth spline a(D) built from a growth table (a_k, D_k)."""
+
+    def __init__(self, a, D):
+        self.a = _f64(a)
+        self.D = _f64(D)
+        self.M = spline_natural(self.D, self.a)
+
+
+class Table:
+    """Tabulated F over knots (x, y, delta); F shaped (nx, ny, nd)."""
+
+    def __init__(self, xk, yk, dk, F):
+        self.xk, self.yk, self.dk = _f64(xk), _f64(yk), _f64(dk)
+        self.F = _f64(F)
+        self.M = table_build(self.dk, self.F)
+
+
+def update_radius(h6, radius_index, growth: Growth, Fmax, Rmax, acoll, reset, method=CLASSIC,
+                  table: Table | None = None):
+    """Apply one smoothing radius to the running maxima (in place).
+    h6: (6, n) float64; Fmax float64[n], Rmax int32[n], acoll float64[n] or None."""
+    h6 = _f64(h6)
+    n = h6.shape[1]
+    assert Fmax.dtype == np.float64 and Fmax.flags.c_contiguous and Fmax.shape == (n,)
+    assert Rmax.dtype == np.int32 and Rmax.flags.c_contiguous and Rmax.shape == (n,)
+    if acoll is not None:
+        assert acoll.dtype == np.float64 and acoll.flags.c_contiguous and acoll.shape == (n,)
+    null = ctypes.cast(None, _D)
+    if method == TABULATED:
+        t = table
+        nx, ny, nd = t.F.shape
+        targs = (nx, ny, nd, _p(t.xk), _p(t.yk), _p(t.dk), _p(t.F), _p(t.M))
+    else:
+        targs = (0, 0, 0, null, null, null, null, null)
+    lib().orc_update_radius(n, *[_p(h6[c]) for c in range(6)], int(radius_index), int(method),
+                            len(growth.D), _p(growth.D), _p(growth.a), _p(growth.M), *targs,
+                            int(bool(reset)), _p(Fmax), Rmax.ctypes.data_as(_I32),
+                            _p(acoll) if acoll is not None else null)
+
+
+def collapse(slabs, growth: Growth, method=CLASSIC, tables=None, with_acoll=True):
+    """Run every radius in order.  slabs: iterable of (6, n) arrays.
+    Returns (Fmax, Rmax, acoll)."""
+    Fmax = Rmax = acoll = None
+    for r, h6 in enumerate(slabs):
+        h6 = _f64(h6)
+        if Fmax is None:
+            n = h6.shape[1]
+            Fmax = np.zeros(n)
+            Rmax = np.full(n, -1, dtype=np.int32)
+            acoll = np.full(n, np.inf) if with_acoll else None
+        update_radius(h6, r, growth, Fmax, Rmax, acoll, reset=(r == 0), method=method,
+                      table=None if tables is None else tables[r])
+    return Fmax, Rmax, acoll

@@ -1,0 +1,466 @@
+/*
+ * Oracle for the per-particle collapse-time computation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, FP64 CPU implementation
+ * written to be checked against the paper by eye.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the HIP
+ * library never does, and the two share no source, header or table.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -shared -fPIC.
+ *
+ * What it computes, with the passages it follows:
+ *   - eigenvalues of the 3x3 Hessian of the smoothed potential, sorted in
+ *     descending order (Sec. 3: "standard analytic method", sorted
+ *     descending).  Here: cyclic Jacobi rotations, not the trigonometric
+ *     closed form the kernel uses.
+ *   - the Classic collapse: third-order LPT of a homogeneous ellipsoid gives a
+ *     non-linear algebraic equation for the growth factor at collapse
+ *     (Sec. 3).  The paper does not print the equation; the reading used is
+ *     stated at orc_lpt_axis() below.  The smallest positive root is found by
+ *     splitting (0, inf) at the critical points of the cubic and bisecting the
+ *     first piece that changes sign.
+ *   - the Tabulated collapse: a table over delta = sum l, x = l1 - l2,
+ *     y = l2 - l3 interpolated with a cubic spline in delta and bilinearly in
+ *     (x, y) (Sec. 3, Sec. 4.2).
+ *   - the natural cubic spline (Sec. 4.2; the GSL routine the paper replaces
+ *     is the natural spline) and the inversion of the growth table a(D)
+ *     (Sec. 3, z_coll = 1/a_coll - 1).
+ *   - the per-element maxima over smoothing radii (Sec. 4.1: the kernel
+ *     updates two output arrays per element; here F = 1/D_c, its radius index,
+ *     and a_coll).
+ *   - D(a) of flat LCDM from the closed-form growth integral, used only to
+ *     check the growth tables handed to both implementations.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_CLASSIC 0
+#define ORC_TABULATED 1
+
+/* ------------------------------------------------------------------------ */
+/* Eigenvalues: cyclic Jacobi on a symmetric 3x3 matrix.                    */
+/* h = (xx, yy, zz, xy, xz, yz).  lam[0] >= lam[1] >= lam[2].               */
+/* ------------------------------------------------------------------------ */
+void orc_eig3(const double h[6], double lam[3])
+{
+    double A[3][3] = {{h[0], h[3], h[4]}, {h[3], h[1], h[5]}, {h[4], h[5], h[2]}};
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (!(off > 0.0) || off <= 1e-40 * dia)
+            break;
+        for (int p = 0; p < 2; ++p) {
+            for (int q = p + 1; q < 3; ++q) {
+                double apq = A[p][q];
+                if (apq == 0.0)
+                    continue;
+                /* rotation angle that zeroes A[p][q] */
+                double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+                double t;
+                if (fabs(theta) > 1e150)
+                    t = 0.5 / theta;
+                else
+                    t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0);
+                double s = t * c;
+                A[p][p] -= t * apq;
+                A[q][q] += t * apq;
+                A[p][q] = A[q][p] = 0.0;
+                for (int r = 0; r < 3; ++r) {
+                    if (r == p || r == q)
+                        continue;
+                    double arp = A[r][p], arq = A[r][q];
+                    A[r][p] = A[p][r] = c * arp - s * arq;
+                    A[r][q] = A[q][r] = s * arp + c * arq;
+                }
+            }
+        }
+    }
+    double d[3] = {A[0][0], A[1][1], A[2][2]};
+    /* sort descending (three elements: plain exchange sort) */
+    for (int i = 0; i < 3; ++i)
+        for (int j = i + 1; j < 3; ++j)
+            if (d[j] > d[i]) {
+                double tmp = d[i];
+                d[i] = d[j];
+                d[j] = tmp;
+            }
+    lam[0] = d[0];
+    lam[1] = d[1];
+    lam[2] = d[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Classic collapse: the LPT reading.                                       */
+/*                                                                          */
+/* Each principal axis of the Lagrangian sphere evolves as                  */
+/*   R_i / q_i = 1 - l_i D + b_i D^2 + c_i D^3   (EdS growing modes),       */
+/* where, with a_i = -l_i, A_i = sum_{j!=i} a_j, B_i = sum_{j!=i} b_j:      */
+/*   b_i = -(3/14) l_i (l_1 + l_2 + l_3 - l_i)                              */
+/*   c_i = -(1/12) a_i B_i - (17/36) b_i A_i - (1/9) a_1 a_2 a_3.           */
+/* Their sums reproduce the second- and third-order LPT trace conditions    */
+/* and, for l_1 = l_2 = l_3, the exact spherical-collapse series.  Collapse */
+/* is the first crossing of the axis with the largest eigenvalue, R_1 = 0.  */
+/* ------------------------------------------------------------------------ */
+void orc_lpt_axis(const double lam[3], int axis, double *b_out, double *c_out)
+{
+    double a[3], b[3];
+    double mu1 = lam[0] + lam[1] + lam[2];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = -lam[i];
+        b[i] = -(3.0 / 14.0) * lam[i] * (mu1 - lam[i]);
+    }
+    double A = 0.0, B = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        if (j == axis)
+            continue;
+        A += a[j];
+        B += b[j];
+    }
+    double c = -(1.0 / 12.0) * a[axis] * B - (17.0 / 36.0) * b[axis] * A - (1.0 / 9.0) * a[0] * a[1] * a[2];
+    *b_out = b[axis];
+    *c_out = c;
+}
+
+static double g_axis(double l1, double beta, double gamma, double D)
+{
+    return 1.0 - l1 * D + beta * D * D + gamma * D * D * D;
+}
+
+/* smallest positive root of g on (lo, hi], given g(lo) > 0 >= g(hi) and g
+ * monotone on the piece: bisection down to adjacent doubles */
+static double bisect(double l1, double beta, double gamma, double lo, double hi)
+{
+    for (int it = 0; it < 5000; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi))
+            break;
+        if (g_axis(l1, beta, gamma, mid) > 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
+/* Growth factor at collapse for sorted eigenvalues lam; *found = 0 when the
+ * axis never collapses (returns 0). */
+double orc_collapse_D(const double lam[3], int *found)
+{
+    double l1 = lam[0], beta, gamma;
+    orc_lpt_axis(lam, 0, &beta, &gamma);
+    *found = 0;
+    if (!(isfinite(l1) && isfinite(beta) && isfinite(gamma)))
+        return 0.0;
+
+    /* positive critical points of g: roots of -l1 + 2 beta D + 3 gamma D^2 */
+    double crit[2];
+    int nc = 0;
+    if (gamma == 0.0) {
+        if (beta != 0.0) {
+            double d = l1 / (2.0 * beta);
+            if (d > 0.0)
+                crit[nc++] = d;
+        }
+    } else {
+        double disc = beta * beta + 3.0 * gamma * l1;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double Q = -(beta + (beta >= 0.0 ? sq : -sq));
+            if (Q != 0.0) {
+                double r1 = Q / (3.0 * gamma);
+                double r2 = -l1 / Q;
+                if (r1 > 0.0)
+                    crit[nc++] = r1;
+                if (r2 > 0.0)
+                    crit[nc++] = r2;
+                if (nc == 2 && crit[1] < crit[0]) {
+                    double tmp = crit[0];
+                    crit[0] = crit[1];
+                    crit[1] = tmp;
+                }
+            }
+        }
+    }
+
+    /* walk the monotone pieces [0, c1], [c1, c2], ... and bisect the first
+     * one whose end values straddle zero */
+    double lo = 0.0;
+    for (int k = 0; k < nc; ++k) {
+        double hi = crit[k];
+        if (g_axis(l1, beta, gamma, lo) > 0.0 && g_axis(l1, beta, gamma, hi) <= 0.0) {
+            *found = 1;
+            return bisect(l1, beta, gamma, lo, hi);
+        }
+        lo = hi;
+    }
+    /* last piece [lo, inf): g goes to -inf only if its leading term is negative */
+    int falls = (gamma < 0.0) || (gamma == 0.0 && beta < 0.0) || (gamma == 0.0 && beta == 0.0 && l1 > 0.0);
+    if (!falls || !(g_axis(l1, beta, gamma, lo) > 0.0))
+        return 0.0;
+    double hi = lo > 0.0 ? 2.0 * lo : 1.0;
+    while (g_axis(l1, beta, gamma, hi) > 0.0) {
+        hi *= 2.0;
+        if (hi > 1e300)
+            return 0.0;
+    }
+    *found = 1;
+    return bisect(l1, beta, gamma, lo, hi);
+}
+
+/* inverse collapse time F = 1/D_c, 0 when there is no collapse */
+double orc_classic_F(const double lam[3])
+{
+    int found;
+    double D = orc_collapse_D(lam, &found);
+    return found ? 1.0 / D : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Natural cubic spline (second derivatives zero at both ends).             */
+/* ------------------------------------------------------------------------ */
+
+/* Second derivatives M[0..n-1].  Returns 0, or -1 if n < 2 or the knots are
+ * not strictly increasing.  Tridiagonal system for the interior knots,
+ *   h_{i-1} M_{i-1} + 2 (h_{i-1} + h_i) M_i + h_i M_{i+1}
+ *     = 6 [ (y_{i+1} - y_i)/h_i - (y_i - y_{i-1})/h_{i-1} ],
+ * solved by Gaussian elimination without pivoting (diagonally dominant). */
+int orc_spline_natural(int n, const double *x, const double *y, double *M)
+{
+    if (n < 2)
+        return -1;
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(x[i + 1] > x[i]))
+            return -1;
+    for (int i = 0; i < n; ++i)
+        M[i] = 0.0;
+    if (n == 2)
+        return 0;
+    int m = n - 2; /* unknowns M[1..n-2] */
+    double *sub = (double *)malloc(sizeof(double) * m);
+    double *dia = (double *)malloc(sizeof(double) * m);
+    double *sup = (double *)malloc(sizeof(double) * m);
+    double *rhs = (double *)malloc(sizeof(double) * m);
+    for (int k = 0; k < m; ++k) {
+        int i = k + 1;
+        double hl = x[i] - x[i - 1], hr = x[i + 1] - x[i];
+        sub[k] = hl;
+        dia[k] = 2.0 * (hl + hr);
+        sup[k] = hr;
+        rhs[k] = 6.0 * ((y[i + 1] - y[i]) / hr - (y[i] - y[i - 1]) / hl);
+    }
+    /* forward elimination */
+    for (int k = 1; k < m; ++k) {
+        double f = sub[k] / dia[k - 1];
+        dia[k] -= f * sup[k - 1];
+        rhs[k] -= f * rhs[k - 1];
+    }
+    /* back substitution */
+    M[m] = rhs[m - 1] / dia[m - 1];
+    for (int k = m - 2; k >= 0; --k)
+        M[k + 1] = (rhs[k] - sup[k] * M[k + 2]) / dia[k];
+    free(sub);
+    free(dia);
+    free(sup);
+    free(rhs);
+    return 0;
+}
+
+/* index i with x[i] <= q < x[i+1]; q at or beyond the last knot maps to the
+ * last interval, q below the first knot to the first */
+static int locate(int n, const double *x, double q)
+{
+    int lo = 0, hi = n - 1;
+    if (q >= x[n - 1])
+        return n - 2;
+    if (q <= x[0])
+        return 0;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (x[mid] <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+/* S(q) on [x_i, x_{i+1}], t = (q - x_i)/h_i:
+ *   S = (1-t) y_i + t y_{i+1} + (h_i^2/6) [((1-t)^3 - (1-t)) M_i + (t^3 - t) M_{i+1}] */
+double orc_spline_eval(int n, const double *x, const double *y, const double *M, double q)
+{
+    int i = locate(n, x, q);
+    double h = x[i + 1] - x[i];
+    double t = (q - x[i]) / h;
+    double s = 1.0 - t;
+    return s * y[i] + t * y[i + 1] + (h * h / 6.0) * ((s * s * s - s) * M[i] + (t * t * t - t) * M[i + 1]);
+}
+
+/* a(D) through the natural spline of (D_k, a_k).  D beyond the last knot
+ * (collapse after the end of the table) gives +inf; D below the first knot is
+ * clamped to the first scale factor. */
+double orc_growth_invert(int nk, const double *D, const double *a, const double *M, double Dc)
+{
+    if (!(Dc <= D[nk - 1]))
+        return INFINITY;
+    if (Dc < D[0])
+        return a[0];
+    return orc_spline_eval(nk, D, a, M, Dc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tabulated collapse: cubic spline in delta at the four corners of the     */
+/* (x, y) cell, then bilinear interpolation.                                */
+/* F[(ix*ny + iy)*nd + id], M the natural-spline second derivatives of each  */
+/* delta row.  Out-of-range coordinates are clamped to the table.           */
+/* ------------------------------------------------------------------------ */
+double orc_table_F(int nx, int ny, int nd, const double *xk, const double *yk, const double *dk,
+                   const double *F, const double *M, const double lam[3])
+{
+    double delta = lam[0] + lam[1] + lam[2];
+    double x = lam[0] - lam[1];
+    double y = lam[1] - lam[2];
+    if (!(isfinite(delta) && isfinite(x) && isfinite(y)))
+        return 0.0;
+    int ix = locate(nx, xk, x);
+    int iy = locate(ny, yk, y);
+    double t = (x - xk[ix]) / (xk[ix + 1] - xk[ix]);
+    double u = (y - yk[iy]) / (yk[iy + 1] - yk[iy]);
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    if (u < 0.0) u = 0.0;
+    if (u > 1.0) u = 1.0;
+    double dq = delta;
+    if (dq < dk[0]) dq = dk[0];
+    if (dq > dk[nd - 1]) dq = dk[nd - 1];
+    double v[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            size_t row = ((size_t)(ix + a) * ny + (iy + b)) * nd;
+            v[a][b] = orc_spline_eval(nd, dk, F + row, M + row, dq);
+        }
+    double f = (1.0 - t) * (1.0 - u) * v[0][0] + t * (1.0 - u) * v[1][0] + (1.0 - t) * u * v[0][1] + t * u * v[1][1];
+    return f > 0.0 ? f : 0.0;
+}
+
+/* second derivatives of every delta row of a table */
+int orc_table_build(int nx, int ny, int nd, const double *dk, const double *F, double *M)
+{
+    for (int r = 0; r < nx * ny; ++r)
+        if (orc_spline_natural(nd, dk, F + (size_t)r * nd, M + (size_t)r * nd) != 0)
+            return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One smoothing radius: per particle, eigenvalues -> F -> max update.       */
+/* ------------------------------------------------------------------------ */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_update_radius(int64_t n, const double *hxx, const double *hyy, const double *hzz, const double *hxy,
+                       const double *hxz, const double *hyz, int32_t radius_index, int method, int nk,
+                       const double *gD, const double *ga, const double *gM, int nx, int ny, int nd,
+                       const double *xk, const double *yk, const double *dk, const double *tF, const double *tM,
+                       int reset, double *Fmax, int32_t *Rmax, double *acoll)
+{
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+        if (reset) {
+            Fmax[i] = 0.0;
+            Rmax[i] = -1;
+            if (acoll)
+                acoll[i] = INFINITY;
+        }
+        double h[6] = {hxx[i], hyy[i], hzz[i], hxy[i], hxz[i], hyz[i]};
+        double lam[3];
+        orc_eig3(h, lam);
+        double F, Dc;
+        if (method == ORC_CLASSIC) {
+            int found;
+            Dc = orc_collapse_D(lam, &found);
+            F = found ? 1.0 / Dc : 0.0;
+        } else {
+            F = orc_table_F(nx, ny, nd, xk, yk, dk, tF, tM, lam);
+            Dc = 1.0 / F;
+        }
+        if (F > Fmax[i]) {
+            Fmax[i] = F;
+            Rmax[i] = radius_index;
+            if (acoll)
+                acoll[i] = orc_growth_invert(nk, gD, ga, gM, Dc);
+        }
+    }
+}
+
+/* per-point diagnostics: sorted eigenvalues and Classic F */
+void orc_points(int64_t n, const double *h6, double *lam_out, double *F_out)
+{
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+        double h[6];
+        for (int c = 0; c < 6; ++c)
+            h[c] = h6[(size_t)c * n + i];
+        double lam[3];
+        orc_eig3(h, lam);
+        lam_out[3 * i + 0] = lam[0];
+        lam_out[3 * i + 1] = lam[1];
+        lam_out[3 * i + 2] = lam[2];
+        F_out[i] = orc_classic_F(lam);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linear growth of flat LCDM from the closed-form integral                  */
+/*   D(a) = (5 Om / 2) E(a) int_0^a da' / (a' E(a'))^3,                      */
+/* substituting a' = t^2, which makes the integrand 2 t^4 (Om + OL t^6)^-3/2. */
+/* Adaptive Simpson quadrature.                                             */
+/* ------------------------------------------------------------------------ */
+static double growth_integrand(double t, double om)
+{
+    double ol = 1.0 - om;
+    double s = om + ol * t * t * t * t * t * t;
+    return 2.0 * t * t * t * t / (s * sqrt(s));
+}
+
+static double simpson_rec(double a, double b, double fa, double fm, double fb, double whole, double tol, int depth,
+                          double om)
+{
+    double m = 0.5 * (a + b);
+    double lm = 0.5 * (a + m), rm = 0.5 * (m + b);
+    double flm = growth_integrand(lm, om), frm = growth_integrand(rm, om);
+    double left = (m - a) / 6.0 * (fa + 4.0 * flm + fm);
+    double right = (b - m) / 6.0 * (fm + 4.0 * frm + fb);
+    double delta = left + right - whole;
+    if (depth <= 0 || fabs(delta) <= 15.0 * tol)
+        return left + right + delta / 15.0;
+    return simpson_rec(a, m, fa, flm, fm, left, 0.5 * tol, depth - 1, om) +
+           simpson_rec(m, b, fm, frm, fb, right, 0.5 * tol, depth - 1, om);
+}
+
+double orc_growth_unnorm(double om, double a)
+{
+    double tb = sqrt(a);
+    double fa = growth_integrand(0.0, om), fb = growth_integrand(tb, om), fm = growth_integrand(0.5 * tb, om);
+    double whole = tb / 6.0 * (fa + 4.0 * fm + fb);
+    double integral = simpson_rec(0.0, tb, fa, fm, fb, whole, 1e-14 * fabs(whole), 40, om);
+    double E = sqrt(om / (a * a * a) + 1.0 - om);
+    return 2.5 * om * E * integral;
+}
+
+double orc_growth_D(double om, double a)
+{
+    return orc_growth_unnorm(om, a) / orc_growth_unnorm(om, 1.0);
+}
