@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the collapse-time path on one MI355X.
+
+Workload: 256^3 particles in a periodic 100 Mpc/h box, 25 Gaussian smoothing
+radii log-spaced 20 -> 0.5 Mpc/h (flat LCDM, Omega_m = 0.3, sigma8 = 0.8,
+n_s = 0.96, BBKS), 512-point growth table; plain FP64 Classic collapse.  All 25
+FP64 Hessian slabs (20 GB) are resident in HBM before timing starts.  One
+step = all 25 radii over all particles (one kernel launch per radius), i.e.
+4.19e8 particle-radius collapse evaluations.
+
+Prints one JSON line (rank 0): evals/s, the roofline of the collapse kernel
+(algorithmic bytes per launch / its mean launch time from HIP events on the
+launch stream) and the oracle's rate on a bounded sample of the same
+workload on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle·radius collapse evals/s, plain FP64 vs surrogate+certify, at ≤1e-6 rel err"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n, updates, reset):
+    """HBM bytes one launch must move: 6 FP64 Hessian components (48 B), the
+    running Fmax (8 B, not read on the RESET radius) and, for every particle
+    whose max changes (all of them on RESET), Fmax + Rmax + a_coll (20 B)."""
+    if reset:
+        return n * (48 + 20)
+    return n * (48 + 8) + updates * 20
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 18, help="particles in the oracle sample")
+    ap.add_argument("--n-side", type=int, default=None, help="override the grid side (testing only)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 (the per-particle "
+                                   "collapse path has no cross-GPU step, see the design notes on sharding)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2510_02873_amd as P
+    import synth
+
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2510_02873_amd import build as libbuild
+        libbuild.build()
+
+    cfg = synth.config("C2")
+    n_side = args.n_side or cfg["n_side"]
+    radii = cfg["radii"]
+    n = n_side ** 3
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    a, D = synth.growth_table(cfg["cosmo"].omega_m, cfg["n_growth"])
+    fld = synth.fields.field(n_side, cfg["box"], cfg["seed"], cfg["cosmo"], device=dev)
+    slabs = [fld.hessian(R) for R in radii]
+    del fld
+    torch.cuda.synchronize()
+    log(f"inputs ready: n={n} radii={len(radii)} in {time.time() - t0:.1f}s "
+        f"({len(radii) * 48 * n / 1e9:.1f} GB of Hessians resident)")
+
+    col = P.Collapse([(a, D)], device=0)
+    Fmax, Rmax, ac = col.outputs(n)
+    stream = torch.cuda.current_stream(dev)
+
+    # untimed pass: how many particles update their max at each radius
+    updates = []
+    prev = None
+    for r in range(len(radii)):
+        col.apply(slabs[r], r, Fmax, Rmax, ac, reset=(r == 0), stream=stream)
+        cur = Fmax.clone()
+        updates.append(int(n if prev is None else (cur != prev).sum().item()))
+        prev = cur
+    del prev, cur
+    bytes_per_launch = [algorithmic_bytes(n, u, r == 0) for r, u in enumerate(updates)]
+
+    items = [col.item(slabs[r], Fmax, Rmax, ac, radius_index=r) for r in range(len(radii))]
+
+    def step(events=None):
+        for r, it in enumerate(items):
+            if events is not None:
+                events[r][0].record(stream)
+            col.eval([it], reset=(r == 0), stream=stream)
+            if events is not None:
+                events[r][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in radii]
+          for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for k in range(args.steps):
+        step(ev[k])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    launch_ms = np.array([[e[0].elapsed_time(e[1]) for e in ev[k]] for k in range(args.steps)])
+    log(f"timed {args.steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.2f} ms)")
+
+    evals_per_step = n * len(radii)
+    ms_per_step = total_ms / args.steps
+    value = evals_per_step / (ms_per_step * 1e-3)
+
+    # roofline of the collapse kernel: algorithmic bytes of each launch over
+    # its measured duration, averaged over launches
+    mean_launch_ms = float(launch_ms.mean())
+    mean_bytes = float(np.mean(bytes_per_launch))
+    achieved_gbs = mean_bytes / (mean_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_classic_f64", "mean_launch_us": round(mean_launch_ms * 1e3, 2),
+                "bytes_per_launch": int(mean_bytes), "update_fraction": round(
+                    float(np.mean([u / n for u in updates[1:]])), 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(12345)
+        m = min(args.cpu_sample, n)
+        idx = torch.from_numpy(np.sort(rng.choice(n, size=m, replace=False))).to(dev)
+        sample = [s[:, idx].cpu().numpy() for s in slabs]
+        g = oracle.Growth(a, D)
+        log(f"cpu baseline: oracle on {m} particles x {len(radii)} radii, {oracle.threads()} threads")
+        c0 = time.perf_counter()
+        ref = oracle.collapse(sample, g)
+        dt = time.perf_counter() - c0
+        cpu = {"value": round(m * len(radii) / dt, 1), "unit": "evals/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"{m} seeded-random particles of the same 256^3 fields x all {len(radii)} radii "
+                         f"({dt:.1f} s)"}
+        # the sampled particles also serve as a parity spot check of this run
+        got_F = Fmax[idx].cpu().numpy()
+        big = ref[0] >= 1e-6
+        rel = float(np.max(np.abs(1 / got_F[big] - 1 / ref[0][big]) * ref[0][big])) if big.any() else 0.0
+        cpu["parity_max_rel_Dc"] = rel
+        log(f"cpu baseline {cpu['value']:.3e} evals/s; sample parity max rel D_c {rel:.2e}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded Gaussian BBKS field, FFT Hessians (no dataset)",
+        "config": {"workload": f"plain-fp64-classic-{n_side}cube-{len(radii)}radii",
+                   "particles": n, "radii": len(radii), "evals_per_step": evals_per_step,
+                   "box_mpc_h": cfg["box"], "growth_knots": cfg["n_growth"], "method": "classic",
+                   "precision": "fp64"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    col.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+"""ctypes binding of include/pino_collapse.h (argument marshalling only).
+
+The functions keep the C names.  Device buffers are torch tensors (their
+data_ptr() is passed); streams are torch streams (their cuda_stream handle is
+passed).  Loading fails loudly when the HIP library has not been built: there
+is no other implementation behind these names.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpino_collapse.so")
+
+PINO_ABI_VERSION = 1
+PINO_OK, PINO_ERR_ARG, PINO_ERR_ALLOC, PINO_ERR_HIP, PINO_ERR_STATE, PINO_ERR_UNSUPPORTED = range(6)
+PINO_CLASSIC, PINO_TABULATED = 0, 1
+PINO_FP64, PINO_MIXED, PINO_SURROGATE = 0, 1, 2
+PINO_EVAL_RESET = 1
+PINO_EVAL_SYNC = 2
+
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+class pino_growth(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("a", _D), ("D", _D)]
+
+
+class pino_table_knots(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nd", ctypes.c_int32),
+                ("x", _D), ("y", _D), ("delta", _D)]
+
+
+class pino_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("n_cosmo", ctypes.c_int32), ("growth", ctypes.POINTER(pino_growth)),
+                ("table", ctypes.POINTER(pino_table_knots)), ("mlp", ctypes.c_void_p),
+                ("mlp_bytes", ctypes.c_int64), ("certify_rtol", ctypes.c_double)]
+
+
+class pino_item(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("h", ctypes.c_void_p * 6), ("cosmo", ctypes.c_int32),
+                ("radius_index", ctypes.c_int32), ("sigma_R", ctypes.c_double),
+                ("table_F", ctypes.c_void_p), ("Fmax", ctypes.c_void_p), ("Rmax", ctypes.c_void_p),
+                ("a_coll", ctypes.c_void_p)]
+
+
+class PinoError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"pino status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTED = ("pino_collapse_init", "pino_collapse_eval", "pino_collapse_free", "pino_collapse_last_error")
+
+
+def lib():
+    """Load libpino_collapse.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or python paper_2510_02873_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pino_collapse_init.argtypes = [ctypes.POINTER(pino_config), ctypes.POINTER(ctypes.c_void_p)]
+        L.pino_collapse_init.restype = ctypes.c_int
+        L.pino_collapse_eval.argtypes = [ctypes.c_void_p, ctypes.POINTER(pino_item), ctypes.c_int32,
+                                         ctypes.c_uint32, ctypes.c_void_p]
+        L.pino_collapse_eval.restype = ctypes.c_int
+        L.pino_collapse_free.argtypes = [ctypes.c_void_p]
+        L.pino_collapse_free.restype = ctypes.c_int
+        L.pino_collapse_last_error.argtypes = [ctypes.c_void_p]
+        L.pino_collapse_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def pino_collapse_last_error(ctx=None) -> str:
+    return lib().pino_collapse_last_error(ctx).decode()
+
+
+def _check(status, ctx=None):
+    if status != PINO_OK:
+        raise PinoError(status, pino_collapse_last_error(ctx))
+
+
+def _host_f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Config:
+    """Holds the host arrays a pino_config points to for the duration of init."""
+
+    def __init__(self, growth_tables, method=PINO_CLASSIC, precision=PINO_FP64, device=0,
+                 table_knots=None, mlp_blob=None, certify_rtol=0.0, abi_version=PINO_ABI_VERSION):
+        self._keep = []
+        arr = (pino_growth * max(1, len(growth_tables)))()
+        for k, (a, D) in enumerate(growth_tables):
+            a, D = _host_f64(a), _host_f64(D)
+            self._keep += [a, D]
+            arr[k] = pino_growth(len(a), a.ctypes.data_as(_D), D.ctypes.data_as(_D))
+        self._growth = arr
+        self.c = pino_config()
+        self.c.abi_version = abi_version
+        self.c.method = method
+        self.c.precision = precision
+        self.c.device = device
+        self.c.n_cosmo = len(growth_tables)
+        self.c.growth = ctypes.cast(arr, ctypes.POINTER(pino_growth))
+        if table_knots is not None:
+            x, y, d = (_host_f64(v) for v in table_knots)
+            self._keep += [x, y, d]
+            self._tk = pino_table_knots(len(x), len(y), len(d), x.ctypes.data_as(_D),
+                                        y.ctypes.data_as(_D), d.ctypes.data_as(_D))
+            self.c.table = ctypes.pointer(self._tk)
+        if mlp_blob is not None:
+            blob = np.frombuffer(bytes(mlp_blob), dtype=np.uint8).copy()
+            self._keep.append(blob)
+            self.c.mlp = blob.ctypes.data
+            self.c.mlp_bytes = blob.nbytes
+        self.c.certify_rtol = certify_rtol
+
+
+def pino_collapse_init(cfg: Config):
+    """Returns an opaque context handle (int)."""
+    out = ctypes.c_void_p()
+    _check(lib().pino_collapse_init(ctypes.byref(cfg.c), ctypes.byref(out)))
+    return out.value
+
+
+def pino_collapse_free(ctx):
+    if ctx is not None:
+        _check(lib().pino_collapse_free(ctx))
+
+
+def make_item(h, Fmax, Rmax, a_coll=None, radius_index=0, cosmo=0, sigma_R=1.0, table_F=None, n=None):
+    """h: sequence of 6 device tensors (or a (6, n) tensor); outputs device tensors."""
+    it = pino_item()
+    comps = [h[c] for c in range(6)]
+    it.n = int(comps[0].numel()) if n is None else int(n)
+    for c in range(6):
+        it.h[c] = comps[c].data_ptr()
+    it.cosmo = cosmo
+    it.radius_index = radius_index
+    it.sigma_R = sigma_R
+    it.table_F = None if table_F is None else table_F.data_ptr()
+    it.Fmax = Fmax.data_ptr()
+    it.Rmax = Rmax.data_ptr()
+    it.a_coll = None if a_coll is None else a_coll.data_ptr()
+    return it
+
+
+def pino_collapse_eval(ctx, items, flags=0, stream=None):
+    """items: list of pino_item; stream: torch stream, raw handle, or None."""
+    n = len(items)
+    arr = (pino_item * max(1, n))(*items)
+    handle = stream
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        handle = stream.cuda_stream
+    _check(lib().pino_collapse_eval(ctx, arr, n, flags, handle), ctx)

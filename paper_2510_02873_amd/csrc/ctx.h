@@ -1,0 +1,39 @@
+// Library context behind the opaque pino_ctx handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+struct pino_ctx {
+    int device = 0;
+    int method = 0;
+    int precision = 0;
+    int n_cosmo = 0;
+    int cu_count = 1;
+    int blocks_per_cu = 8;
+
+    // growth tables [D | a | M] per cosmology, stride 3 * nk_max doubles
+    int nk_max = 0;
+    std::vector<int> nk;
+    double* d_growth = nullptr;
+
+    // tabulated method: dimensionless knots [x | y | delta], the interleaved
+    // (F, M) table of the current radius, sigma-scaled delta knots
+    int nx = 0, ny = 0, nd = 0;
+    double* d_tknots = nullptr;
+    double* d_tab = nullptr;
+    double* d_dscaled = nullptr;
+
+    // spline-build scratch
+    double* d_tmp = nullptr;
+
+    // surrogate network (device copy of the weight blob)
+    void* d_mlp = nullptr;
+    double certify_rtol = 1e-7;
+    int64_t* d_counters = nullptr;
+
+    bool broken = false;
+    std::string err = "no error";
+};

@@ -1,0 +1,297 @@
+// Device building blocks of the collapse-time path (gfx950).
+//
+// eig_*      : eigenvalues of the 3x3 symmetric Hessian by the trigonometric
+//              closed form of the characteristic cubic (Sec. 3: an analytic
+//              method, eigenvalues sorted in descending order).
+// lpt_root_* : smallest positive root of the axis-1 third-order LPT collapse
+//              cubic (Sec. 3), solved in u = l1 * D by a bracketed Halley
+//              iteration; the bracket comes from the critical points of the
+//              cubic so the root returned is the first crossing.
+// spline_*   : natural cubic spline evaluation with knots staged in LDS and a
+//              branch-free binary search (Sec. 4.2).
+//
+// Every function is straight-line code or a loop with a per-lane exit, so
+// lanes of a wavefront follow the same instruction stream (Sec. 4.1: masked
+// execution instead of divergent branches).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pino {
+
+constexpr double kTwoPiOver3 = 2.0943951023931954923;
+constexpr double kInf = __builtin_huge_val();
+
+// ---------------------------------------------------------------------------
+// Eigenvalues.  With q = tr(H)/3, p = sqrt(tr((H - qI)^2)/6) and
+// r = det((H - qI)/p)/2, the eigenvalues are q + 2p cos(phi + 2 pi k/3),
+// phi = acos(r)/3, k = 0 giving the largest and k = 1 the smallest.
+// ---------------------------------------------------------------------------
+struct Hess64 {
+    double xx, yy, zz, xy, xz, yz;
+};
+
+// cos(phi) and the scale of the trigonometric solution; p == 0 (a multiple
+// of the identity) gives q for every eigenvalue.  r is returned so callers
+// can detect a nearly repeated eigenvalue (r -> -1: l1 ~ l2, r -> +1: l2 ~ l3)
+// where the closed form loses about half the digits of the pair.
+__host__ __device__ __forceinline__ void eig_trig(const Hess64& h, double& q, double& p2x, double& phi, double& r)
+{
+    q = (h.xx + h.yy + h.zz) * (1.0 / 3.0);
+    const double dx = h.xx - q, dy = h.yy - q, dz = h.zz - q;
+    const double off = h.xy * h.xy + h.xz * h.xz + h.yz * h.yz;
+    const double ss = dx * dx + dy * dy + dz * dz + 2.0 * off;
+    const double p = sqrt(ss * (1.0 / 6.0));
+    const double det = dx * (dy * dz - h.yz * h.yz) - h.xy * (h.xy * dz - h.yz * h.xz) + h.xz * (h.xy * h.yz - dy * h.xz);
+    const double ip = p > 0.0 ? 1.0 / p : 0.0;
+    r = 0.5 * det * (ip * ip * ip);
+    r = fmin(fmax(r, -1.0), 1.0);
+    phi = acos(r) * (1.0 / 3.0);
+    p2x = 2.0 * p;
+}
+
+// Threshold on 1 -+ r below which the repeated pair is recomputed by
+// deflation.  Above it the closed form keeps ~1e-12 relative accuracy.
+constexpr double kNearRepeated = 1e-6;
+
+// The two eigenvalues orthogonal to a well-separated eigenvalue mu: the
+// eigenvector v of mu is the largest cross product of two rows of H - mu I;
+// H projected on an orthonormal basis (u, w) of the plane normal to v is a
+// 2x2 block whose eigenvalues m +- sqrt(((b11 - b22)/2)^2 + b12^2) have no
+// cancellation however close they are.
+__host__ __device__ __forceinline__ void deflate_pair(const Hess64& h, double mu, double& hi, double& lo)
+{
+    const double r0x = h.xx - mu, r0y = h.xy, r0z = h.xz;
+    const double r1x = h.xy, r1y = h.yy - mu, r1z = h.yz;
+    const double r2x = h.xz, r2y = h.yz, r2z = h.zz - mu;
+    double ax = r0y * r1z - r0z * r1y, ay = r0z * r1x - r0x * r1z, az = r0x * r1y - r0y * r1x;
+    const double bx = r0y * r2z - r0z * r2y, by = r0z * r2x - r0x * r2z, bz = r0x * r2y - r0y * r2x;
+    const double cx = r1y * r2z - r1z * r2y, cy = r1z * r2x - r1x * r2z, cz = r1x * r2y - r1y * r2x;
+    double na = ax * ax + ay * ay + az * az;
+    const double nb = bx * bx + by * by + bz * bz;
+    const double nc = cx * cx + cy * cy + cz * cz;
+    if (nb > na) {
+        ax = bx; ay = by; az = bz; na = nb;
+    }
+    if (nc > na) {
+        ax = cx; ay = cy; az = cz; na = nc;
+    }
+    if (!(na > 0.0)) {
+        hi = lo = mu;
+        return;
+    }
+    const double iv = 1.0 / sqrt(na);
+    const double vx = ax * iv, vy = ay * iv, vz = az * iv;
+    // u: v crossed with the coordinate axis least aligned with v
+    double ux, uy, uz;
+    if (fabs(vx) <= fabs(vy) && fabs(vx) <= fabs(vz)) {
+        ux = 0.0; uy = vz; uz = -vy;
+    } else if (fabs(vy) <= fabs(vz)) {
+        ux = -vz; uy = 0.0; uz = vx;
+    } else {
+        ux = vy; uy = -vx; uz = 0.0;
+    }
+    const double iu = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+    ux *= iu; uy *= iu; uz *= iu;
+    const double wx = vy * uz - vz * uy, wy = vz * ux - vx * uz, wz = vx * uy - vy * ux;
+    const double hux = h.xx * ux + h.xy * uy + h.xz * uz;
+    const double huy = h.xy * ux + h.yy * uy + h.yz * uz;
+    const double huz = h.xz * ux + h.yz * uy + h.zz * uz;
+    const double hwx = h.xx * wx + h.xy * wy + h.xz * wz;
+    const double hwy = h.xy * wx + h.yy * wy + h.yz * wz;
+    const double hwz = h.xz * wx + h.yz * wy + h.zz * wz;
+    const double b11 = ux * hux + uy * huy + uz * huz;
+    const double b22 = wx * hwx + wy * hwy + wz * hwz;
+    const double b12 = ux * hwx + uy * hwy + uz * hwz;
+    const double m = 0.5 * (b11 + b22);
+    const double d = sqrt(0.25 * (b11 - b22) * (b11 - b22) + b12 * b12);
+    hi = m + d;
+    lo = m - d;
+}
+
+// Largest eigenvalue l1 together with s = l2 + l3 and pp = l2 * l3, the only
+// combinations the axis-1 collapse condition needs.  s = tr - l1 and
+// pp = mu2 - l1 s, mu2 the sum of the principal 2x2 minors.
+__host__ __device__ __forceinline__ void eig_top(const Hess64& h, double& l1, double& s, double& pp)
+{
+    double q, p2x, phi, r;
+    eig_trig(h, q, p2x, phi, r);
+    l1 = q + p2x * cos(phi);
+    if (1.0 + r < kNearRepeated) {
+        // l1 ~ l2: l3 is well separated, the pair comes from the 2x2 block
+        double lo;
+        const double l3 = q + p2x * cos(phi + kTwoPiOver3);
+        deflate_pair(h, l3, l1, lo);
+    }
+    const double tr = h.xx + h.yy + h.zz;
+    const double mu2 = h.xx * h.yy + h.xx * h.zz + h.yy * h.zz - h.xy * h.xy - h.xz * h.xz - h.yz * h.yz;
+    s = tr - l1;
+    pp = mu2 - l1 * s;
+}
+
+// All three eigenvalues, descending.
+__host__ __device__ __forceinline__ void eig_all(const Hess64& h, double& l1, double& l2, double& l3)
+{
+    double q, p2x, phi, r;
+    eig_trig(h, q, p2x, phi, r);
+    l1 = q + p2x * cos(phi);
+    l3 = q + p2x * cos(phi + kTwoPiOver3);
+    l2 = (h.xx + h.yy + h.zz) - l1 - l3;
+    if (1.0 + r < kNearRepeated)
+        deflate_pair(h, l3, l1, l2);
+    else if (1.0 - r < kNearRepeated)
+        deflate_pair(h, l1, l2, l3);
+    l2 = fmin(fmax(l2, l3), l1);
+}
+
+// ---------------------------------------------------------------------------
+// Classic collapse.  Along the axis with eigenvalue l1 the LPT reading gives
+//   R1/q1 = g(D) = 1 - l1 D + beta D^2 + gamma D^3,
+//   beta  = -(3/14) l1 s,
+//   gamma = -l1 [ (l1 s + 2 pp)/56 + 17 s^2/168 - pp/9 ],
+// with s = l2 + l3 and pp = l2 l3.  D_c is its smallest positive root (the
+// first crossing of the axis).  No root exists for l1 <= 0.  In u = l1 D:
+//   g(u) = 1 - u + b u^2 + c u^3,  b = beta/l1^2,  c = gamma/l1^3.
+// ---------------------------------------------------------------------------
+struct CubicU {
+    double b, c;
+};
+
+__host__ __device__ __forceinline__ double g_u(const CubicU& k, double u)
+{
+    return 1.0 + u * (-1.0 + u * (k.b + k.c * u));
+}
+
+__host__ __device__ __forceinline__ CubicU lpt_cubic(double l1, double s, double pp, double il1)
+{
+    const double sg = s * il1;
+    const double pi = pp * (il1 * il1);
+    CubicU k;
+    k.b = (-3.0 / 14.0) * sg;
+    k.c = -(sg * (1.0 / 56.0) + pi * (2.0 / 56.0) + (17.0 / 168.0) * (sg * sg) - pi * (1.0 / 9.0));
+    return k;
+}
+
+// Bracket [lo, hi] on which g is monotone decreasing with g(lo) > 0 >= g(hi):
+//  * the first positive critical point u1 = 1/(b + sqrt(b^2 + 3c)) is a local
+//    minimum; if g(u1) <= 0 the root lies in (0, u1];
+//  * if g(u1) > 0 and c >= 0, g rises for ever after u1: no root;
+//  * if g(u1) > 0 and c < 0 the root lies past the local maximum
+//    u2 = 1/(b - sqrt(b^2 + 3c));
+//  * with no positive critical point g decreases on (0, inf).
+// For c < 0, g(u) < 0 at u = max(1, 2 max(b, 0) / (-c)); for c = 0 without a
+// critical point, b <= 0 and g(1) = b <= 0.
+struct Bracket {
+    double lo, hi;
+    bool root;
+};
+
+__host__ __device__ __forceinline__ Bracket lpt_bracket(const CubicU& k)
+{
+    const double disc = k.b * k.b + 3.0 * k.c;
+    const double sq = sqrt(fmax(disc, 0.0));
+    const double den1 = k.b + sq;
+    const bool has1 = disc >= 0.0 && den1 > 0.0;
+    const double u1 = has1 ? 1.0 / den1 : 0.0;
+    const bool before_min = has1 && g_u(k, u1) <= 0.0;
+    const double far = k.c < 0.0 ? fmax(1.0, 2.0 * fmax(k.b, 0.0) / (-k.c)) : 1.0;
+    const bool past_max = has1 && !before_min && k.c < 0.0;
+    Bracket br;
+    br.root = !has1 || before_min || past_max;
+    br.lo = past_max ? 1.0 / (k.b - sq) : 0.0;
+    br.hi = before_min ? u1 : far;
+    return br;
+}
+
+// Halley iteration kept inside the bracket (bisection when a step leaves it);
+// stops when the step is below a few ulps.  Starts from the second-order LPT
+// root 2 / (1 + sqrt(1 - 4b)) when it lies in the bracket.
+__host__ __device__ __forceinline__ double lpt_solve_u(const CubicU& k, Bracket br)
+{
+    const double disc2 = 1.0 - 4.0 * k.b;
+    double u = disc2 >= 0.0 ? 2.0 / (1.0 + sqrt(disc2)) : 1.0;
+    if (!(u > br.lo && u < br.hi))
+        u = 0.5 * (br.lo + br.hi);
+    double lo = br.lo, hi = br.hi;
+    for (int it = 0; it < 80; ++it) {
+        const double g = g_u(k, u);
+        if (g == 0.0)
+            break;  // landed on the root
+        const double g1 = -1.0 + u * (2.0 * k.b + 3.0 * k.c * u);
+        const double g2 = 2.0 * k.b + 6.0 * k.c * u;
+        if (g > 0.0)
+            lo = u;
+        else
+            hi = u;
+        double un = u - (2.0 * g * g1) / (2.0 * g1 * g1 - g * g2);
+        if (!(un > lo && un < hi))
+            un = 0.5 * (lo + hi);
+        const double step = fabs(un - u);
+        u = un;
+        if (step <= 4e-16 * u)
+            break;
+    }
+    return u;
+}
+
+// F = 1/D_c (0 without collapse) and D_c itself (inf without collapse).
+__host__ __device__ __forceinline__ double classic_F(double l1, double s, double pp, double& Dc)
+{
+    Dc = kInf;
+    if (!(l1 > 0.0))
+        return 0.0;
+    const double il1 = 1.0 / l1;
+    const CubicU k = lpt_cubic(l1, s, pp, il1);
+    const Bracket br = lpt_bracket(k);
+    if (!br.root)
+        return 0.0;
+    const double u = lpt_solve_u(k, br);
+    Dc = u * il1;
+    return 1.0 / Dc;
+}
+
+// ---------------------------------------------------------------------------
+// Natural cubic spline evaluation on knots x[0..n-1] (LDS or global), values
+// y and second derivatives m.  Interval i with x_i <= q < x_{i+1}; q at or past
+// the last knot uses the last interval.  t = (q - x_i)/h:
+//   S = (1-t) y_i + t y_{i+1} + h^2/6 [((1-t)^3 - (1-t)) m_i + (t^3 - t) m_{i+1}]
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int locate(const double* x, int n, double q)
+{
+    int lo = 0;
+    int step = 1;
+    while (step * 2 <= n - 2)
+        step *= 2;
+    for (; step > 0; step >>= 1) {
+        const int j = lo + step;
+        if (j <= n - 2 && x[j] <= q)
+            lo = j;
+    }
+    return lo;
+}
+
+__host__ __device__ __forceinline__ double spline_piece(double x0, double x1, double y0, double y1, double m0, double m1,
+                                               double q)
+{
+    const double h = x1 - x0;
+    const double t = (q - x0) / h;
+    const double w = 1.0 - t;
+    return w * y0 + t * y1 + (h * h * (1.0 / 6.0)) * ((w * w * w - w) * m0 + (t * t * t - t) * m1);
+}
+
+// a(D) from the growth knots staged as [D | a | M] (n each).
+__host__ __device__ __forceinline__ double growth_invert(const double* g, int n, double Dc)
+{
+    const double* D = g;
+    const double* a = g + n;
+    const double* M = g + 2 * n;
+    if (!(Dc <= D[n - 1]))
+        return kInf;
+    if (Dc < D[0])
+        return a[0];
+    const int i = locate(D, n, Dc);
+    return spline_piece(D[i], D[i + 1], a[i], a[i + 1], M[i], M[i + 1], Dc);
+}
+
+}  // namespace pino

@@ -1,0 +1,219 @@
+// FP64 kernels of the collapse-time path: spline construction (Classic growth
+// tables and the per-radius delta splines of the Tabulated method) and the
+// per-radius collapse + max-update kernels.
+#pragma once
+
+#include "device_collapse.h"
+
+namespace pino {
+
+// ---------------------------------------------------------------------------
+// Spline construction (Sec. 4.2: the interpolation tables are built on the
+// device so the per-radius Tabulated update never goes through the host).
+// Natural cubic spline second derivatives for `rows` value rows over shared
+// knots x[0..n-1]:
+//   h_{i-1} M_{i-1} + 2 (h_{i-1} + h_i) M_i + h_i M_{i+1}
+//     = 6 [(y_{i+1} - y_i)/h_i - (y_i - y_{i-1})/h_{i-1}],  M_0 = M_{n-1} = 0,
+// one Thomas solve per thread.  Row r reads y[r*ldy + k*sy] and writes
+// m[r*ldm + k*sm]; `tmp` holds n doubles per row (the eliminated
+// super-diagonal).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_spline_build(const double* __restrict__ x, int n, const double* __restrict__ y,
+                                                    int64_t ldy, int sy, double* __restrict__ m, int64_t ldm, int sm,
+                                                    double* __restrict__ tmp, int rows)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows)
+        return;
+    const double* yr = y + r * ldy;
+    double* mr = m + r * ldm;
+    double* cp = tmp + (int64_t)r * n;
+    mr[0] = 0.0;
+    mr[(int64_t)(n - 1) * sm] = 0.0;
+    if (n < 3)
+        return;
+    // forward sweep over unknowns i = 1..n-2 (d' kept in m, c' in tmp)
+    double cprev = 0.0, dprev = 0.0;
+    double hl = x[1] - x[0];
+    double yl = yr[0], yc = yr[sy];
+    for (int i = 1; i <= n - 2; ++i) {
+        const double hr = x[i + 1] - x[i];
+        const double yn = yr[(int64_t)(i + 1) * sy];
+        const double rhs = 6.0 * ((yn - yc) / hr - (yc - yl) / hl);
+        const double den = 2.0 * (hl + hr) - hl * cprev;
+        const double c = hr / den;
+        const double d = (rhs - hl * dprev) / den;
+        cp[i] = c;
+        mr[(int64_t)i * sm] = d;
+        cprev = c;
+        dprev = d;
+        hl = hr;
+        yl = yc;
+        yc = yn;
+    }
+    // back substitution
+    double mnext = 0.0;
+    for (int i = n - 2; i >= 1; --i) {
+        const double v = mr[(int64_t)i * sm] - cp[i] * mnext;
+        mr[(int64_t)i * sm] = v;
+        mnext = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-radius Classic FP64 kernel.  One particle per lane per step of a
+// grid-stride loop; the growth knots [D | a | M] of the item's cosmology are
+// staged once per workgroup in LDS.  Hessian loads are coalesced SoA reads
+// that bypass the caches' retention (each value is read once).
+// ---------------------------------------------------------------------------
+struct ItemArgs {
+    const double* h[6];
+    int64_t n;
+    const double* growth;  // [D | a | M], nk each
+    int nk;
+    int32_t radius;
+    uint32_t reset;
+    double* Fmax;
+    int32_t* Rmax;
+    double* acoll;
+};
+
+__device__ __forceinline__ void stage(double* dst, const double* __restrict__ src, int count)
+{
+    for (int k = threadIdx.x; k < count; k += blockDim.x)
+        dst[k] = src[k];
+}
+
+__device__ __forceinline__ Hess64 load_h64(const ItemArgs& a, int64_t i)
+{
+    Hess64 h;
+    h.xx = __builtin_nontemporal_load(a.h[0] + i);
+    h.yy = __builtin_nontemporal_load(a.h[1] + i);
+    h.zz = __builtin_nontemporal_load(a.h[2] + i);
+    h.xy = __builtin_nontemporal_load(a.h[3] + i);
+    h.xz = __builtin_nontemporal_load(a.h[4] + i);
+    h.yz = __builtin_nontemporal_load(a.h[5] + i);
+    return h;
+}
+
+// max update with the strict '>' rule; RESET writes every element
+__device__ __forceinline__ void update_max(const ItemArgs& a, const double* g, int64_t i, double F, double Dc)
+{
+    const double fm = a.reset ? 0.0 : a.Fmax[i];
+    const bool upd = F > fm;
+    if (upd || a.reset) {
+        a.Fmax[i] = upd ? F : 0.0;
+        a.Rmax[i] = upd ? a.radius : -1;
+        if (a.acoll)
+            a.acoll[i] = upd ? growth_invert(g, a.nk, Dc) : kInf;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_classic_f64(ItemArgs a)
+{
+    extern __shared__ double lds[];
+    stage(lds, a.growth, 3 * a.nk);
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const Hess64 h = load_h64(a, i);
+        double l1, s, pp;
+        eig_top(h, l1, s, pp);
+        double Dc;
+        const double F = classic_F(l1, s, pp, Dc);
+        update_max(a, lds, i, F, Dc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tabulated FP64.  The library keeps, per radius, an interleaved copy of the
+// table, tab[((ix*ny + iy)*nd + id)*2 + {0,1}] = (F, M), so the two knots of a
+// corner spline are 32 contiguous bytes.  Knots (scaled by sigma_R) live in
+// LDS after the growth knots.
+// ---------------------------------------------------------------------------
+struct TabArgs {
+    const double* xk;  // dimensionless knots, nx, ny, nd
+    const double* yk;
+    const double* dk;
+    int nx, ny, nd;
+    double scale;      // sigma_R
+    const double* tab; // interleaved (F, M)
+};
+
+__device__ __forceinline__ double corner(const double* __restrict__ tab, int64_t row, int nd, int j, double d0,
+                                         double d1, double q)
+{
+    const double2* p = reinterpret_cast<const double2*>(tab + (row * nd + j) * 2);
+    const double2 lo = p[0];
+    const double2 hi = p[1];
+    return spline_piece(d0, d1, lo.x, hi.x, lo.y, hi.y, q);
+}
+
+__device__ __forceinline__ double table_F(const TabArgs& t, const double* xs, const double* ys, const double* ds,
+                                          double l1, double l2, double l3)
+{
+    const double delta = l1 + l2 + l3;
+    const double x = l1 - l2;
+    const double y = l2 - l3;
+    const int ix = locate(xs, t.nx, x);
+    const int iy = locate(ys, t.ny, y);
+    const double tt = fmin(fmax((x - xs[ix]) / (xs[ix + 1] - xs[ix]), 0.0), 1.0);
+    const double uu = fmin(fmax((y - ys[iy]) / (ys[iy + 1] - ys[iy]), 0.0), 1.0);
+    const double dq = fmin(fmax(delta, ds[0]), ds[t.nd - 1]);
+    const int j = locate(ds, t.nd, dq);
+    const double d0 = ds[j], d1 = ds[j + 1];
+    const int64_t r00 = (int64_t)ix * t.ny + iy;
+    const double v00 = corner(t.tab, r00, t.nd, j, d0, d1, dq);
+    const double v01 = corner(t.tab, r00 + 1, t.nd, j, d0, d1, dq);
+    const double v10 = corner(t.tab, r00 + t.ny, t.nd, j, d0, d1, dq);
+    const double v11 = corner(t.tab, r00 + t.ny + 1, t.nd, j, d0, d1, dq);
+    const double f = (1.0 - tt) * (1.0 - uu) * v00 + tt * (1.0 - uu) * v10 + (1.0 - tt) * uu * v01 + tt * uu * v11;
+    return f > 0.0 ? f : 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
+{
+    extern __shared__ double lds[];
+    double* g = lds;
+    double* xs = lds + 3 * a.nk;
+    double* ys = xs + t.nx;
+    double* ds = ys + t.ny;
+    stage(g, a.growth, 3 * a.nk);
+    for (int k = threadIdx.x; k < t.nx; k += blockDim.x)
+        xs[k] = t.xk[k] * t.scale;
+    for (int k = threadIdx.x; k < t.ny; k += blockDim.x)
+        ys[k] = t.yk[k] * t.scale;
+    for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
+        ds[k] = t.dk[k] * t.scale;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const Hess64 h = load_h64(a, i);
+        double l1, l2, l3;
+        eig_all(h, l1, l2, l3);
+        const bool finite = isfinite(l1) && isfinite(l2) && isfinite(l3);
+        const double F = finite ? table_F(t, xs, ys, ds, l1, l2, l3) : 0.0;
+        const double Dc = 1.0 / F;
+        update_max(a, g, i, F, Dc);
+    }
+}
+
+// dst[k] = src[k] * scale
+__global__ void __launch_bounds__(256) k_scale_copy(const double* __restrict__ src, int n, double scale,
+                                                   double* __restrict__ dst)
+{
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        dst[k] = src[k] * scale;
+}
+
+// copy the caller's F values into the even slots of the interleaved table
+// (the spline build writes M into the odd slots)
+__global__ void __launch_bounds__(256) k_table_copy_F(const double* __restrict__ F, double* __restrict__ tab,
+                                                     int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        tab[2 * i] = F[i];
+}
+
+}  // namespace pino

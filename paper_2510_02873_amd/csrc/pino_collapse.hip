@@ -1,0 +1,403 @@
+// Host side of the C ABI declared in include/pino_collapse.h: argument
+// validation, context lifetime, device tables and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pino_collapse.h"
+#include "ctx.h"
+#include "kernels_fp64.h"
+#include "launch_ext.h"
+
+using namespace pino;
+
+namespace {
+
+thread_local std::string g_init_error = "no error";
+
+constexpr int kMaxGrowthKnots = 2048;
+constexpr int64_t kMaxTableCells = int64_t(1) << 24;
+
+bool strictly_increasing(const double* v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i]))
+            return false;
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(v[i + 1] > v[i]))
+            return false;
+    return true;
+}
+
+// Pure host checks of a configuration; no HIP call.
+bool validate_config(const pino_config* cfg, std::string& why)
+{
+    if (!cfg) {
+        why = "config is NULL";
+        return false;
+    }
+    if (cfg->abi_version != PINO_ABI_VERSION) {
+        why = "abi_version " + std::to_string(cfg->abi_version) + " != " + std::to_string(PINO_ABI_VERSION);
+        return false;
+    }
+    if (cfg->method != PINO_CLASSIC && cfg->method != PINO_TABULATED) {
+        why = "unknown method";
+        return false;
+    }
+    if (cfg->precision != PINO_FP64 && cfg->precision != PINO_MIXED && cfg->precision != PINO_SURROGATE) {
+        why = "unknown precision";
+        return false;
+    }
+    if (cfg->device < 0) {
+        why = "device < 0";
+        return false;
+    }
+    if (cfg->n_cosmo < 1 || !cfg->growth) {
+        why = "need at least one growth table";
+        return false;
+    }
+    for (int c = 0; c < cfg->n_cosmo; ++c) {
+        const pino_growth& g = cfg->growth[c];
+        if (g.n < 4 || g.n > kMaxGrowthKnots || !g.a || !g.D) {
+            why = "growth table " + std::to_string(c) + ": need 4 <= n <= 2048 and non-NULL a, D";
+            return false;
+        }
+        if (!strictly_increasing(g.a, g.n) || !strictly_increasing(g.D, g.n)) {
+            why = "growth table " + std::to_string(c) + ": a and D must be finite and strictly increasing";
+            return false;
+        }
+    }
+    if (cfg->method == PINO_TABULATED) {
+        const pino_table_knots* t = cfg->table;
+        if (!t || !t->x || !t->y || !t->delta || t->nx < 2 || t->ny < 2 || t->nd < 4) {
+            why = "tabulated method needs table knots with nx, ny >= 2 and nd >= 4";
+            return false;
+        }
+        if ((int64_t)t->nx * t->ny * t->nd > kMaxTableCells) {
+            why = "table larger than 2^24 cells";
+            return false;
+        }
+        if (!strictly_increasing(t->x, t->nx) || !strictly_increasing(t->y, t->ny) ||
+            !strictly_increasing(t->delta, t->nd)) {
+            why = "table knots must be finite and strictly increasing";
+            return false;
+        }
+        if (cfg->precision == PINO_SURROGATE) {
+            why = "the surrogate replaces the Classic solve only";
+            return false;
+        }
+    }
+    if (cfg->precision == PINO_SURROGATE) {
+        std::string mwhy;
+        if (!mlp_blob_valid(cfg->mlp, cfg->mlp_bytes, mwhy)) {
+            why = "surrogate weights: " + mwhy;
+            return false;
+        }
+    }
+    return true;
+}
+
+bool validate_items(const pino_ctx* ctx, const pino_item* items, int32_t n_items, std::string& why)
+{
+    if (n_items < 0) {
+        why = "n_items < 0";
+        return false;
+    }
+    if (n_items > 0 && !items) {
+        why = "items is NULL";
+        return false;
+    }
+    for (int32_t k = 0; k < n_items; ++k) {
+        const pino_item& it = items[k];
+        const std::string at = "item " + std::to_string(k) + ": ";
+        if (it.n < 0) {
+            why = at + "n < 0";
+            return false;
+        }
+        if (it.cosmo < 0 || it.cosmo >= ctx->n_cosmo) {
+            why = at + "cosmo index out of range";
+            return false;
+        }
+        if (it.radius_index < 0) {
+            why = at + "radius_index < 0";
+            return false;
+        }
+        if (it.n == 0)
+            continue;
+        for (int c = 0; c < 6; ++c)
+            if (!it.h[c]) {
+                why = at + "Hessian component pointer is NULL";
+                return false;
+            }
+        if (!it.Fmax || !it.Rmax) {
+            why = at + "Fmax and Rmax must be non-NULL";
+            return false;
+        }
+        if ((ctx->method == PINO_TABULATED || ctx->precision == PINO_SURROGATE) &&
+            !(std::isfinite(it.sigma_R) && it.sigma_R > 0.0)) {
+            why = at + "sigma_R must be finite and > 0";
+            return false;
+        }
+        if (ctx->method == PINO_TABULATED && !it.table_F) {
+            why = at + "table_F is NULL";
+            return false;
+        }
+    }
+    return true;
+}
+
+pino_status hip_fail(pino_ctx* ctx, hipError_t e, const char* what)
+{
+    ctx->broken = true;
+    ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    return PINO_ERR_HIP;
+}
+
+#define PINO_HIP(ctx, call)                          \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess)                        \
+            return hip_fail((ctx), e_, #call);       \
+    } while (0)
+
+int grid_for(const pino_ctx* ctx, int64_t n, int block)
+{
+    const int64_t need = (n + block - 1) / block;
+    const int64_t cap = (int64_t)ctx->cu_count * ctx->blocks_per_cu;
+    return (int)std::max<int64_t>(1, std::min(need, cap));
+}
+
+void free_all(pino_ctx* c)
+{
+    if (!c)
+        return;
+    void* ptrs[] = {c->d_growth, c->d_tknots, c->d_tab, c->d_dscaled, c->d_tmp, c->d_mlp, c->d_counters};
+    for (void* p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    c->d_growth = c->d_tknots = c->d_tab = c->d_dscaled = c->d_tmp = nullptr;
+    c->d_mlp = nullptr;
+    c->d_counters = nullptr;
+}
+
+pino_status init_impl(const pino_config* cfg, pino_ctx* c)
+{
+    PINO_HIP(c, hipSetDevice(cfg->device));
+    int cus = 0;
+    PINO_HIP(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device));
+    c->cu_count = cus > 0 ? cus : 1;
+    if (const char* env = std::getenv("PINO_BLOCKS_PER_CU")) {
+        const int v = std::atoi(env);
+        if (v > 0 && v <= 64)
+            c->blocks_per_cu = v;
+    }
+
+    // growth tables: [D | a | M] per cosmology, stride 3 * nk_max
+    int nk_max = 0;
+    for (int k = 0; k < cfg->n_cosmo; ++k)
+        nk_max = std::max(nk_max, (int)cfg->growth[k].n);
+    c->nk_max = nk_max;
+    c->nk.resize(cfg->n_cosmo);
+    std::vector<double> host((size_t)cfg->n_cosmo * 3 * nk_max, 0.0);
+    for (int k = 0; k < cfg->n_cosmo; ++k) {
+        const pino_growth& g = cfg->growth[k];
+        c->nk[k] = g.n;
+        double* dst = host.data() + (size_t)k * 3 * nk_max;
+        std::memcpy(dst, g.D, sizeof(double) * g.n);
+        std::memcpy(dst + g.n, g.a, sizeof(double) * g.n);
+    }
+    PINO_HIP(c, hipMalloc((void**)&c->d_growth, host.size() * sizeof(double)));
+    PINO_HIP(c, hipMemcpy(c->d_growth, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+
+    int64_t tmp_doubles = (int64_t)cfg->n_cosmo * nk_max;
+    if (cfg->method == PINO_TABULATED) {
+        const pino_table_knots* t = cfg->table;
+        c->nx = t->nx;
+        c->ny = t->ny;
+        c->nd = t->nd;
+        std::vector<double> kn;
+        kn.insert(kn.end(), t->x, t->x + t->nx);
+        kn.insert(kn.end(), t->y, t->y + t->ny);
+        kn.insert(kn.end(), t->delta, t->delta + t->nd);
+        PINO_HIP(c, hipMalloc((void**)&c->d_tknots, kn.size() * sizeof(double)));
+        PINO_HIP(c, hipMemcpy(c->d_tknots, kn.data(), kn.size() * sizeof(double), hipMemcpyHostToDevice));
+        const int64_t cells = (int64_t)t->nx * t->ny * t->nd;
+        PINO_HIP(c, hipMalloc((void**)&c->d_tab, 2 * cells * sizeof(double)));
+        PINO_HIP(c, hipMalloc((void**)&c->d_dscaled, t->nd * sizeof(double)));
+        tmp_doubles = std::max(tmp_doubles, cells);
+    }
+    PINO_HIP(c, hipMalloc((void**)&c->d_tmp, tmp_doubles * sizeof(double)));
+
+    // natural-spline second derivatives of a(D), built on the device
+    for (int k = 0; k < cfg->n_cosmo; ++k) {
+        double* g = c->d_growth + (size_t)k * 3 * nk_max;
+        const int n = c->nk[k];
+        hipLaunchKernelGGL(k_spline_build, dim3(1), dim3(64), 0, 0, g, n, g + n, (int64_t)0, 1, g + 2 * n,
+                           (int64_t)0, 1, c->d_tmp + (size_t)k * nk_max, 1);
+        PINO_HIP(c, hipGetLastError());
+    }
+
+    if (cfg->precision == PINO_SURROGATE) {
+        c->certify_rtol = cfg->certify_rtol > 0.0 ? cfg->certify_rtol : 1e-7;
+        const pino_status st = mlp_upload(c, cfg->mlp, cfg->mlp_bytes);
+        if (st != PINO_OK)
+            return st;
+    }
+    PINO_HIP(c, hipDeviceSynchronize());
+    return PINO_OK;
+}
+
+pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStream_t st)
+{
+    if (it.n == 0)
+        return PINO_OK;
+    ItemArgs a;
+    for (int k = 0; k < 6; ++k)
+        a.h[k] = static_cast<const double*>(it.h[k]);
+    a.n = it.n;
+    a.nk = c->nk[it.cosmo];
+    a.growth = c->d_growth + (size_t)it.cosmo * 3 * c->nk_max;
+    a.radius = it.radius_index;
+    a.reset = (flags & PINO_EVAL_RESET) ? 1u : 0u;
+    a.Fmax = it.Fmax;
+    a.Rmax = it.Rmax;
+    a.acoll = it.a_coll;
+    const int block = 256;
+    const int grid = grid_for(c, it.n, block);
+    size_t lds = 3 * (size_t)a.nk * sizeof(double);
+
+    if (c->method == PINO_TABULATED) {
+        // per-radius table: copy F into the interleaved table and rebuild the
+        // delta splines on the device
+        const int64_t rows = (int64_t)c->nx * c->ny;
+        const int64_t cells = rows * c->nd;
+        hipLaunchKernelGGL(k_table_copy_F, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, it.table_F,
+                           c->d_tab, cells);
+        PINO_HIP(c, hipGetLastError());
+        const double* dks = c->d_tknots + c->nx + c->ny;
+        hipLaunchKernelGGL(k_scale_copy, dim3(1), dim3(256), 0, st, dks, c->nd, it.sigma_R, c->d_dscaled);
+        PINO_HIP(c, hipGetLastError());
+        hipLaunchKernelGGL(k_spline_build, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, c->d_dscaled,
+                           c->nd, it.table_F, (int64_t)c->nd, 1, c->d_tab + 1, (int64_t)2 * c->nd, 2,
+                           c->d_tmp, (int)rows);
+        PINO_HIP(c, hipGetLastError());
+    }
+
+    if (c->precision == PINO_FP64) {
+        if (c->method == PINO_CLASSIC) {
+            hipLaunchKernelGGL(k_classic_f64, dim3(grid), dim3(block), lds, st, a);
+        } else {
+            TabArgs t;
+            t.xk = c->d_tknots;
+            t.yk = c->d_tknots + c->nx;
+            t.dk = c->d_tknots + c->nx + c->ny;
+            t.nx = c->nx;
+            t.ny = c->ny;
+            t.nd = c->nd;
+            t.scale = it.sigma_R;
+            t.tab = c->d_tab;
+            lds += (size_t)(c->nx + c->ny + c->nd) * sizeof(double);
+            hipLaunchKernelGGL(k_tabulated_f64, dim3(grid), dim3(block), lds, st, a, t);
+        }
+        PINO_HIP(c, hipGetLastError());
+        return PINO_OK;
+    }
+    if (c->precision == PINO_MIXED)
+        return launch_mixed(c, it, a, flags, st, grid, block);
+    return launch_surrogate(c, it, a, flags, st, grid, block);
+}
+
+}  // namespace
+
+extern "C" {
+
+pino_status pino_collapse_init(const pino_config* cfg, pino_ctx** out)
+{
+    if (!out) {
+        g_init_error = "out is NULL";
+        return PINO_ERR_ARG;
+    }
+    *out = nullptr;
+    std::string why;
+    if (!validate_config(cfg, why)) {
+        g_init_error = why;
+        return PINO_ERR_ARG;
+    }
+    pino_ctx* c = new (std::nothrow) pino_ctx();
+    if (!c) {
+        g_init_error = "host allocation failed";
+        return PINO_ERR_ALLOC;
+    }
+    c->device = cfg->device;
+    c->method = cfg->method;
+    c->precision = cfg->precision;
+    c->n_cosmo = cfg->n_cosmo;
+    const pino_status st = init_impl(cfg, c);
+    if (st != PINO_OK) {
+        g_init_error = c->err;
+        free_all(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return PINO_OK;
+}
+
+pino_status pino_collapse_eval(pino_ctx* ctx, const pino_item* items, int32_t n_items, uint32_t flags,
+                               void* hip_stream)
+{
+    if (!ctx) {
+        g_init_error = "ctx is NULL";
+        return PINO_ERR_ARG;
+    }
+    if (ctx->broken) {
+        return PINO_ERR_STATE;
+    }
+    if (flags & ~(PINO_EVAL_RESET | PINO_EVAL_SYNC)) {
+        ctx->err = "unknown flag bits";
+        return PINO_ERR_ARG;
+    }
+    std::string why;
+    if (!validate_items(ctx, items, n_items, why)) {
+        ctx->err = why;
+        return PINO_ERR_ARG;
+    }
+    PINO_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    for (int32_t k = 0; k < n_items; ++k) {
+        const pino_status s = launch_item(ctx, items[k], flags, st);
+        if (s != PINO_OK)
+            return s;
+    }
+    if (flags & PINO_EVAL_SYNC)
+        PINO_HIP(ctx, hipStreamSynchronize(st));
+    return PINO_OK;
+}
+
+pino_status pino_collapse_free(pino_ctx* ctx)
+{
+    if (!ctx)
+        return PINO_OK;
+    pino_status st = PINO_OK;
+    if (hipSetDevice(ctx->device) == hipSuccess) {
+        if (hipDeviceSynchronize() != hipSuccess)
+            st = PINO_ERR_HIP;
+    }
+    free_all(ctx);
+    delete ctx;
+    return st;
+}
+
+const char* pino_collapse_last_error(const pino_ctx* ctx)
+{
+    if (!ctx)
+        return g_init_error.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

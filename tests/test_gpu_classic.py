@@ -1,0 +1,162 @@
+"""GPU parity of the plain FP64 Classic path against the oracle (through the
+C ABI).  Gate: D_c = 1/Fmax and a_coll within 1e-9 relative, radius index
+exact except at documented near-ties, |dF| <= 1e-15 where F < 1e-6."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests._helpers import REL_TOL, c1_inputs, compare, near_tie_mask, run_gpu_radii
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2510_02873_amd as P
+    return P
+
+
+def _stack_cpu(h):
+    return h.cpu().numpy() if torch.is_tensor(h) else np.asarray(h)
+
+
+def test_c1_full(pkg, orc):
+    cfg, slabs, a, D = c1_inputs()
+    print(f"C1: n={slabs[0].shape[1]} radii={len(slabs)}", flush=True)
+    ref = orc.collapse([_stack_cpu(h) for h in slabs], orc.Growth(a, D))
+    ties = near_tie_mask([orc.points(_stack_cpu(h))[1] for h in slabs])
+    with pkg.Collapse([(a, D)]) as col:
+        got = run_gpu_radii(col, [h.cuda() for h in slabs])
+    st = compare(ref, got, tie_mask=ties, label="C1")
+    print("C1 stats", st, "near ties", int(ties.sum()), flush=True)
+
+
+def _single(pkg, orc, h6, a, D, acoll=True):
+    """One radius with RESET: per-particle F and a_coll, GPU vs oracle."""
+    n = h6.shape[1]
+    g = orc.Growth(a, D)
+    F = np.zeros(n)
+    R = np.full(n, -1, np.int32)
+    A = np.full(n, np.inf)
+    orc.update_radius(h6, 0, g, F, R, A, reset=True)
+    with pkg.Collapse([(a, D)]) as col:
+        got = run_gpu_radii(col, [torch.from_numpy(np.ascontiguousarray(h6)).cuda()], acoll=acoll)
+    return (F, R, A if acoll else None), got
+
+
+def _special_hessians():
+    rng = np.random.default_rng(17)
+    rows = []
+    # diagonal, spherical, planar, rank-one, repeated eigenvalues, tiny and large scales
+    for lam in [(1, 1, 1), (2, 0, 0), (1, 1, 0), (3, 3, -1), (0.5, -0.5, -0.5), (1e-8, 1e-9, -1e-9),
+                (40.0, 3.0, -2.0), (-1, -2, -3), (0, 0, 0), (1e-3, 0, 0), (5, 5, 5.0000001)]:
+        rows.append([lam[0], lam[1], lam[2], 0, 0, 0])
+    for _ in range(200):   # random rotations of degenerate spectra
+        Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        l = rng.normal(size=3)
+        l[1] = l[0] * (1 + rng.choice([0, 1e-12, 1e-8, 1e-5]))
+        if rng.uniform() < 0.5:
+            l[2] = l[1]
+        H = Q @ np.diag(l) @ Q.T
+        rows.append([H[0, 0], H[1, 1], H[2, 2], H[0, 1], H[0, 2], H[1, 2]])
+    return np.array(rows).T.copy()
+
+
+def test_special_matrices(pkg, orc):
+    a, D = synth.growth_table(0.3)
+    h6 = _special_hessians()
+    print(f"special: n={h6.shape[1]}", flush=True)
+    ref, got = _single(pkg, orc, h6, a, D)
+    compare(ref, got, label="special")
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 255, 257, 4097, 100003])
+def test_ragged_sizes(pkg, orc, n):
+    a, D = synth.growth_table(0.3)
+    rng = np.random.default_rng(n)
+    h6 = rng.normal(size=(6, n)) * rng.uniform(0.05, 3.0)
+    print(f"ragged n={n}", flush=True)
+    ref, got = _single(pkg, orc, h6, a, D)
+    compare(ref, got, label=f"n={n}")
+
+
+def test_empty_item_and_null_acoll(pkg, orc):
+    a, D = synth.growth_table(0.3)
+    with pkg.Collapse([(a, D)]) as col:
+        Fmax, Rmax, ac = col.outputs(0)
+        h = torch.zeros((6, 0), dtype=torch.float64, device="cuda")
+        col.apply(h, 0, Fmax, Rmax, ac, reset=True, sync=True)
+    rng = np.random.default_rng(5)
+    h6 = rng.normal(size=(6, 5000))
+    ref, got = _single(pkg, orc, h6, a, D, acoll=False)
+    compare(ref, got, label="null a_coll")
+
+
+def test_nan_inf_never_update(pkg):
+    a, D = synth.growth_table(0.3)
+    n = 4096
+    rng = np.random.default_rng(8)
+    good = torch.from_numpy(rng.normal(size=(6, n))).cuda()
+    bad = good.clone() * 3.0
+    bad[0, :100] = float("nan")
+    bad[3, 100:200] = float("inf")
+    bad[5, 200:300] = -float("inf")
+    with pkg.Collapse([(a, D)]) as col:
+        Fmax, Rmax, ac = col.outputs(n)
+        col.apply(good, 0, Fmax, Rmax, ac, reset=True)
+        F0, R0, A0 = Fmax.clone(), Rmax.clone(), ac.clone()
+        col.apply(bad, 1, Fmax, Rmax, ac)
+        torch.cuda.synchronize()
+    assert torch.equal(Fmax[:300], F0[:300]) and torch.equal(Rmax[:300], R0[:300])
+    assert torch.equal(ac[:300], A0[:300])
+
+
+def test_multi_cosmology_items_in_one_call(pkg, orc):
+    tables = [synth.growth_table(om) for om in (0.25, 0.3, 0.35)]
+    rng = np.random.default_rng(21)
+    hs = [rng.normal(size=(6, 3000 + 500 * k)) for k in range(3)]
+    with pkg.Collapse(tables) as col:
+        outs, items = [], []
+        for k, h6 in enumerate(hs):
+            Fm, Rm, ac = col.outputs(h6.shape[1])
+            dh = torch.from_numpy(h6).cuda()
+            outs.append((Fm, Rm, ac, dh))
+            items.append(col.item(dh, Fm, Rm, ac, radius_index=k, cosmo=k))
+        col.eval(items, reset=True, sync=True)
+        for k, h6 in enumerate(hs):
+            g = orc.Growth(*tables[k])
+            n = h6.shape[1]
+            F, R, A = np.zeros(n), np.full(n, -1, np.int32), np.full(n, np.inf)
+            orc.update_radius(h6, k, g, F, R, A, reset=True)
+            Fm, Rm, ac, _ = outs[k]
+            compare((F, R, A), (Fm.cpu().numpy(), Rm.cpu().numpy(), ac.cpu().numpy()), label=f"cosmo {k}")
+
+
+def test_c2_full_size_sampled(pkg, orc):
+    """256^3 x 25 radii on the GPU in the benchmark's launch configuration;
+    the oracle recomputes a seeded sample of particles over all radii."""
+    cfg = synth.config("C2")
+    a, D = synth.growth_table(cfg["cosmo"].omega_m, cfg["n_growth"])
+    fld = synth.fields.field(cfg["n_side"], cfg["box"], cfg["seed"], cfg["cosmo"], device="cuda")
+    n = cfg["n_side"] ** 3
+    rng = np.random.default_rng(99)
+    idx = np.sort(rng.choice(n, size=20000, replace=False))
+    idx = np.concatenate([idx, [0, n - 1]])
+    tidx = torch.from_numpy(idx).cuda()
+    sample = []
+    print(f"C2 full size: n={n} radii={len(cfg['radii'])}", flush=True)
+    with pkg.Collapse([(a, D)]) as col:
+        Fmax, Rmax, ac = col.outputs(n)
+        for r, R in enumerate(cfg["radii"]):
+            h = fld.hessian(R)
+            col.apply(h, r, Fmax, Rmax, ac, reset=(r == 0))
+            sample.append(h[:, tidx].cpu().numpy())
+            del h
+        torch.cuda.synchronize()
+        got = (Fmax[tidx].cpu().numpy(), Rmax[tidx].cpu().numpy(), ac[tidx].cpu().numpy())
+    ref = orc.collapse(sample, orc.Growth(a, D))
+    ties = near_tie_mask([orc.points(s)[1] for s in sample])
+    st = compare(ref, got, tie_mask=ties, label="C2 sample")
+    print("C2 sample stats", st, flush=True)
