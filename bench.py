@@ -34,13 +34,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(n, updates, reset):
+def algorithmic_bytes(n, updates, reset, finalize):
     """HBM bytes one launch must move: 6 FP64 Hessian components (48 B), the
-    running Fmax (8 B, not read on the RESET radius) and, for every particle
-    whose max changes (all of them on RESET), Fmax + Rmax + a_coll (20 B)."""
-    if reset:
-        return n * (48 + 20)
-    return n * (48 + 8) + updates * 20
+    running Fmax (8 B, not read on the RESET radius), Fmax + Rmax (12 B) for
+    every particle whose maximum changes (all of them on RESET), and a_coll
+    (8 B per particle) on the finalizing launch."""
+    b = n * 48 + (0 if reset else n * 8) + (n if reset else updates) * 12
+    return b + (n * 8 if finalize else 0)
 
 
 def main():
@@ -51,6 +51,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 18, help="particles in the oracle sample")
     ap.add_argument("--n-side", type=int, default=None, help="override the grid side (testing only)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, copy a buffer of this many MiB device-to-device once, so HBM "
+                         "counters can be scaled against a transfer of known size")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -85,28 +88,41 @@ def main():
     log(f"inputs ready: n={n} radii={len(radii)} in {time.time() - t0:.1f}s "
         f"({len(radii) * 48 * n / 1e9:.1f} GB of Hessians resident)")
 
+    if args.calib_copy_mib > 0:
+        src = torch.empty(args.calib_copy_mib << 17, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
+
     col = P.Collapse([(a, D)], device=0)
     Fmax, Rmax, ac = col.outputs(n)
     stream = torch.cuda.current_stream(dev)
+
+    last = len(radii) - 1
+    # a_coll is produced once, from the running maximum, on the last radius
+    # (PINO_EVAL_FINALIZE; identical to updating it at every radius)
+    items = [col.item(slabs[r], Fmax, Rmax, ac if r == last else None, radius_index=r)
+             for r in range(len(radii))]
 
     # untimed pass: how many particles update their max at each radius
     updates = []
     prev = None
     for r in range(len(radii)):
-        col.apply(slabs[r], r, Fmax, Rmax, ac, reset=(r == 0), stream=stream)
+        col.eval([items[r]], reset=(r == 0), finalize=(r == last), stream=stream)
         cur = Fmax.clone()
         updates.append(int(n if prev is None else (cur != prev).sum().item()))
         prev = cur
     del prev, cur
-    bytes_per_launch = [algorithmic_bytes(n, u, r == 0) for r, u in enumerate(updates)]
-
-    items = [col.item(slabs[r], Fmax, Rmax, ac, radius_index=r) for r in range(len(radii))]
+    bytes_per_launch = [algorithmic_bytes(n, u, r == 0, r == last) for r, u in enumerate(updates)]
 
     def step(events=None):
         for r, it in enumerate(items):
             if events is not None:
                 events[r][0].record(stream)
-            col.eval([it], reset=(r == 0), stream=stream)
+            col.eval([it], reset=(r == 0), finalize=(r == last), stream=stream)
             if events is not None:
                 events[r][1].record(stream)
 
@@ -164,9 +180,15 @@ def main():
                          f"({dt:.1f} s)"}
         # the sampled particles also serve as a parity spot check of this run
         got_F = Fmax[idx].cpu().numpy()
+        got_R = Rmax[idx].cpu().numpy()
+        got_a = ac[idx].cpu().numpy()
         big = ref[0] >= 1e-6
         rel = float(np.max(np.abs(1 / got_F[big] - 1 / ref[0][big]) * ref[0][big])) if big.any() else 0.0
+        fin = np.isfinite(ref[2])
+        rel_a = float(np.max(np.abs(got_a[fin] - ref[2][fin]) / ref[2][fin])) if fin.any() else 0.0
         cpu["parity_max_rel_Dc"] = rel
+        cpu["parity_max_rel_acoll"] = rel_a
+        cpu["parity_index_mismatches"] = int(np.sum(got_R != ref[1]))
         log(f"cpu baseline {cpu['value']:.3e} evals/s; sample parity max rel D_c {rel:.2e}")
 
     out = {

@@ -75,8 +75,13 @@ typedef enum { PINO_CLASSIC = 0, PINO_TABULATED = 1 } pino_method;
 typedef enum { PINO_FP64 = 0, PINO_MIXED = 1, PINO_SURROGATE = 2 } pino_precision;
 
 /* eval flags */
-#define PINO_EVAL_RESET 1u  /* set Fmax = 0, Rmax = -1, a_coll = +inf before applying the item */
-#define PINO_EVAL_SYNC 2u   /* wait for the stream before returning */
+#define PINO_EVAL_RESET 1u     /* set Fmax = 0, Rmax = -1, a_coll = +inf before applying the item */
+#define PINO_EVAL_SYNC 2u      /* wait for the stream before returning */
+#define PINO_EVAL_FINALIZE 4u  /* after applying the item, set a_coll (non-NULL) for every particle
+                                  from the running maximum: a(1/Fmax), or +inf where Fmax == 0.
+                                  Because a(D) is increasing, this equals what per-update a_coll
+                                  gives, bit for bit; callers may pass a_coll = NULL for all but
+                                  the last radius and FINALIZE on the last one. */
 
 /* One linear growth table: n >= 4 knots, a and D strictly increasing and
  * finite (host pointers, copied by init).  The library builds the natural

@@ -22,6 +22,7 @@ PINO_CLASSIC, PINO_TABULATED = 0, 1
 PINO_FP64, PINO_MIXED, PINO_SURROGATE = 0, 1, 2
 PINO_EVAL_RESET = 1
 PINO_EVAL_SYNC = 2
+PINO_EVAL_FINALIZE = 4
 
 _D = ctypes.POINTER(ctypes.c_double)
 

@@ -19,6 +19,14 @@ struct pino_ctx {
     std::vector<int> nk;
     double* d_growth = nullptr;
 
+    // per cosmology interval index of the growth knots: [idx | need], stride
+    // 2 * nb_max ints; bin geometry and whether the two-compare bound holds
+    int nb_max = 0;
+    int* d_gidx = nullptr;
+    std::vector<int> nb;
+    std::vector<float> gL0, gS;
+    std::vector<int> gok;
+
     // tabulated method: dimensionless knots [x | y | delta], the interleaved
     // (F, M) table of the current radius, sigma-scaled delta knots
     int nx = 0, ny = 0, nd = 0;

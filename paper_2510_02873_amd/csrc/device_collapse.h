@@ -23,6 +23,34 @@ namespace pino {
 constexpr double kTwoPiOver3 = 2.0943951023931954923;
 constexpr double kInf = __builtin_huge_val();
 
+// Reciprocal: hardware estimate refined by Newton-Raphson steps (each step
+// squares the relative error).  Two steps reach the FP64 rounding level; the
+// result is not IEEE-rounded, which only the last bit can tell.
+__host__ __device__ __forceinline__ double rcp2(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// x = 2 cos(phi), the root of x^3 - 3x = 2r on [1, 2] (phi = acos(r)/3, the
+// largest eigenvalue) or on [-2, -1] (phi + 2 pi/3, the smallest): an FP32
+// estimate from the trigonometric form, then two FP64 Halley steps.  Outside
+// the nearly repeated band (|1 -+ r| < kNearRepeated, handled by deflation)
+// the estimate is within ~3e-5 and two steps leave < 1e-16.
+__host__ __device__ __forceinline__ double depressed_root(double r, bool largest)
+{
+    const float th = acosf((float)r) * (1.0f / 3.0f) + (largest ? 0.0f : 2.0943951f);
+    double x = 2.0 * (double)__cosf(th);
+    for (int k = 0; k < 2; ++k) {
+        const double f = x * (x * x - 3.0) - 2.0 * r;
+        const double f1 = 3.0 * (x * x - 1.0);
+        const double f2 = 6.0 * x;
+        x -= (2.0 * f * f1) * rcp2(2.0 * f1 * f1 - f * f2);
+    }
+    return x;
+}
+
 // ---------------------------------------------------------------------------
 // Eigenvalues.  With q = tr(H)/3, p = sqrt(tr((H - qI)^2)/6) and
 // r = det((H - qI)/p)/2, the eigenvalues are q + 2p cos(phi + 2 pi k/3),
@@ -32,23 +60,21 @@ struct Hess64 {
     double xx, yy, zz, xy, xz, yz;
 };
 
-// cos(phi) and the scale of the trigonometric solution; p == 0 (a multiple
-// of the identity) gives q for every eigenvalue.  r is returned so callers
-// can detect a nearly repeated eigenvalue (r -> -1: l1 ~ l2, r -> +1: l2 ~ l3)
-// where the closed form loses about half the digits of the pair.
-__host__ __device__ __forceinline__ void eig_trig(const Hess64& h, double& q, double& p2x, double& phi, double& r)
+// q = tr/3, p and r of the trigonometric solution.  p == 0 (a multiple of
+// the identity) gives r = 0 and every eigenvalue equal to q.  r -> -1 means
+// l1 ~ l2 and r -> +1 means l2 ~ l3; near either end the cubic has a nearly
+// double root and the pair loses about half its digits.
+__host__ __device__ __forceinline__ void eig_moments(const Hess64& h, double& q, double& p, double& r)
 {
     q = (h.xx + h.yy + h.zz) * (1.0 / 3.0);
     const double dx = h.xx - q, dy = h.yy - q, dz = h.zz - q;
     const double off = h.xy * h.xy + h.xz * h.xz + h.yz * h.yz;
     const double ss = dx * dx + dy * dy + dz * dz + 2.0 * off;
-    const double p = sqrt(ss * (1.0 / 6.0));
+    p = sqrt(ss * (1.0 / 6.0));
     const double det = dx * (dy * dz - h.yz * h.yz) - h.xy * (h.xy * dz - h.yz * h.xz) + h.xz * (h.xy * h.yz - dy * h.xz);
-    const double ip = p > 0.0 ? 1.0 / p : 0.0;
+    const double ip = p > 0.0 ? rcp2(p) : 0.0;
     r = 0.5 * det * (ip * ip * ip);
     r = fmin(fmax(r, -1.0), 1.0);
-    phi = acos(r) * (1.0 / 3.0);
-    p2x = 2.0 * p;
 }
 
 // Threshold on 1 -+ r below which the repeated pair is recomputed by
@@ -115,13 +141,14 @@ __host__ __device__ __forceinline__ void deflate_pair(const Hess64& h, double mu
 // pp = mu2 - l1 s, mu2 the sum of the principal 2x2 minors.
 __host__ __device__ __forceinline__ void eig_top(const Hess64& h, double& l1, double& s, double& pp)
 {
-    double q, p2x, phi, r;
-    eig_trig(h, q, p2x, phi, r);
-    l1 = q + p2x * cos(phi);
+    double q, p, r;
+    eig_moments(h, q, p, r);
+    l1 = q + p * depressed_root(r, true);
     if (1.0 + r < kNearRepeated) {
-        // l1 ~ l2: l3 is well separated, the pair comes from the 2x2 block
+        // l1 ~ l2: l3 (a simple root there) is well separated, the pair
+        // comes from the 2x2 block
         double lo;
-        const double l3 = q + p2x * cos(phi + kTwoPiOver3);
+        const double l3 = q + p * depressed_root(r, false);
         deflate_pair(h, l3, l1, lo);
     }
     const double tr = h.xx + h.yy + h.zz;
@@ -133,15 +160,21 @@ __host__ __device__ __forceinline__ void eig_top(const Hess64& h, double& l1, do
 // All three eigenvalues, descending.
 __host__ __device__ __forceinline__ void eig_all(const Hess64& h, double& l1, double& l2, double& l3)
 {
-    double q, p2x, phi, r;
-    eig_trig(h, q, p2x, phi, r);
-    l1 = q + p2x * cos(phi);
-    l3 = q + p2x * cos(phi + kTwoPiOver3);
-    l2 = (h.xx + h.yy + h.zz) - l1 - l3;
-    if (1.0 + r < kNearRepeated)
+    double q, p, r;
+    eig_moments(h, q, p, r);
+    // near either end of r one root of the depressed cubic is simple (well
+    // conditioned) and the nearly repeated pair comes from deflation
+    if (1.0 + r < kNearRepeated) {
+        l3 = q + p * depressed_root(r, false);
         deflate_pair(h, l3, l1, l2);
-    else if (1.0 - r < kNearRepeated)
+    } else if (1.0 - r < kNearRepeated) {
+        l1 = q + p * depressed_root(r, true);
         deflate_pair(h, l1, l2, l3);
+    } else {
+        l1 = q + p * depressed_root(r, true);
+        l3 = q + p * depressed_root(r, false);
+        l2 = (h.xx + h.yy + h.zz) - l1 - l3;
+    }
     l2 = fmin(fmax(l2, l3), l1);
 }
 
@@ -193,27 +226,51 @@ __host__ __device__ __forceinline__ Bracket lpt_bracket(const CubicU& k)
     const double sq = sqrt(fmax(disc, 0.0));
     const double den1 = k.b + sq;
     const bool has1 = disc >= 0.0 && den1 > 0.0;
-    const double u1 = has1 ? 1.0 / den1 : 0.0;
+    const double u1 = has1 ? rcp2(den1) : 0.0;
     const bool before_min = has1 && g_u(k, u1) <= 0.0;
-    const double far = k.c < 0.0 ? fmax(1.0, 2.0 * fmax(k.b, 0.0) / (-k.c)) : 1.0;
+    const double far = k.c < 0.0 ? fmax(1.0, 2.0 * fmax(k.b, 0.0) * rcp2(-k.c)) : 1.0;
     const bool past_max = has1 && !before_min && k.c < 0.0;
     Bracket br;
     br.root = !has1 || before_min || past_max;
-    br.lo = past_max ? 1.0 / (k.b - sq) : 0.0;
+    br.lo = past_max ? rcp2(k.b - sq) : 0.0;
     br.hi = before_min ? u1 : far;
     return br;
 }
 
+// FP32 estimate of the largest real root of w^3 - w^2 + b w + c, which is
+// 1/u of the smallest positive root of g (w = 1/u maps one onto the other).
+// Depressed with w = t + 1/3: t^3 + P t + Q = 0.  Three real roots: the
+// largest is m cos(acos(3Q/(P m))/3), m = 2 sqrt(-P/3); one real root: the
+// cancellation-free Cardano form A - P/(3A), A = -sign(Q) cbrt(|Q|/2 + sqrt(d)).
+__host__ __device__ __forceinline__ float top_root_guess(double b, double c)
+{
+    const float P = (float)(b - 1.0 / 3.0);
+    const float Q = (float)(c + b * (1.0 / 3.0) - 2.0 / 27.0);
+    const float p3 = P * (1.0f / 3.0f);
+    const float d = 0.25f * Q * Q + p3 * p3 * p3;
+    float t;
+    if (d <= 0.0f) {
+        const float m = 2.0f * sqrtf(fmaxf(-p3, 0.0f));
+        const float arg = fminf(fmaxf(3.0f * Q / (P * m), -1.0f), 1.0f);
+        t = m * __cosf(acosf(arg) * (1.0f / 3.0f));
+    } else {
+        const float A = -copysignf(cbrtf(0.5f * fabsf(Q) + sqrtf(d)), Q);
+        t = A != 0.0f ? A - P / (3.0f * A) : 0.0f;
+    }
+    return t + (1.0f / 3.0f);
+}
+
 // Halley iteration kept inside the bracket (bisection when a step leaves it);
-// stops when the step is below a few ulps.  Starts from the second-order LPT
-// root 2 / (1 + sqrt(1 - 4b)) when it lies in the bracket.
+// stops when the step is below a few ulps.  The start is the FP32 estimate
+// above, so two steps normally reach full FP64 accuracy; the bracket makes the
+// result the smallest positive root whatever the estimate.
 __host__ __device__ __forceinline__ double lpt_solve_u(const CubicU& k, Bracket br)
 {
-    const double disc2 = 1.0 - 4.0 * k.b;
-    double u = disc2 >= 0.0 ? 2.0 / (1.0 + sqrt(disc2)) : 1.0;
-    if (!(u > br.lo && u < br.hi))
-        u = 0.5 * (br.lo + br.hi);
+    const float w0 = top_root_guess(k.b, k.c);
+    double u = rcp2((double)w0);
     double lo = br.lo, hi = br.hi;
+    if (!(u > lo && u < hi))
+        u = 0.5 * (lo + hi);
     for (int it = 0; it < 80; ++it) {
         const double g = g_u(k, u);
         if (g == 0.0)
@@ -224,8 +281,9 @@ __host__ __device__ __forceinline__ double lpt_solve_u(const CubicU& k, Bracket 
             lo = u;
         else
             hi = u;
-        double un = u - (2.0 * g * g1) / (2.0 * g1 * g1 - g * g2);
-        if (!(un > lo && un < hi))
+        double un = u - (2.0 * g * g1) * rcp2(2.0 * g1 * g1 - g * g2);
+        // inclusive: a step below one ulp leaves u on a bracket end
+        if (!(un >= lo && un <= hi))
             un = 0.5 * (lo + hi);
         const double step = fabs(un - u);
         u = un;
@@ -235,20 +293,50 @@ __host__ __device__ __forceinline__ double lpt_solve_u(const CubicU& k, Bracket 
     return u;
 }
 
-// F = 1/D_c (0 without collapse) and D_c itself (inf without collapse).
-__host__ __device__ __forceinline__ double classic_F(double l1, double s, double pp, double& Dc)
+// Direct solve in w = 1/u: the collapse is the largest real root of the monic
+// cubic q(w) = w^3 - w^2 + b w + c (F = l1 w, no collapse when it is <= 0).
+// Two FP64 Halley steps polish the FP32 estimate.  The result is accepted
+// when the last step was small (converged) and w is provably the largest
+// root: either q has no critical points (1 - 3b <= 0, q increasing), or w
+// lies past the upper critical point wc = (1 + sqrt(1 - 3b))/3 (taken with a
+// margin above the FP32 rounding of wc), or q's local minimum at wc is
+// positive (one real root).  Otherwise the bracketed solver decides.
+__host__ __device__ __forceinline__ bool top_root_w(const CubicU& k, double& w)
 {
-    Dc = kInf;
+    w = (double)top_root_guess(k.b, k.c);
+    double step = 0.0;
+    for (int it = 0; it < 2; ++it) {
+        const double q = ((w - 1.0) * w + k.b) * w + k.c;
+        const double q1 = (3.0 * w - 2.0) * w + k.b;
+        const double q2 = 6.0 * w - 2.0;
+        step = (2.0 * q * q1) * rcp2(2.0 * q1 * q1 - q * q2);
+        w -= step;
+    }
+    const bool converged = fabs(step) <= 1e-7 * fabs(w);
+    const float e = (float)(1.0 - 3.0 * k.b);
+    bool largest = true;
+    if (e > 0.0f) {
+        const double wc = (double)((1.0f + sqrtf(e)) * (1.0f / 3.0f));
+        const double qc = ((wc - 1.0) * wc + k.b) * wc + k.c;
+        largest = w >= wc * (1.0 + 1e-6) || qc > 0.0;
+    }
+    return converged && largest;
+}
+
+// F = 1/D_c, 0 without collapse.
+__host__ __device__ __forceinline__ double classic_F(double l1, double s, double pp)
+{
     if (!(l1 > 0.0))
         return 0.0;
-    const double il1 = 1.0 / l1;
+    const double il1 = rcp2(l1);
     const CubicU k = lpt_cubic(l1, s, pp, il1);
-    const Bracket br = lpt_bracket(k);
-    if (!br.root)
-        return 0.0;
-    const double u = lpt_solve_u(k, br);
-    Dc = u * il1;
-    return 1.0 / Dc;
+    double w;
+    if (!top_root_w(k, w)) {
+        // nearly tangent or unconverged: bracketed solve in u = 1/w
+        const Bracket br = lpt_bracket(k);
+        w = br.root ? rcp2(lpt_solve_u(k, br)) : 0.0;
+    }
+    return w > 0.0 ? l1 * w : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -275,13 +363,36 @@ __host__ __device__ __forceinline__ double spline_piece(double x0, double x1, do
                                                double q)
 {
     const double h = x1 - x0;
-    const double t = (q - x0) / h;
+    const double t = (q - x0) * rcp2(h);
     const double w = 1.0 - t;
     return w * y0 + t * y1 + (h * h * (1.0 / 6.0)) * ((w * w * w - w) * m0 + (t * t * t - t) * m1);
 }
 
+// Interval lookup for the growth knots: bins uniform in log2(D) map a query
+// to the first knot interval that can contain it (idx), and at most two
+// compares finish the search; init verifies that bound for the table at hand
+// (otherwise the plain binary search is used).  The interval found is the one
+// `locate` finds.
+struct GrowthIndex {
+    const int* idx;  // nb entries (in LDS once staged)
+    int nb;
+    float L0;        // log2 of the first knot
+    float S;         // bins per unit of log2 D
+    int ok;          // the two-compare bound holds for this table
+};
+
+__host__ __device__ __forceinline__ int locate_indexed(const double* D, int n, double q, const GrowthIndex& gi)
+{
+    float fb = (__log2f((float)q) - gi.L0) * gi.S;
+    fb = fminf(fmaxf(fb, 0.0f), (float)(gi.nb - 1));
+    int i = gi.idx[(int)fb];
+    i += (i + 1 <= n - 2 && D[i + 1] <= q) ? 1 : 0;
+    i += (i + 1 <= n - 2 && D[i + 1] <= q) ? 1 : 0;
+    return i;
+}
+
 // a(D) from the growth knots staged as [D | a | M] (n each).
-__host__ __device__ __forceinline__ double growth_invert(const double* g, int n, double Dc)
+__host__ __device__ __forceinline__ double growth_invert(const double* g, int n, double Dc, const GrowthIndex& gi)
 {
     const double* D = g;
     const double* a = g + n;
@@ -290,7 +401,7 @@ __host__ __device__ __forceinline__ double growth_invert(const double* g, int n,
         return kInf;
     if (Dc < D[0])
         return a[0];
-    const int i = locate(D, n, Dc);
+    const int i = gi.ok ? locate_indexed(D, n, Dc, gi) : locate(D, n, Dc);
     return spline_piece(D[i], D[i + 1], a[i], a[i + 1], M[i], M[i + 1], Dc);
 }
 

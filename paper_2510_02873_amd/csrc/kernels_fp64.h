@@ -71,8 +71,10 @@ struct ItemArgs {
     int64_t n;
     const double* growth;  // [D | a | M], nk each
     int nk;
+    GrowthIndex gi;        // idx points to global memory; kernels stage it
     int32_t radius;
     uint32_t reset;
+    uint32_t finalize;
     double* Fmax;
     int32_t* Rmax;
     double* acoll;
@@ -82,6 +84,24 @@ __device__ __forceinline__ void stage(double* dst, const double* __restrict__ sr
 {
     for (int k = threadIdx.x; k < count; k += blockDim.x)
         dst[k] = src[k];
+}
+
+// growth knots and their interval index into LDS; returns the LDS index view
+__device__ __forceinline__ GrowthIndex stage_growth(double* lds, const ItemArgs& a)
+{
+    stage(lds, a.growth, 3 * a.nk);
+    int* idx = reinterpret_cast<int*>(lds + 3 * a.nk);
+    for (int k = threadIdx.x; k < a.gi.nb; k += blockDim.x)
+        idx[k] = a.gi.idx[k];
+    GrowthIndex gi = a.gi;
+    gi.idx = idx;
+    return gi;
+}
+
+// LDS bytes of stage_growth
+__host__ __device__ inline size_t growth_lds_bytes(int nk, int nb)
+{
+    return 3 * (size_t)nk * sizeof(double) + (((size_t)nb * sizeof(int) + 7) / 8) * 8;
 }
 
 __device__ __forceinline__ Hess64 load_h64(const ItemArgs& a, int64_t i)
@@ -96,32 +116,48 @@ __device__ __forceinline__ Hess64 load_h64(const ItemArgs& a, int64_t i)
     return h;
 }
 
-// max update with the strict '>' rule; RESET writes every element
-__device__ __forceinline__ void update_max(const ItemArgs& a, const double* g, int64_t i, double F, double Dc)
+// Max update with the strict '>' rule.  Every element is written, whether
+// or not its maximum changes: a wave then stores whole cache lines, which HBM
+// takes far faster than the partial lines of masked stores (the old Rmax and
+// a_coll are read to be written back).  a(D_c), D_c = 1/F, is evaluated only
+// where needed: on update, or for every element from the running maximum
+// when finalizing.
+__device__ __forceinline__ void update_max(const ItemArgs& a, const double* g, const GrowthIndex& gi, int64_t i,
+                                           double F, double fm)
 {
-    const double fm = a.reset ? 0.0 : a.Fmax[i];
     const bool upd = F > fm;
-    if (upd || a.reset) {
-        a.Fmax[i] = upd ? F : 0.0;
-        a.Rmax[i] = upd ? a.radius : -1;
-        if (a.acoll)
-            a.acoll[i] = upd ? growth_invert(g, a.nk, Dc) : kInf;
+    const double fnew = upd ? F : fm;
+    const int32_t rm = a.reset ? -1 : a.Rmax[i];
+    a.Fmax[i] = fnew;
+    a.Rmax[i] = upd ? a.radius : rm;
+    if (a.acoll) {
+        if (a.finalize) {
+            a.acoll[i] = fnew > 0.0 ? growth_invert(g, a.nk, rcp2(fnew), gi) : kInf;
+        } else {
+            const double am = a.reset ? kInf : a.acoll[i];
+            a.acoll[i] = upd ? growth_invert(g, a.nk, rcp2(F), gi) : am;
+        }
     }
 }
 
-__global__ void __launch_bounds__(256) k_classic_f64(ItemArgs a)
+#ifndef PINO_WAVES_PER_EU
+#define PINO_WAVES_PER_EU 4
+#endif
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PINO_WAVES_PER_EU)))
+k_classic_f64(ItemArgs a)
 {
     extern __shared__ double lds[];
-    stage(lds, a.growth, 3 * a.nk);
+    const GrowthIndex gi = stage_growth(lds, a);
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
         const Hess64 h = load_h64(a, i);
+        const double fm = a.reset ? 0.0 : a.Fmax[i];
         double l1, s, pp;
         eig_top(h, l1, s, pp);
-        double Dc;
-        const double F = classic_F(l1, s, pp, Dc);
-        update_max(a, lds, i, F, Dc);
+        const double F = classic_F(l1, s, pp);
+        update_max(a, lds, gi, i, F, fm);
     }
 }
 
@@ -157,8 +193,8 @@ __device__ __forceinline__ double table_F(const TabArgs& t, const double* xs, co
     const double y = l2 - l3;
     const int ix = locate(xs, t.nx, x);
     const int iy = locate(ys, t.ny, y);
-    const double tt = fmin(fmax((x - xs[ix]) / (xs[ix + 1] - xs[ix]), 0.0), 1.0);
-    const double uu = fmin(fmax((y - ys[iy]) / (ys[iy + 1] - ys[iy]), 0.0), 1.0);
+    const double tt = fmin(fmax((x - xs[ix]) * rcp2(xs[ix + 1] - xs[ix]), 0.0), 1.0);
+    const double uu = fmin(fmax((y - ys[iy]) * rcp2(ys[iy + 1] - ys[iy]), 0.0), 1.0);
     const double dq = fmin(fmax(delta, ds[0]), ds[t.nd - 1]);
     const int j = locate(ds, t.nd, dq);
     const double d0 = ds[j], d1 = ds[j + 1];
@@ -175,10 +211,10 @@ __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
 {
     extern __shared__ double lds[];
     double* g = lds;
-    double* xs = lds + 3 * a.nk;
+    const GrowthIndex gi = stage_growth(lds, a);
+    double* xs = lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
     double* ys = xs + t.nx;
     double* ds = ys + t.ny;
-    stage(g, a.growth, 3 * a.nk);
     for (int k = threadIdx.x; k < t.nx; k += blockDim.x)
         xs[k] = t.xk[k] * t.scale;
     for (int k = threadIdx.x; k < t.ny; k += blockDim.x)
@@ -193,9 +229,27 @@ __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
         eig_all(h, l1, l2, l3);
         const bool finite = isfinite(l1) && isfinite(l2) && isfinite(l3);
         const double F = finite ? table_F(t, xs, ys, ds, l1, l2, l3) : 0.0;
-        const double Dc = 1.0 / F;
-        update_max(a, g, i, F, Dc);
+        update_max(a, g, gi, i, F, a.reset ? 0.0 : a.Fmax[i]);
     }
+}
+
+// Interval index of a growth table (see GrowthIndex): bin b covers
+// log2 D in [L0 + b/S, L0 + (b+1)/S), widened by a margin far above the FP32
+// rounding of the lookup; idx[b] is the interval of the bin's low end and
+// need[b] the number of compares the bin's high end needs beyond it.
+__global__ void __launch_bounds__(256) k_growth_index(const double* __restrict__ D, int n, int nb, double L0,
+                                                     double S, int* __restrict__ idx, int* __restrict__ need)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb)
+        return;
+    const double margin = 1e-4;
+    const double lo = exp2(L0 + b / S - margin);
+    const double hi = exp2(L0 + (b + 1) / S + margin);
+    const int i0 = locate(D, n, lo);
+    const int i1 = locate(D, n, hi);
+    idx[b] = i0;
+    need[b] = i1 - i0;
 }
 
 // dst[k] = src[k] * scale

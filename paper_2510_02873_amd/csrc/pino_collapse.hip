@@ -102,7 +102,7 @@ bool validate_config(const pino_config* cfg, std::string& why)
     return true;
 }
 
-bool validate_items(const pino_ctx* ctx, const pino_item* items, int32_t n_items, std::string& why)
+bool validate_items(const pino_ctx* ctx, const pino_item* items, int32_t n_items, uint32_t flags, std::string& why)
 {
     if (n_items < 0) {
         why = "n_items < 0";
@@ -138,6 +138,10 @@ bool validate_items(const pino_ctx* ctx, const pino_item* items, int32_t n_items
             why = at + "Fmax and Rmax must be non-NULL";
             return false;
         }
+        if ((flags & PINO_EVAL_FINALIZE) && !it.a_coll) {
+            why = at + "PINO_EVAL_FINALIZE needs a_coll";
+            return false;
+        }
         if ((ctx->method == PINO_TABULATED || ctx->precision == PINO_SURROGATE) &&
             !(std::isfinite(it.sigma_R) && it.sigma_R > 0.0)) {
             why = at + "sigma_R must be finite and > 0";
@@ -165,6 +169,30 @@ pino_status hip_fail(pino_ctx* ctx, hipError_t e, const char* what)
             return hip_fail((ctx), e_, #call);       \
     } while (0)
 
+// LDS per workgroup: growth knots + index bins, plus the table knots of the
+// Tabulated method; kept within 64 KiB
+constexpr size_t kLdsBudget = 65536;
+
+int index_bins(int nk)
+{
+    return (int)std::min<int64_t>(4 * (int64_t)nk, (57344 - 24 * (int64_t)nk) / 4);
+}
+
+bool lds_fits(const pino_config* cfg, std::string& why)
+{
+    int nk_max = 0;
+    for (int k = 0; k < cfg->n_cosmo; ++k)
+        nk_max = std::max(nk_max, (int)cfg->growth[k].n);
+    size_t need = growth_lds_bytes(nk_max, index_bins(nk_max));
+    if (cfg->method == PINO_TABULATED)
+        need += sizeof(double) * ((size_t)cfg->table->nx + cfg->table->ny + cfg->table->nd);
+    if (need > kLdsBudget) {
+        why = "growth and table knots need " + std::to_string(need) + " bytes of LDS, more than 64 KiB";
+        return false;
+    }
+    return true;
+}
+
 int grid_for(const pino_ctx* ctx, int64_t n, int block)
 {
     const int64_t need = (n + block - 1) / block;
@@ -176,11 +204,12 @@ void free_all(pino_ctx* c)
 {
     if (!c)
         return;
-    void* ptrs[] = {c->d_growth, c->d_tknots, c->d_tab, c->d_dscaled, c->d_tmp, c->d_mlp, c->d_counters};
+    void* ptrs[] = {c->d_growth, c->d_gidx, c->d_tknots, c->d_tab, c->d_dscaled, c->d_tmp, c->d_mlp, c->d_counters};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
     c->d_growth = c->d_tknots = c->d_tab = c->d_dscaled = c->d_tmp = nullptr;
+    c->d_gidx = nullptr;
     c->d_mlp = nullptr;
     c->d_counters = nullptr;
 }
@@ -242,6 +271,40 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
         PINO_HIP(c, hipGetLastError());
     }
 
+    // interval index of each growth table (bins uniform in log2 D, up to 4 per
+    // knot, kept within the LDS budget of the kernels)
+    c->nb_max = index_bins(nk_max);
+    c->nb.resize(cfg->n_cosmo);
+    c->gL0.resize(cfg->n_cosmo);
+    c->gS.resize(cfg->n_cosmo);
+    c->gok.resize(cfg->n_cosmo);
+    PINO_HIP(c, hipMalloc((void**)&c->d_gidx, (size_t)cfg->n_cosmo * 2 * c->nb_max * sizeof(int)));
+    for (int k = 0; k < cfg->n_cosmo; ++k) {
+        const pino_growth& g = cfg->growth[k];
+        const int nb = index_bins(g.n);
+        const float L0 = (float)std::log2(g.D[0]);
+        const float S = (float)(nb / (std::log2(g.D[g.n - 1]) - (double)L0));
+        c->nb[k] = nb;
+        c->gL0[k] = L0;
+        c->gS[k] = S;
+        int* idx = c->d_gidx + (size_t)k * 2 * c->nb_max;
+        hipLaunchKernelGGL(k_growth_index, dim3((nb + 255) / 256), dim3(256), 0, 0, c->d_growth + (size_t)k * 3 * nk_max,
+                           g.n, nb, (double)L0, (double)S, idx, idx + c->nb_max);
+        PINO_HIP(c, hipGetLastError());
+    }
+    PINO_HIP(c, hipDeviceSynchronize());
+    {
+        std::vector<int> need(c->nb_max);
+        for (int k = 0; k < cfg->n_cosmo; ++k) {
+            PINO_HIP(c, hipMemcpy(need.data(), c->d_gidx + (size_t)k * 2 * c->nb_max + c->nb_max,
+                                  c->nb[k] * sizeof(int), hipMemcpyDeviceToHost));
+            int worst = 0;
+            for (int b = 0; b < c->nb[k]; ++b)
+                worst = std::max(worst, need[b]);
+            c->gok[k] = worst <= 2 ? 1 : 0;
+        }
+    }
+
     if (cfg->precision == PINO_SURROGATE) {
         c->certify_rtol = cfg->certify_rtol > 0.0 ? cfg->certify_rtol : 1e-7;
         const pino_status st = mlp_upload(c, cfg->mlp, cfg->mlp_bytes);
@@ -262,14 +325,20 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
     a.n = it.n;
     a.nk = c->nk[it.cosmo];
     a.growth = c->d_growth + (size_t)it.cosmo * 3 * c->nk_max;
+    a.gi.idx = c->d_gidx + (size_t)it.cosmo * 2 * c->nb_max;
+    a.gi.nb = c->nb[it.cosmo];
+    a.gi.L0 = c->gL0[it.cosmo];
+    a.gi.S = c->gS[it.cosmo];
+    a.gi.ok = c->gok[it.cosmo];
     a.radius = it.radius_index;
     a.reset = (flags & PINO_EVAL_RESET) ? 1u : 0u;
+    a.finalize = (flags & PINO_EVAL_FINALIZE) ? 1u : 0u;
     a.Fmax = it.Fmax;
     a.Rmax = it.Rmax;
     a.acoll = it.a_coll;
     const int block = 256;
     const int grid = grid_for(c, it.n, block);
-    size_t lds = 3 * (size_t)a.nk * sizeof(double);
+    size_t lds = growth_lds_bytes(a.nk, a.gi.nb);
 
     if (c->method == PINO_TABULATED) {
         // per-radius table: copy F into the interleaved table and rebuild the
@@ -328,6 +397,10 @@ pino_status pino_collapse_init(const pino_config* cfg, pino_ctx** out)
         g_init_error = why;
         return PINO_ERR_ARG;
     }
+    if (!lds_fits(cfg, why)) {
+        g_init_error = why;
+        return PINO_ERR_UNSUPPORTED;
+    }
     pino_ctx* c = new (std::nothrow) pino_ctx();
     if (!c) {
         g_init_error = "host allocation failed";
@@ -358,12 +431,12 @@ pino_status pino_collapse_eval(pino_ctx* ctx, const pino_item* items, int32_t n_
     if (ctx->broken) {
         return PINO_ERR_STATE;
     }
-    if (flags & ~(PINO_EVAL_RESET | PINO_EVAL_SYNC)) {
+    if (flags & ~(PINO_EVAL_RESET | PINO_EVAL_SYNC | PINO_EVAL_FINALIZE)) {
         ctx->err = "unknown flag bits";
         return PINO_ERR_ARG;
     }
     std::string why;
-    if (!validate_items(ctx, items, n_items, why)) {
+    if (!validate_items(ctx, items, n_items, flags, why)) {
         ctx->err = why;
         return PINO_ERR_ARG;
     }

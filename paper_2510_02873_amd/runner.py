@@ -43,16 +43,17 @@ class Collapse:
         return _abi.make_item(h, Fmax, Rmax, acoll, radius_index=radius_index, cosmo=cosmo,
                               sigma_R=sigma_R, table_F=table_F)
 
-    def eval(self, items, reset=False, sync=False, stream=None):
-        flags = (_abi.PINO_EVAL_RESET if reset else 0) | (_abi.PINO_EVAL_SYNC if sync else 0)
+    def eval(self, items, reset=False, sync=False, stream=None, finalize=False):
+        flags = ((_abi.PINO_EVAL_RESET if reset else 0) | (_abi.PINO_EVAL_SYNC if sync else 0)
+                 | (_abi.PINO_EVAL_FINALIZE if finalize else 0))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         _abi.pino_collapse_eval(self.ctx, list(items), flags, stream)
 
     def apply(self, h, radius_index, Fmax, Rmax, acoll=None, reset=False, cosmo=0, sigma_R=1.0,
-              table_F=None, sync=False, stream=None):
+              table_F=None, sync=False, stream=None, finalize=False):
         self.eval([self.item(h, Fmax, Rmax, acoll, radius_index, cosmo, sigma_R, table_F)], reset=reset,
-                  sync=sync, stream=stream)
+                  sync=sync, stream=stream, finalize=finalize)
 
     def close(self):
         if self.ctx is not None:

@@ -160,3 +160,24 @@ def test_c2_full_size_sampled(pkg, orc):
     ties = near_tie_mask([orc.points(s)[1] for s in sample])
     st = compare(ref, got, tie_mask=ties, label="C2 sample")
     print("C2 sample stats", st, flush=True)
+
+
+def test_finalize_equals_per_update(pkg):
+    """a_coll from the running maximum on the last radius equals a_coll
+    updated at every radius, bit for bit (a(D) is increasing)."""
+    cfg, slabs, a, D = c1_inputs()
+    with pkg.Collapse([(a, D)]) as col:
+        n = slabs[0].shape[1]
+        F1, R1, A1 = col.outputs(n)
+        F2, R2, A2 = col.outputs(n)
+        last = len(slabs) - 1
+        for r, h in enumerate(slabs):
+            hd = h.cuda()
+            col.apply(hd, r, F1, R1, A1, reset=(r == 0))
+            col.apply(hd, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last))
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F2) and torch.equal(R1, R2)
+        assert torch.equal(A1, A2)
+        with pytest.raises(pkg.PinoError) as e:
+            col.apply(slabs[0].cuda(), 0, F2, R2, None, finalize=True)
+        assert e.value.status == pkg.PINO_ERR_ARG
