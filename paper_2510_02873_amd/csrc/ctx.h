@@ -18,6 +18,7 @@ struct pino_ctx {
     int nk_max = 0;
     std::vector<int> nk;
     double* d_growth = nullptr;
+    float* d_growth32 = nullptr;  // FP32 copy for the mixed-precision path
 
     // per cosmology interval index of the growth knots: [idx | need], stride
     // 2 * nb_max ints; bin geometry and whether the two-compare bound holds

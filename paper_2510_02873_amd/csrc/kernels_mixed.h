@@ -1,0 +1,94 @@
+// Mixed-precision Classic kernel: FP32 Hessians (24 B per particle), FP32
+// eigenvalues with an FP64 branch for nearly repeated l1 ~ l2, the FP64
+// collapse root (FP32 estimate + FP64 Halley polish), and a(D) interpolated
+// in FP32 from FP32 copies of the growth knots.
+#pragma once
+
+#include "device_mixed.h"
+#include "kernels_fp64.h"
+
+namespace pino {
+
+__device__ __forceinline__ Hess32 load_h32(const ItemArgs& a, int64_t i)
+{
+    Hess32 h;
+    h.xx = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[0]) + i);
+    h.yy = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[1]) + i);
+    h.zz = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[2]) + i);
+    h.xy = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[3]) + i);
+    h.xz = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[4]) + i);
+    h.yz = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[5]) + i);
+    return h;
+}
+
+// FP32 growth knots and the interval index into LDS
+__device__ __forceinline__ GrowthIndex stage_growth32(float* lds, const float* __restrict__ g32, const ItemArgs& a)
+{
+    for (int k = threadIdx.x; k < 3 * a.nk; k += blockDim.x)
+        lds[k] = g32[k];
+    int* idx = reinterpret_cast<int*>(lds + 3 * a.nk);
+    for (int k = threadIdx.x; k < a.gi.nb; k += blockDim.x)
+        idx[k] = a.gi.idx[k];
+    GrowthIndex gi = a.gi;
+    gi.idx = idx;
+    return gi;
+}
+
+// same whole-line update as update_max, with a(D) in FP32
+__device__ __forceinline__ void update_max_f32(const ItemArgs& a, const float* g, const GrowthIndex& gi, int64_t i,
+                                               double F, double fm)
+{
+    const bool upd = F > fm;
+    const double fnew = upd ? F : fm;
+    const int32_t rm = a.reset ? -1 : a.Rmax[i];
+    a.Fmax[i] = fnew;
+    a.Rmax[i] = upd ? a.radius : rm;
+    if (a.acoll) {
+        if (a.finalize) {
+            a.acoll[i] = fnew > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew), gi) : kInf;
+        } else {
+            const double am = a.reset ? kInf : a.acoll[i];
+            a.acoll[i] = upd ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F), gi) : am;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_classic_mixed(ItemArgs a, const float* __restrict__ growth32)
+{
+    extern __shared__ double lds[];
+    float* g = reinterpret_cast<float*>(lds);
+    const GrowthIndex gi = stage_growth32(g, growth32, a);
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const Hess32 h = load_h32(a, i);
+        const double fm = a.reset ? 0.0 : a.Fmax[i];
+        float l1f, sf, ppf;
+        double l1, s, pp;
+        if (eig_top_f32(h, l1f, sf, ppf)) {
+            l1 = l1f;
+            s = sf;
+            pp = ppf;
+        } else {
+            eig_top(widen(h), l1, s, pp);
+        }
+        const double F = classic_F(l1, s, pp);
+        update_max_f32(a, g, gi, i, F, fm);
+    }
+}
+
+// FP32 copy of count doubles
+__global__ void __launch_bounds__(256) k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        dst[i] = (float)src[i];
+}
+
+// LDS bytes of stage_growth32
+__host__ __device__ inline size_t growth32_lds_bytes(int nk, int nb)
+{
+    return (((size_t)3 * nk * sizeof(float) + 7) / 8) * 8 + (((size_t)nb * sizeof(int) + 7) / 8) * 8;
+}
+
+}  // namespace pino

@@ -72,6 +72,10 @@ bool validate_config(const pino_config* cfg, std::string& why)
             return false;
         }
     }
+    if (cfg->precision == PINO_MIXED && cfg->method != PINO_CLASSIC) {
+        why = "mixed precision is implemented for the Classic method";
+        return false;
+    }
     if (cfg->method == PINO_TABULATED) {
         const pino_table_knots* t = cfg->table;
         if (!t || !t->x || !t->y || !t->delta || t->nx < 2 || t->ny < 2 || t->nd < 4) {
@@ -204,12 +208,13 @@ void free_all(pino_ctx* c)
 {
     if (!c)
         return;
-    void* ptrs[] = {c->d_growth, c->d_gidx, c->d_tknots, c->d_tab, c->d_dscaled, c->d_tmp, c->d_mlp, c->d_counters};
+    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tab, c->d_dscaled, c->d_tmp, c->d_mlp, c->d_counters};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
     c->d_growth = c->d_tknots = c->d_tab = c->d_dscaled = c->d_tmp = nullptr;
     c->d_gidx = nullptr;
+    c->d_growth32 = nullptr;
     c->d_mlp = nullptr;
     c->d_counters = nullptr;
 }
@@ -268,6 +273,15 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
         const int n = c->nk[k];
         hipLaunchKernelGGL(k_spline_build, dim3(1), dim3(64), 0, 0, g, n, g + n, (int64_t)0, 1, g + 2 * n,
                            (int64_t)0, 1, c->d_tmp + (size_t)k * nk_max, 1);
+        PINO_HIP(c, hipGetLastError());
+    }
+
+    // FP32 copy of the growth knots for the mixed-precision path
+    if (cfg->precision == PINO_MIXED) {
+        const int64_t count = (int64_t)cfg->n_cosmo * 3 * nk_max;
+        PINO_HIP(c, hipMalloc((void**)&c->d_growth32, count * sizeof(float)));
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, 0, c->d_growth,
+                           c->d_growth32, count);
         PINO_HIP(c, hipGetLastError());
     }
 

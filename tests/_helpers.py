@@ -37,6 +37,8 @@ def run_gpu_radii(col, slabs, acoll=True, sigmas=None, tables=None, cosmo=0):
 def near_tie_mask(F_per_radius):
     """Particles whose two largest per-radius F are within 1e-12 relative."""
     Fs = np.sort(np.asarray(F_per_radius), axis=0)
+    if Fs.shape[0] < 2:
+        return np.zeros(Fs.shape[1], dtype=bool)
     top, second = Fs[-1], Fs[-2]
     return (top > 0) & (np.abs(top - second) <= 1e-12 * top)
 
