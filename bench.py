@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle·radius collapse evals/s, plain FP64 vs surrogate+certify, at ≤1e-6 rel err"
+PROFILE = os.path.join(ROOT, "profiles", "k_classic_f64_256cube_25radii.txt")
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
@@ -43,14 +44,95 @@ def algorithmic_bytes(n, updates, reset, finalize):
     return b + (n * 8 if finalize else 0)
 
 
+def _time_steps(step, steps, stream):
+    import torch
+    step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, steps):
+    """Secondary rates on the same resident fields: mixed precision (FP32
+    copies of the Hessians) and the Tabulated method (64 x 64 x 128 tables
+    filled per radius by the library's Classic kernel on the table's sample
+    points).  Each reports evals/s and the agreement of its outputs with the
+    plain FP64 run just timed."""
+    import numpy as np
+    import torch
+
+    import synth
+
+    out = {}
+    last = len(radii) - 1
+    F64, R64, A64 = Fmax.clone(), Rmax.clone(), ac.clone()
+
+    # mixed precision
+    s32 = [h.to(torch.float32) for h in slabs]
+    mcol = P.Collapse([(a, D)], precision=P.PINO_MIXED)
+    Fm, Rm, Am = mcol.outputs(n)
+    mitems = [mcol.item(s32[r], Fm, Rm, Am if r == last else None, radius_index=r) for r in range(len(radii))]
+
+    def mstep():
+        for r, it in enumerate(mitems):
+            mcol.eval([it], reset=(r == 0), finalize=(r == last), stream=stream)
+
+    ms = _time_steps(mstep, steps, stream)
+    big = F64 > 1e-6
+    rel = ((1 / Fm[big] - 1 / F64[big]).abs() * F64[big]).cpu().numpy()
+    out["mixed"] = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s", "ms_per_step": round(ms, 4),
+                    "dtype": "f32 inputs/eigen/interp, f64 root", "workload": f"same {n_side}^3 x {len(radii)} fields",
+                    "rel_Dc_vs_fp64": {"max": float(rel.max()), "p99.9": float(np.percentile(rel, 99.9)),
+                                       "mean": float(rel.mean())},
+                    "index_mismatch_frac": float((Rm != R64).double().mean().item())}
+    mcol.close()
+    del s32
+
+    # Tabulated: fill each radius' table with the Classic kernel on the
+    # table's sample points (diagonal Hessians), then interpolate
+    knots = synth.table_knots(1.0, 64, 64, 128)
+    sig = [synth.grid_sigma_gauss(n_side, cfg["box"], R) for R in radii]
+    tabs = []
+    for sR in sig:
+        grid = torch.from_numpy(synth.table_grid_hessians(*(np.asarray(k) * sR for k in knots))).cuda()
+        Ft, Rt, _ = col.outputs(grid.shape[1])
+        col.apply(grid, 0, Ft, Rt, None, reset=True, stream=stream)
+        tabs.append(Ft)
+    tcol = P.Collapse([(a, D)], method=P.PINO_TABULATED, table_knots=knots)
+    Ft, Rt, At = tcol.outputs(n)
+    titems = [tcol.item(slabs[r], Ft, Rt, At if r == last else None, radius_index=r, sigma_R=sig[r],
+                        table_F=tabs[r]) for r in range(len(radii))]
+
+    def tstep():
+        for r, it in enumerate(titems):
+            tcol.eval([it], reset=(r == 0), finalize=(r == last), stream=stream)
+
+    ms = _time_steps(tstep, steps, stream)
+    both = (F64 > 0.05) & (Ft > 0)
+    relt = ((Ft[both] - F64[both]).abs() / F64[both]).cpu().numpy()
+    out["tabulated"] = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s",
+                        "ms_per_step": round(ms, 4), "table": "64x64x128 per radius, rebuilt on device",
+                        "rel_F_vs_classic_median": float(np.median(relt))}
+    tcol.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 18, help="particles in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="particles in the oracle sample")
     ap.add_argument("--n-side", type=int, default=None, help="override the grid side (testing only)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary measurements (mixed precision, Tabulated) on the same fields")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB device-to-device once, so HBM "
                          "counters can be scaled against a transfer of known size")
@@ -156,11 +238,23 @@ def main():
     mean_launch_ms = float(launch_ms.mean())
     mean_bytes = float(np.mean(bytes_per_launch))
     achieved_gbs = mean_bytes / (mean_launch_ms * 1e-3) / 1e9
+    # measured HBM traffic per launch (scaled rocprofv3 counters), valid only
+    # while the kernel sources are the ones that were profiled
+    from paper_2510_02873_amd.profiling import read_traffic, source_digest
+    traffic, digest = read_traffic(PROFILE)
+    if digest != source_digest():
+        traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                "traffic_unit": "GB per launch",
                 "kernel": "k_classic_f64", "mean_launch_us": round(mean_launch_ms * 1e3, 2),
                 "bytes_per_launch": int(mean_bytes), "update_fraction": round(
                     float(np.mean([u / n for u in updates[1:]])), 4)}
+
+    extras = {}
+    if not args.no_extras:
+        extras = measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, args.steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -168,28 +262,31 @@ def main():
         rng = np.random.default_rng(12345)
         m = min(args.cpu_sample, n)
         idx = torch.from_numpy(np.sort(rng.choice(n, size=m, replace=False))).to(dev)
-        sample = [s[:, idx].cpu().numpy() for s in slabs]
         g = oracle.Growth(a, D)
         log(f"cpu baseline: oracle on {m} particles x {len(radii)} radii, {oracle.threads()} threads")
-        c0 = time.perf_counter()
-        ref = oracle.collapse(sample, g)
-        dt = time.perf_counter() - c0
+        rF, rR, rA = np.zeros(m), np.full(m, -1, np.int32), np.full(m, np.inf)
+        dt = 0.0
+        for r in range(len(radii)):
+            sample = slabs[r][:, idx].cpu().numpy()       # gathered outside the timed call
+            c0 = time.perf_counter()
+            oracle.update_radius(sample, r, g, rF, rR, rA, reset=(r == 0))
+            dt += time.perf_counter() - c0
         cpu = {"value": round(m * len(radii) / dt, 1), "unit": "evals/s", "cores": oracle.threads(),
                "kind": "oracle",
-               "sample": f"{m} seeded-random particles of the same 256^3 fields x all {len(radii)} radii "
-                         f"({dt:.1f} s)"}
+               "sample": f"{m} seeded-random particles of the same {n_side}^3 fields x all {len(radii)} radii "
+                         f"({dt:.1f} s of oracle time)"}
         # the sampled particles also serve as a parity spot check of this run
         got_F = Fmax[idx].cpu().numpy()
         got_R = Rmax[idx].cpu().numpy()
         got_a = ac[idx].cpu().numpy()
-        big = ref[0] >= 1e-6
-        rel = float(np.max(np.abs(1 / got_F[big] - 1 / ref[0][big]) * ref[0][big])) if big.any() else 0.0
-        fin = np.isfinite(ref[2])
-        rel_a = float(np.max(np.abs(got_a[fin] - ref[2][fin]) / ref[2][fin])) if fin.any() else 0.0
+        big = rF >= 1e-6
+        rel = float(np.max(np.abs(1 / got_F[big] - 1 / rF[big]) * rF[big])) if big.any() else 0.0
+        fin = np.isfinite(rA)
+        rel_a = float(np.max(np.abs(got_a[fin] - rA[fin]) / rA[fin])) if fin.any() else 0.0
         cpu["parity_max_rel_Dc"] = rel
         cpu["parity_max_rel_acoll"] = rel_a
-        cpu["parity_index_mismatches"] = int(np.sum(got_R != ref[1]))
-        log(f"cpu baseline {cpu['value']:.3e} evals/s; sample parity max rel D_c {rel:.2e}")
+        cpu["parity_index_mismatches"] = int(np.sum(got_R != rR))
+        log(f"cpu baseline {cpu['value']:.3e} evals/s; sample parity max rel D_c {rel:.2e} a_coll {rel_a:.2e}")
 
     out = {
         "metric": METRIC,
@@ -210,6 +307,7 @@ def main():
                    "precision": "fp64"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
     col.close()
