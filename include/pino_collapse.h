@@ -85,11 +85,13 @@ typedef enum { PINO_FP64 = 0, PINO_MIXED = 1, PINO_SURROGATE = 2 } pino_precisio
 
 /* One linear growth table: n >= 4 knots, a and D strictly increasing and
  * finite (host pointers, copied by init).  The library builds the natural
- * spline a(D) from it on the device. */
+ * spline a(D) from it on the device.  omega_m is the matter density of the
+ * cosmology (an input of the surrogate network; otherwise unused). */
 typedef struct {
     int32_t n;
     const double *a;
     const double *D;
+    double omega_m;
 } pino_growth;
 
 /* Knots of the collapse table in units of sigma(R): each item's sigma_R

@@ -28,7 +28,7 @@ _D = ctypes.POINTER(ctypes.c_double)
 
 
 class pino_growth(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("a", _D), ("D", _D)]
+    _fields_ = [("n", ctypes.c_int32), ("a", _D), ("D", _D), ("omega_m", ctypes.c_double)]
 
 
 class pino_table_knots(ctypes.Structure):
@@ -103,10 +103,11 @@ class Config:
                  table_knots=None, mlp_blob=None, certify_rtol=0.0, abi_version=PINO_ABI_VERSION):
         self._keep = []
         arr = (pino_growth * max(1, len(growth_tables)))()
-        for k, (a, D) in enumerate(growth_tables):
-            a, D = _host_f64(a), _host_f64(D)
+        for k, tab in enumerate(growth_tables):
+            a, D = _host_f64(tab[0]), _host_f64(tab[1])
+            om = float(tab[2]) if len(tab) > 2 else 0.3
             self._keep += [a, D]
-            arr[k] = pino_growth(len(a), a.ctypes.data_as(_D), D.ctypes.data_as(_D))
+            arr[k] = pino_growth(len(a), a.ctypes.data_as(_D), D.ctypes.data_as(_D), om)
         self._growth = arr
         self.c = pino_config()
         self.c.abi_version = abi_version
@@ -166,3 +167,111 @@ def pino_collapse_eval(ctx, items, flags=0, stream=None):
     if stream is not None and hasattr(stream, "cuda_stream"):
         handle = stream.cuda_stream
     _check(lib().pino_collapse_eval(ctx, arr, n, flags, handle), ctx)
+
+
+# ---------------------------------------------------------------------------
+# include/pino_mlp.h
+# ---------------------------------------------------------------------------
+PINO_MLP_PARAMS = 8705
+_F = ctypes.POINTER(ctypes.c_float)
+_mlp_bound = False
+
+
+def _bind_mlp():
+    global _mlp_bound
+    if _mlp_bound:
+        return lib()
+    L = lib()
+    c_p, c_i64, c_f = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float
+    L.pino_mlp_create.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]
+    L.pino_mlp_set_params.argtypes = [c_p, _F]
+    L.pino_mlp_get_params.argtypes = [c_p, _F]
+    L.pino_mlp_forward.argtypes = [c_p, c_p, c_p, c_i64, c_p]
+    L.pino_mlp_grad.argtypes = [c_p, c_p, c_p, c_i64, c_p, c_p, c_p]
+    L.pino_mlp_adam.argtypes = [c_p, c_p, c_f, c_f, c_f, c_f, c_p]
+    L.pino_mlp_train_step.argtypes = [c_p, c_p, c_p, c_i64, c_f, c_p, c_p]
+    L.pino_mlp_export.argtypes = [c_p, c_p, c_i64, ctypes.POINTER(c_i64)]
+    L.pino_mlp_free.argtypes = [c_p]
+    L.pino_collapse_features.argtypes = [c_p, ctypes.POINTER(pino_item), c_p, c_p, c_p]
+    L.pino_collapse_predict.argtypes = [c_p, c_p, c_p, c_i64, c_p]
+    L.pino_collapse_surrogate_stats.argtypes = [c_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
+                                                ctypes.POINTER(c_i64), ctypes.c_int32]
+    for name in ("pino_mlp_create", "pino_mlp_set_params", "pino_mlp_get_params", "pino_mlp_forward",
+                 "pino_mlp_grad", "pino_mlp_adam", "pino_mlp_train_step", "pino_mlp_export", "pino_mlp_free",
+                 "pino_collapse_features", "pino_collapse_predict", "pino_collapse_surrogate_stats"):
+        getattr(L, name).restype = ctypes.c_int
+    _mlp_bound = True
+    return L
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return stream
+
+
+def pino_mlp_create(device=0, seed=0):
+    out = ctypes.c_void_p()
+    _check(_bind_mlp().pino_mlp_create(device, seed, ctypes.byref(out)))
+    return out.value
+
+
+def pino_mlp_set_params(m, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == PINO_MLP_PARAMS
+    _check(_bind_mlp().pino_mlp_set_params(m, p.ctypes.data_as(_F)))
+
+
+def pino_mlp_get_params(m):
+    p = np.empty(PINO_MLP_PARAMS, dtype=np.float32)
+    _check(_bind_mlp().pino_mlp_get_params(m, p.ctypes.data_as(_F)))
+    return p
+
+
+def pino_mlp_forward(m, x, y, stream=None):
+    _check(_bind_mlp().pino_mlp_forward(m, _ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+
+
+def pino_mlp_grad(m, x, w, grad, loss=None, stream=None):
+    _check(_bind_mlp().pino_mlp_grad(m, _ptr(x), _ptr(w), x.shape[0], _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def pino_mlp_adam(m, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_bind_mlp().pino_mlp_adam(m, _ptr(grad), lr, beta1, beta2, eps, _stream(stream)))
+
+
+def pino_mlp_train_step(m, x, w, lr, loss=None, stream=None):
+    _check(_bind_mlp().pino_mlp_train_step(m, _ptr(x), _ptr(w), x.shape[0], lr, _ptr(loss), _stream(stream)))
+
+
+def pino_mlp_export(m):
+    L = _bind_mlp()
+    need = ctypes.c_int64()
+    _check(L.pino_mlp_export(m, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(L.pino_mlp_export(m, buf, need.value, ctypes.byref(need)))
+    return buf.raw
+
+
+def pino_mlp_free(m):
+    if m is not None:
+        _check(_bind_mlp().pino_mlp_free(m))
+
+
+def pino_collapse_features(ctx, item, x, w=None, stream=None):
+    _check(_bind_mlp().pino_collapse_features(ctx, ctypes.byref(item), _ptr(x), _ptr(w), _stream(stream)), ctx)
+
+
+def pino_collapse_predict(ctx, x, y, stream=None):
+    _check(_bind_mlp().pino_collapse_predict(ctx, _ptr(x), _ptr(y), x.shape[0], _stream(stream)), ctx)
+
+
+def pino_collapse_surrogate_stats(ctx, reset=False):
+    c, f, g = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_bind_mlp().pino_collapse_surrogate_stats(ctx, ctypes.byref(c), ctypes.byref(f), ctypes.byref(g),
+                                                     int(bool(reset))), ctx)
+    return {"certified": c.value, "fallback": f.value, "gated": g.value}

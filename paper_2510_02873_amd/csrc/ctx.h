@@ -38,10 +38,12 @@ struct pino_ctx {
     // spline-build scratch
     double* d_tmp = nullptr;
 
-    // surrogate network (device copy of the weight blob)
+    // surrogate network: BF16 weight fragments, certificate tolerance,
+    // counters (certified, fallback, gated), Omega_m per cosmology
     void* d_mlp = nullptr;
-    double certify_rtol = 1e-7;
+    double certify_rtol = 5e-7;
     int64_t* d_counters = nullptr;
+    std::vector<double> omega;
 
     bool broken = false;
     std::string err = "no error";

@@ -1,0 +1,126 @@
+// Surrogate + certify collapse kernel, network-input and prediction kernels.
+#pragma once
+
+#include "kernels_fp64.h"
+#include "kernels_mixed.h"
+#include "surrogate.h"
+
+namespace pino {
+
+// The Hessian of an item as FP64 (FP64 inputs) or widened FP32 inputs.
+__device__ __forceinline__ Hess64 load_h(const ItemArgs& a, int64_t i, bool f32)
+{
+    return f32 ? widen(load_h32(a, i)) : load_h64(a, i);
+}
+
+// Per particle: FP64 eigenvalues of the FP32 Hessian, the BF16 network's
+// prediction, one certified FP64 Newton step, or the full solve.  The loop is
+// wave-uniform (all 64 lanes run the network together); lanes past the end
+// compute on zeros and store nothing.  counters: certified, fallback, gated
+// (wave totals added once per wave).
+__global__ void __launch_bounds__(256) k_surrogate(ItemArgs a, const NetFrags* __restrict__ net, double sigma,
+                                                  double omega_m, double rtol,
+                                                  unsigned long long* __restrict__ counters)
+{
+    extern __shared__ double lds[];
+    const GrowthIndex gi = stage_growth(lds, a);
+    NetFrags* N = reinterpret_cast<NetFrags*>(lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double));
+    {
+        const int4* src = reinterpret_cast<const int4*>(net);
+        int4* dst = reinterpret_cast<int4*>(N);
+        for (int k = threadIdx.x; k < (int)(sizeof(NetFrags) / sizeof(int4)); k += blockDim.x)
+            dst[k] = src[k];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long ncert = 0, nfall = 0, ngate = 0;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < a.n; base += stride) {
+        const int64_t i = base + lane;
+        const bool valid = i < a.n;
+        Hess64 h{};
+        double fm = 0.0;
+        if (valid) {
+            h = widen(load_h32(a, i));
+            fm = a.reset ? 0.0 : a.Fmax[i];
+        }
+        double l1, s, pp;
+        eig_top(h, l1, s, pp);
+        float x[4];
+        const bool consult = net_inputs(l1, s, pp, sigma, omega_m, x) && valid;
+        if (!consult)
+            x[0] = x[1] = x[2] = x[3] = 0.0f;
+        const float y = net_bf16(*N, x);
+        double F = 0.0;
+        bool cert = false;
+        if (l1 > 0.0) {
+            const CubicU k = lpt_cubic(l1, s, pp, rcp2(l1));
+            double u1;
+            if (consult && certify(k, (double)y, rtol, u1)) {
+                F = l1 * rcp2(u1);
+                cert = true;
+            } else {
+                F = classic_F(l1, s, pp);
+            }
+        }
+        ncert += __popcll(__ballot(valid && cert));
+        nfall += __popcll(__ballot(valid && consult && !cert));
+        ngate += __popcll(__ballot(valid && !consult));
+        if (valid)
+            update_max(a, lds, gi, i, F, fm);
+    }
+    if (lane == 0 && counters) {
+        atomicAdd(counters + 0, ncert);
+        atomicAdd(counters + 1, nfall);
+        atomicAdd(counters + 2, ngate);
+    }
+}
+
+// Network inputs x [n][4] and target w = 1/(l1 D_c) (0 where the network is
+// not consulted) from the full FP64 solve.
+__global__ void __launch_bounds__(256) k_features(ItemArgs a, bool f32, double sigma, double omega_m,
+                                                 float* __restrict__ X, float* __restrict__ W)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n)
+        return;
+    const Hess64 h = load_h(a, i, f32);
+    double l1, s, pp;
+    eig_top(h, l1, s, pp);
+    float x[4];
+    const bool consult = net_inputs(l1, s, pp, sigma, omega_m, x);
+    for (int k = 0; k < 4; ++k)
+        X[i * 4 + k] = x[k];
+    if (W) {
+        const double F = consult ? classic_F(l1, s, pp) : 0.0;
+        W[i] = F > 0.0 ? (float)(F / l1) : 0.0f;
+    }
+}
+
+// The BF16 network on given inputs (wave-uniform loop)
+__global__ void __launch_bounds__(256) k_predict(const NetFrags* __restrict__ net, const float* __restrict__ X,
+                                                float* __restrict__ Y, int64_t n)
+{
+    __shared__ NetFrags N;
+    {
+        const int4* src = reinterpret_cast<const int4*>(net);
+        int4* dst = reinterpret_cast<int4*>(&N);
+        for (int k = threadIdx.x; k < (int)(sizeof(NetFrags) / sizeof(int4)); k += blockDim.x)
+            dst[k] = src[k];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        const int64_t i = base + lane;
+        float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (i < n)
+            for (int k = 0; k < 4; ++k)
+                x[k] = X[i * 4 + k];
+        const float y = net_bf16(N, x);
+        if (i < n)
+            Y[i] = y;
+    }
+}
+
+}  // namespace pino

@@ -1,4 +1,4 @@
-// Launchers of the reduced-precision and surrogate variants.
+// Launcher of the mixed-precision variant.
 #pragma once
 
 #include "ctx.h"
@@ -7,17 +7,7 @@
 
 namespace {
 
-inline bool mlp_blob_valid(const void*, int64_t, std::string& why)
-{
-    why = "not available";
-    return false;
-}
 
-inline pino_status mlp_upload(pino_ctx* c, const void*, int64_t)
-{
-    c->err = "surrogate not available";
-    return PINO_ERR_UNSUPPORTED;
-}
 
 inline pino_status launch_mixed(pino_ctx* c, const pino_item& it, const pino::ItemArgs& a, uint32_t, hipStream_t st,
                                 int grid, int block)
@@ -38,11 +28,5 @@ inline pino_status launch_mixed(pino_ctx* c, const pino_item& it, const pino::It
     return PINO_OK;
 }
 
-inline pino_status launch_surrogate(pino_ctx* c, const pino_item&, const pino::ItemArgs&, uint32_t, hipStream_t,
-                                    int, int)
-{
-    c->err = "surrogate not available";
-    return PINO_ERR_UNSUPPORTED;
-}
 
 }  // namespace

@@ -13,6 +13,7 @@
 #include "ctx.h"
 #include "kernels_fp64.h"
 #include "launch_ext.h"
+#include "mlp_api.h"
 
 using namespace pino;
 
@@ -67,10 +68,18 @@ bool validate_config(const pino_config* cfg, std::string& why)
             why = "growth table " + std::to_string(c) + ": need 4 <= n <= 2048 and non-NULL a, D";
             return false;
         }
+        if (!std::isfinite(g.omega_m)) {
+            why = "growth table " + std::to_string(c) + ": omega_m must be finite";
+            return false;
+        }
         if (!strictly_increasing(g.a, g.n) || !strictly_increasing(g.D, g.n)) {
             why = "growth table " + std::to_string(c) + ": a and D must be finite and strictly increasing";
             return false;
         }
+    }
+    if (cfg->certify_rtol < 0.0 || !std::isfinite(cfg->certify_rtol)) {
+        why = "certify_rtol must be finite and >= 0";
+        return false;
     }
     if (cfg->precision == PINO_MIXED && cfg->method != PINO_CLASSIC) {
         why = "mixed precision is implemented for the Classic method";
@@ -237,6 +246,9 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
         nk_max = std::max(nk_max, (int)cfg->growth[k].n);
     c->nk_max = nk_max;
     c->nk.resize(cfg->n_cosmo);
+    c->omega.resize(cfg->n_cosmo);
+    for (int k = 0; k < cfg->n_cosmo; ++k)
+        c->omega[k] = cfg->growth[k].omega_m;
     std::vector<double> host((size_t)cfg->n_cosmo * 3 * nk_max, 0.0);
     for (int k = 0; k < cfg->n_cosmo; ++k) {
         const pino_growth& g = cfg->growth[k];
@@ -320,7 +332,7 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
     }
 
     if (cfg->precision == PINO_SURROGATE) {
-        c->certify_rtol = cfg->certify_rtol > 0.0 ? cfg->certify_rtol : 1e-7;
+        c->certify_rtol = cfg->certify_rtol > 0.0 ? cfg->certify_rtol : 5e-7;
         const pino_status st = mlp_upload(c, cfg->mlp, cfg->mlp_bytes);
         if (st != PINO_OK)
             return st;
@@ -485,6 +497,97 @@ const char* pino_collapse_last_error(const pino_ctx* ctx)
     if (!ctx)
         return g_init_error.c_str();
     return ctx->err.c_str();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+pino_status pino_collapse_features(pino_ctx* ctx, const pino_item* item, float* x, float* w, void* hip_stream)
+{
+    if (!ctx || !item || (item->n > 0 && !x)) {
+        g_init_error = "ctx, item and x must be non-NULL";
+        return PINO_ERR_ARG;
+    }
+    if (ctx->broken)
+        return PINO_ERR_STATE;
+    std::string why;
+    pino_item it = *item;
+    double* dummyF = reinterpret_cast<double*>(x);  // outputs are not written; validation wants them non-NULL
+    if (!it.Fmax)
+        it.Fmax = dummyF;
+    if (!it.Rmax)
+        it.Rmax = reinterpret_cast<int32_t*>(x);
+    if (!validate_items(ctx, &it, 1, 0, why)) {
+        ctx->err = why;
+        return PINO_ERR_ARG;
+    }
+    if (!(std::isfinite(it.sigma_R) && it.sigma_R > 0.0)) {
+        ctx->err = "sigma_R must be finite and > 0";
+        return PINO_ERR_ARG;
+    }
+    if (it.n == 0)
+        return PINO_OK;
+    PINO_HIP(ctx, hipSetDevice(ctx->device));
+    ItemArgs a{};
+    for (int k = 0; k < 6; ++k)
+        a.h[k] = static_cast<const double*>(it.h[k]);
+    a.n = it.n;
+    const bool f32 = ctx->precision != PINO_FP64;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((it.n + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), a, f32, it.sigma_R, ctx->omega[it.cosmo], x, w);
+    PINO_HIP(ctx, hipGetLastError());
+    return PINO_OK;
+}
+
+pino_status pino_collapse_predict(pino_ctx* ctx, const float* x, float* y, int64_t n, void* hip_stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!x || !y))) {
+        g_init_error = "bad arguments";
+        return PINO_ERR_ARG;
+    }
+    if (ctx->broken)
+        return PINO_ERR_STATE;
+    if (ctx->precision != PINO_SURROGATE) {
+        ctx->err = "pino_collapse_predict needs a PINO_SURROGATE context";
+        return PINO_ERR_ARG;
+    }
+    if (n == 0)
+        return PINO_OK;
+    PINO_HIP(ctx, hipSetDevice(ctx->device));
+    const int grid = grid_for(ctx, n, 256);
+    hipLaunchKernelGGL(k_predict, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                       static_cast<const NetFrags*>(ctx->d_mlp), x, y, n);
+    PINO_HIP(ctx, hipGetLastError());
+    return PINO_OK;
+}
+
+pino_status pino_collapse_surrogate_stats(pino_ctx* ctx, int64_t* certified, int64_t* fallback, int64_t* gated,
+                                          int32_t reset)
+{
+    if (!ctx) {
+        g_init_error = "ctx is NULL";
+        return PINO_ERR_ARG;
+    }
+    if (ctx->broken)
+        return PINO_ERR_STATE;
+    if (ctx->precision != PINO_SURROGATE || !ctx->d_counters) {
+        ctx->err = "surrogate statistics need a PINO_SURROGATE context";
+        return PINO_ERR_ARG;
+    }
+    PINO_HIP(ctx, hipSetDevice(ctx->device));
+    PINO_HIP(ctx, hipDeviceSynchronize());
+    int64_t v[4];
+    PINO_HIP(ctx, hipMemcpy(v, ctx->d_counters, sizeof(v), hipMemcpyDeviceToHost));
+    if (certified)
+        *certified = v[0];
+    if (fallback)
+        *fallback = v[1];
+    if (gated)
+        *gated = v[2];
+    if (reset)
+        PINO_HIP(ctx, hipMemset(ctx->d_counters, 0, sizeof(v)));
+    return PINO_OK;
 }
 
 }  // extern "C"

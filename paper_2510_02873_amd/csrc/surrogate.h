@@ -1,0 +1,375 @@
+// Learned surrogate of the Classic collapse: network inputs, FP32 training
+// kernels (forward, backward, Adam), the BF16 MFMA inference used by the
+// collapse kernel, and the FP64 Newton certificate.
+#pragma once
+
+#include "device_collapse.h"
+
+namespace pino {
+
+// ---------------------------------------------------------------------------
+// Parameter layout (FP32): W1[64][4], b1[64], W2[64][64], b2[64],
+// W3[64][64], b3[64], W4[64], b4.
+// ---------------------------------------------------------------------------
+constexpr int kH = 64;
+constexpr int kIn = 4;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kH * kIn;
+constexpr int kOffW2 = kOffB1 + kH;
+constexpr int kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH;
+constexpr int kOffB3 = kOffW3 + kH * kH;
+constexpr int kOffW4 = kOffB3 + kH;
+constexpr int kOffB4 = kOffW4 + kH;
+constexpr int kNParam = kOffB4 + 1;  // 8705
+
+// the network is consulted only where l1 >= kGate * max|l| (and l1 > 0)
+constexpr double kGate = 0.1;
+
+// Network inputs from l1, s = l2 + l3, pp = l2 l3: sorted eigenvalues over
+// sigma and the centred matter density.  Returns whether the network is
+// consulted (l1 > 0 and l1 >= kGate * |l3|, l3 the smallest eigenvalue).
+__host__ __device__ __forceinline__ bool net_inputs(double l1, double s, double pp, double sigma, double omega_m,
+                                                    float x[4])
+{
+    const double disc = fmax(0.25 * s * s - pp, 0.0);
+    const double rt = sqrt(disc);
+    const double l2 = 0.5 * s + rt;
+    const double l3 = 0.5 * s - rt;
+    const double is = 1.0 / sigma;
+    x[0] = (float)(l1 * is);
+    x[1] = (float)(l2 * is);
+    x[2] = (float)(l3 * is);
+    x[3] = (float)((omega_m - 0.3) * 20.0);
+    return l1 > 0.0 && l1 >= kGate * fabs(l3);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 training kernels.  A block of kTB samples (one per lane) keeps the
+// block's activations and back-propagated errors in LDS; the parameters are
+// read at lane-uniform addresses from global memory.  Per-sample forward and
+// backward passes run one sample per lane; weight gradients are sums over the
+// block's samples, each lane owning two output rows, written as a per-block
+// partial that k_mlp_reduce sums in fixed order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int kTB = 32;
+constexpr int kLd = kTB + 1;  // padded row stride of [unit][sample] arrays
+
+__host__ __device__ inline size_t mlp_grad_lds_bytes()
+{
+    return sizeof(float) * ((size_t)6 * kH * kLd + kIn * kLd + 2 * kTB);
+}
+
+__global__ void __launch_bounds__(kTB) k_mlp_grad_block(const float* __restrict__ p, const float* __restrict__ X,
+                                                       const float* __restrict__ Wt, int64_t n,
+                                                       float* __restrict__ partial)
+{
+    extern __shared__ float sm[];
+    float* h1 = sm;
+    float* h2 = h1 + kH * kLd;
+    float* h3 = h2 + kH * kLd;
+    float* d1 = h3 + kH * kLd;
+    float* d2 = d1 + kH * kLd;
+    float* d3 = d2 + kH * kLd;
+    float* xs = d3 + kH * kLd;
+    float* dys = xs + kIn * kLd;
+    float* ls = dys + kTB;
+    const int t = threadIdx.x;
+    const int64_t smp = (int64_t)blockIdx.x * kTB + t;
+    const bool valid = smp < n;
+    const float w = valid ? Wt[smp] : 0.0f;
+    const bool use = valid && w > 0.0f;
+    for (int k = 0; k < kIn; ++k)
+        xs[k * kLd + t] = valid ? X[smp * kIn + k] : 0.0f;
+    const float* W1 = p + kOffW1;
+    const float* W2 = p + kOffW2;
+    const float* W3 = p + kOffW3;
+    // forward
+    for (int o = 0; o < kH; ++o) {
+        float z = p[kOffB1 + o];
+        for (int k = 0; k < kIn; ++k)
+            z += W1[o * kIn + k] * xs[k * kLd + t];
+        h1[o * kLd + t] = fmaxf(z, 0.0f);
+    }
+    for (int o = 0; o < kH; ++o) {
+        float z = p[kOffB2 + o];
+        for (int k = 0; k < kH; ++k)
+            z += W2[o * kH + k] * h1[k * kLd + t];
+        h2[o * kLd + t] = fmaxf(z, 0.0f);
+    }
+    float y = p[kOffB4];
+    for (int o = 0; o < kH; ++o) {
+        float z = p[kOffB3 + o];
+        for (int k = 0; k < kH; ++k)
+            z += W3[o * kH + k] * h2[k * kLd + t];
+        const float hv = fmaxf(z, 0.0f);
+        h3[o * kLd + t] = hv;
+        y += p[kOffW4 + o] * hv;
+    }
+    // loss ((y - w)/w)^2 averaged over all n samples; dL/dy
+    const float r = use ? (y - w) / w : 0.0f;
+    const float dy = use ? 2.0f * r / (w * (float)n) : 0.0f;
+    dys[t] = dy;
+    ls[t] = r * r;
+    // backward through the hidden layers, per sample
+    for (int o = 0; o < kH; ++o)
+        d3[o * kLd + t] = h3[o * kLd + t] > 0.0f ? dy * p[kOffW4 + o] : 0.0f;
+    for (int k = 0; k < kH; ++k) {
+        float g = 0.0f;
+        for (int o = 0; o < kH; ++o)
+            g += W3[o * kH + k] * d3[o * kLd + t];
+        d2[k * kLd + t] = h2[k * kLd + t] > 0.0f ? g : 0.0f;
+    }
+    for (int k = 0; k < kH; ++k) {
+        float g = 0.0f;
+        for (int o = 0; o < kH; ++o)
+            g += W2[o * kH + k] * d2[o * kLd + t];
+        d1[k * kLd + t] = h1[k * kLd + t] > 0.0f ? g : 0.0f;
+    }
+    __syncthreads();
+    // weight gradients: lane t owns output rows t and t + kTB of every layer
+    float* out = partial + (int64_t)blockIdx.x * (kNParam + 1);
+    for (int o = t; o < kH; o += kTB) {
+        for (int k = 0; k < kIn; ++k) {
+            float g = 0.0f;
+            for (int s = 0; s < kTB; ++s)
+                g += d1[o * kLd + s] * xs[k * kLd + s];
+            out[kOffW1 + o * kIn + k] = g;
+        }
+        float gb1 = 0.0f, gb2 = 0.0f, gb3 = 0.0f, gw4 = 0.0f;
+        for (int s = 0; s < kTB; ++s) {
+            gb1 += d1[o * kLd + s];
+            gb2 += d2[o * kLd + s];
+            gb3 += d3[o * kLd + s];
+            gw4 += dys[s] * h3[o * kLd + s];
+        }
+        out[kOffB1 + o] = gb1;
+        out[kOffB2 + o] = gb2;
+        out[kOffB3 + o] = gb3;
+        out[kOffW4 + o] = gw4;
+        for (int k = 0; k < kH; ++k) {
+            float g2 = 0.0f, g3 = 0.0f;
+            for (int s = 0; s < kTB; ++s) {
+                g2 += d2[o * kLd + s] * h1[k * kLd + s];
+                g3 += d3[o * kLd + s] * h2[k * kLd + s];
+            }
+            out[kOffW2 + o * kH + k] = g2;
+            out[kOffW3 + o * kH + k] = g3;
+        }
+    }
+    if (t == 0) {
+        float gb4 = 0.0f, lsum = 0.0f;
+        for (int s = 0; s < kTB; ++s) {
+            gb4 += dys[s];
+            lsum += ls[s];
+        }
+        out[kOffB4] = gb4;
+        out[kNParam] = lsum;
+    }
+}
+
+// grad[j] = sum over blocks of partial[b][j] (fixed order); loss likewise / n
+__global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ partial, int nblk, int64_t n,
+                                                   float* __restrict__ grad, float* __restrict__ loss)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > kNParam)
+        return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b)
+        s += partial[(int64_t)b * (kNParam + 1) + j];
+    if (j < kNParam)
+        grad[j] = s;
+    else if (loss)
+        *loss = s / (float)n;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_adam(float* __restrict__ P, float* __restrict__ m1,
+                                                 float* __restrict__ m2, const float* __restrict__ g, float lr,
+                                                 float b1, float b2, float eps, float c1, float c2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kNParam)
+        return;
+    const float gj = g[j];
+    const float a = b1 * m1[j] + (1.0f - b1) * gj;
+    const float v = b2 * m2[j] + (1.0f - b2) * gj * gj;
+    m1[j] = a;
+    m2[j] = v;
+    P[j] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// FP32 inference, one sample per lane, parameters in LDS
+__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ P, const float* __restrict__ X,
+                                                    float* __restrict__ Y, int64_t n)
+{
+    extern __shared__ float p[];
+    for (int k = threadIdx.x; k < kNParam; k += blockDim.x)
+        p[k] = P[k];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    float a[kH], b[kH];
+    for (int o = 0; o < kH; ++o) {
+        float z = p[kOffB1 + o];
+        for (int k = 0; k < kIn; ++k)
+            z += p[kOffW1 + o * kIn + k] * X[i * kIn + k];
+        a[o] = fmaxf(z, 0.0f);
+    }
+    for (int o = 0; o < kH; ++o) {
+        float z = p[kOffB2 + o];
+        for (int k = 0; k < kH; ++k)
+            z += p[kOffW2 + o * kH + k] * a[k];
+        b[o] = fmaxf(z, 0.0f);
+    }
+    float y = p[kOffB4];
+    for (int o = 0; o < kH; ++o) {
+        float z = p[kOffB3 + o];
+        for (int k = 0; k < kH; ++k)
+            z += p[kOffW3 + o * kH + k] * b[k];
+        y += p[kOffW4 + o] * fmaxf(z, 0.0f);
+    }
+    Y[i] = y;
+}
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA inference.  v_mfma_f32_16x16x16bf16_1k: lane l holds
+// A[i = l%16][k = 4(l/16)+j], B[k = 4(l/16)+j][n = l%16] and returns
+// D[i = 4(l/16)+j][n = l%16], j = 0..3.  With weights as A (rows = output
+// neurons, 16 per tile mt) and activations as B (columns = 16 particles of
+// tile nt), a layer's output tile (mt, nt) is exactly the B operand of the
+// next layer's k-tile kt = mt: the whole network stays in registers.
+// The weight fragments are laid out at init so that each lane reads its 8
+// bytes contiguously from LDS.
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Layer 1 has K = 4 inputs and the MFMA K = 16: the padding carries a hi/lo
+// split of inputs and weights, k = 0..3: W_hi x_hi, 4..7: W_hi x_lo,
+// 8..11: W_lo x_hi (12..15 zero), so the first layer is accurate to ~2^-16
+// although its operands are BF16.
+struct NetFrags {
+    bf16x4 w1[4][64];     // [mt][lane]
+    bf16x4 w2[4][4][64];  // [mt][kt][lane]
+    bf16x4 w3[4][4][64];
+    float b1[kH], b2[kH], b3[kH], w4[kH];
+    float b4;
+    float pad[3];
+};
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs)
+__host__ __device__ __forceinline__ short bf16_bits(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__host__ __device__ __forceinline__ float bf16_value(short b)
+{
+    return __builtin_bit_cast(float, (uint32_t)(uint16_t)b << 16);
+}
+
+__device__ __forceinline__ bf16x4 pack_relu(f32x4 v)
+{
+    bf16x4 r;
+    r[0] = bf16_bits(fmaxf(v[0], 0.0f));
+    r[1] = bf16_bits(fmaxf(v[1], 0.0f));
+    r[2] = bf16_bits(fmaxf(v[2], 0.0f));
+    r[3] = bf16_bits(fmaxf(v[3], 0.0f));
+    return r;
+}
+
+__device__ __forceinline__ f32x4 bias4(const float* b, int mt, int g)
+{
+    return *reinterpret_cast<const f32x4*>(b + 16 * mt + 4 * g);
+}
+
+// Network output for this lane's particle (all 64 lanes of the wave must
+// call it together; x of inactive lanes may be anything finite).
+__device__ __forceinline__ float net_bf16(const NetFrags& N, const float x[4])
+{
+    const int l = threadIdx.x & 63;
+    const int q = l & 15;
+    const int g = l >> 4;
+    float out = 0.0f;
+    for (int nt = 0; nt < 4; ++nt) {
+        const int src = 16 * nt + q;
+        bf16x4 bx;
+        for (int j = 0; j < 4; ++j) {
+            const float f = __shfl(x[j], src, 64);
+            const short hi = bf16_bits(f);
+            const short lo = bf16_bits(f - bf16_value(hi));
+            bx[j] = (g == 0 || g == 2) ? hi : (g == 1 ? lo : (short)0);
+        }
+        f32x4 acc[4];
+        bf16x4 hb[4];
+        for (int mt = 0; mt < 4; ++mt) {
+            acc[mt] = bias4(N.b1, mt, g);
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w1[mt][l], bx, acc[mt], 0, 0, 0);
+        }
+        for (int mt = 0; mt < 4; ++mt)
+            hb[mt] = pack_relu(acc[mt]);
+        for (int mt = 0; mt < 4; ++mt) {
+            acc[mt] = bias4(N.b2, mt, g);
+            for (int kt = 0; kt < 4; ++kt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w2[mt][kt][l], hb[kt], acc[mt], 0, 0, 0);
+        }
+        for (int mt = 0; mt < 4; ++mt)
+            hb[mt] = pack_relu(acc[mt]);
+        for (int mt = 0; mt < 4; ++mt) {
+            acc[mt] = bias4(N.b3, mt, g);
+            for (int kt = 0; kt < 4; ++kt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w3[mt][kt][l], hb[kt], acc[mt], 0, 0, 0);
+        }
+        // output layer in FP32: this lane's 16 neurons of column q, then
+        // the sum over the four lanes that share the column
+        float part = 0.0f;
+        for (int mt = 0; mt < 4; ++mt) {
+            const f32x4 w = bias4(N.w4, mt, g);
+            for (int j = 0; j < 4; ++j)
+                part += w[j] * fmaxf(acc[mt][j], 0.0f);
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (g == nt)
+            out = part + N.b4;
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Certificate.  From the prediction u0 = 1/y (u = l1 D), one FP64 Newton
+// step u1 = u0 - g(u0)/g'(u0).  u1 is accepted as the collapse when
+//   (i)   |g(u1)/g'(u1)| <= rtol u1 (the next Newton correction, i.e. the
+//         error of u1 to first order, is below rtol),
+//   (ii)  g'(u1) < 0 (a downward crossing),
+//   (iii) no local minimum of g with g <= 0 lies in (0, u1) (so no earlier
+//         crossing): the first positive critical point of g is its first
+//         local minimum, u_m = 1/(b + sqrt(b^2 + 3c)).
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ bool certify(const CubicU& k, double y, double rtol, double& u1)
+{
+    if (!(y > 0.0) || !isfinite(y))
+        return false;
+    const double u0 = rcp2(y);
+    const double g0 = g_u(k, u0);
+    const double d0 = -1.0 + u0 * (2.0 * k.b + 3.0 * k.c * u0);
+    u1 = u0 - g0 * rcp2(d0);
+    const double g1 = g_u(k, u1);
+    const double d1 = -1.0 + u1 * (2.0 * k.b + 3.0 * k.c * u1);
+    const bool small = fabs(g1) <= rtol * u1 * fabs(d1);
+    const bool down = d1 < 0.0;
+    const double disc = k.b * k.b + 3.0 * k.c;
+    const double den = k.b + sqrt(fmax(disc, 0.0));
+    bool earlier = false;
+    if (disc >= 0.0 && den > 0.0) {
+        const double um = rcp2(den);
+        earlier = um < u1 && g_u(k, um) <= 0.0;
+    }
+    return u1 > 0.0 && small && down && !earlier && isfinite(u1);
+}
+
+}  // namespace pino

@@ -1,0 +1,215 @@
+"""The learned surrogate: training kernels against the FP64 reference
+network, the BF16 MFMA network against the same network in FP64, network
+inputs against the oracle, and the certified collapse against the oracle
+(gate: 1e-6 relative on D_c after certification), with the fallback
+fraction and the gain over the same certificate without a trained network
+reported."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+import oracle.mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+BF16_EPS = 2.0 ** -8
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2510_02873_amd as P
+    from paper_2510_02873_amd import _abi
+    return P, _abi
+
+
+def _theta(seed, scale=0.25):
+    th = np.random.default_rng(seed).normal(size=omlp.NPARAM) * scale
+    th[-1] = 1.0
+    return th.astype(np.float32)
+
+
+def test_mlp_grad_and_forward_vs_fp64(P):
+    _, A = P
+    rng = np.random.default_rng(7)
+    n = 3000
+    x = rng.normal(size=(n, 4)).astype(np.float32)
+    w = rng.uniform(0.5, 2.0, size=n).astype(np.float32)
+    w[::17] = 0.0
+    th = _theta(11)
+    m = A.pino_mlp_create(0, 0)
+    try:
+        A.pino_mlp_set_params(m, th)
+        xd, wd = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+        g = torch.empty(A.PINO_MLP_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        A.pino_mlp_grad(m, xd, wd, g, loss)
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        A.pino_mlp_forward(m, xd, y)
+        torch.cuda.synchronize()
+        gg, yy = g.cpu().numpy().astype(np.float64), y.cpu().numpy()
+    finally:
+        A.pino_mlp_free(m)
+    ref_g = omlp.grad(th.astype(np.float64), x, w)
+    ref_y, _ = omlp.forward(th.astype(np.float64), x)
+    rel_g = np.linalg.norm(gg - ref_g) / np.linalg.norm(ref_g)
+    print(f"grad rel err (2-norm) {rel_g:.2e}; forward max rel {np.max(np.abs(yy - ref_y) / np.abs(ref_y)):.2e}")
+    assert rel_g < 1e-3
+    assert np.allclose(gg, ref_g, rtol=1e-3, atol=1e-5 * np.max(np.abs(ref_g)))
+    assert np.allclose(yy, ref_y, rtol=1e-4, atol=1e-5)
+    assert abs(float(loss.item()) - omlp.loss(th.astype(np.float64), x, w)) < 1e-4 * omlp.loss(th.astype(np.float64), x, w)
+
+
+def test_adam_step_matches_formula(P):
+    _, A = P
+    th = _theta(3)
+    g = (np.random.default_rng(4).normal(size=omlp.NPARAM) * 1e-2).astype(np.float32)
+    m = A.pino_mlp_create(0, 0)
+    try:
+        A.pino_mlp_set_params(m, th)
+        gd = torch.from_numpy(g).cuda()
+        A.pino_mlp_adam(m, gd, 1e-3)
+        A.pino_mlp_adam(m, gd, 1e-3)
+        got = A.pino_mlp_get_params(m).astype(np.float64)
+    finally:
+        A.pino_mlp_free(m)
+    # two Adam steps with the same gradient, textbook bias correction
+    t = th.astype(np.float64)
+    m1 = v = np.zeros_like(t)
+    for k in (1, 2):
+        m1 = 0.9 * m1 + 0.1 * g
+        v = 0.999 * v + 0.001 * g.astype(np.float64) ** 2
+        t = t - 1e-3 * (m1 / (1 - 0.9 ** k)) / (np.sqrt(v / (1 - 0.999 ** k)) + 1e-8)
+    assert np.allclose(got, t, rtol=1e-5, atol=1e-6)
+
+
+def _fields(n_side, box, radii, seed, cosmo, dtype=torch.float32):
+    fld = synth.fields.field(n_side, box, seed, cosmo, device="cuda")
+    return [(fld.hessian(R).to(dtype), synth.grid_sigma_gauss(n_side, box, R, cosmo)) for R in radii]
+
+
+def test_features_vs_oracle(P):
+    Pk, A = P
+    a, D = synth.growth_table(0.3)
+    (h, sig), = _fields(32, 100.0, [2.0], 1, synth.Cosmology())
+    with Pk.Collapse([(a, D, 0.3)], precision=Pk.PINO_MIXED) as col:
+        n = h.shape[1]
+        x = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        w = torch.empty(n, dtype=torch.float32, device="cuda")
+        F = torch.empty(1, dtype=torch.float64, device="cuda")
+        R = torch.empty(1, dtype=torch.int32, device="cuda")
+        A.pino_collapse_features(col.ctx, A.make_item(h, F, R, sigma_R=sig, n=n), x, w)
+        torch.cuda.synchronize()
+    lam, Fr = _orc().points(h.double().cpu().numpy())
+    xr = lam / sig
+    assert np.allclose(x.cpu().numpy()[:, :3], xr, rtol=2e-6, atol=2e-6 * np.abs(xr).max())
+    consult = (lam[:, 0] > 0) & (lam[:, 0] >= 0.1 * np.abs(lam[:, 2]))
+    wr = np.where(consult & (Fr > 0), Fr / np.where(lam[:, 0] > 0, lam[:, 0], 1), 0.0)
+    wg = w.cpu().numpy()
+    assert np.array_equal(wg > 0, wr > 0)
+    m = wr > 0
+    assert np.allclose(wg[m], wr[m], rtol=1e-6)
+
+
+def _orc():
+    import oracle
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def trained(P):
+    """A network trained by the library's kernels on pairs from 96^3 fields
+    of two cosmologies (small and quick; the benchmark trains the full one)."""
+    Pk, A = P
+    from paper_2510_02873_amd import surrogate
+    cosmos = [synth.Cosmology(0.3, 0.8), synth.Cosmology(0.27, 0.8)]
+    tables = [(*synth.growth_table(c.omega_m), c.omega_m) for c in cosmos]
+    fields = []
+    for k, c in enumerate(cosmos):
+        for h, sig in _fields(96, 150.0, [6.0, 3.0, 1.5, 0.8], 31 + k, c):
+            fields.append((h, sig, k))
+    x, w = surrogate.training_pairs(fields, tables)
+    print(f"training pairs: {x.shape[0]}", flush=True)
+    blob, params, hist = surrogate.train(x, w, steps=3000, batch=8192, lr_max=3e-3, seed=1, log_every=1000)
+    print("loss history", hist, flush=True)
+    assert hist[-1][1] < 0.2 * hist[0][1]
+    return blob, params
+
+
+def test_predict_bf16_vs_fp64(P, trained):
+    Pk, A = P
+    blob, params = trained
+    a, D = synth.growth_table(0.3)
+    # inputs as the collapse kernel sees them: network inputs of a field
+    (h, sig), = _fields(32, 100.0, [2.0], 9, synth.Cosmology())
+    lam, _ = _orc().points(h.double().cpu().numpy())
+    keep = (lam[:, 0] > 0) & (lam[:, 0] >= 0.1 * np.abs(lam[:, 2]))
+    x = np.column_stack([lam[keep] / sig, np.zeros(keep.sum())]).astype(np.float32)
+    n = x.shape[0]
+    with Pk.Collapse([(a, D, 0.3)], precision=Pk.PINO_SURROGATE, mlp_blob=blob) as col:
+        xd = torch.from_numpy(x).cuda()
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        A.pino_collapse_predict(col.ctx, xd, y)
+        torch.cuda.synchronize()
+    ref, _ = omlp.forward(params.astype(np.float64), x)
+    rel = np.abs(y.cpu().numpy() - ref) / np.abs(ref)
+    print(f"BF16 MFMA vs FP64 network: n={n} median rel {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e} "
+          f"max {rel.max():.2e}")
+    # BF16 rounding of the hidden activations and weights (the first layer is
+    # split hi/lo): a fraction of 2^-8 typically, a few 2^-8 at worst
+    assert np.median(rel) < BF16_EPS / 2 and rel.max() < 8 * BF16_EPS
+
+
+def _run_surrogate(Pk, A, blob, slabs32, a, D, sigmas, rtol=0.0):
+    with Pk.Collapse([(a, D, 0.3)], precision=Pk.PINO_SURROGATE, mlp_blob=blob, certify_rtol=rtol) as col:
+        n = slabs32[0].shape[1]
+        Fm, Rm, ac = col.outputs(n)
+        last = len(slabs32) - 1
+        for r, (h, s) in enumerate(zip(slabs32, sigmas)):
+            col.apply(h, r, Fm, Rm, ac if r == last else None, reset=(r == 0), finalize=(r == last), sigma_R=s)
+        stats = A.pino_collapse_surrogate_stats(col.ctx)
+        return (Fm.cpu().numpy(), Rm.cpu().numpy(), ac.cpu().numpy()), stats
+
+
+def test_surrogate_parity_and_gain(P, trained):
+    Pk, A = P
+    from paper_2510_02873_amd import surrogate
+    orc = _orc()
+    blob, _ = trained
+    cfg = synth.config("C1")
+    a, D = synth.growth_table(0.3)
+    data = _fields(cfg["n_side"], cfg["box"], cfg["radii"], cfg["seed"], cfg["cosmo"])
+    slabs32 = [h.contiguous() for h, _ in data]
+    sig = [s for _, s in data]
+    widened = [h.double().cpu().numpy() for h in slabs32]
+    ref = orc.collapse(widened, orc.Growth(a, D))
+    got, stats = _run_surrogate(Pk, A, blob, slabs32, a, D, sig)
+    n = slabs32[0].shape[1]
+    tot = stats["certified"] + stats["fallback"] + stats["gated"]
+    assert tot == n * len(slabs32)
+    Fr, Rr, Ar = ref
+    F, R, Ac = got
+    big = Fr >= 1e-6
+    rel = np.abs(1 / F[big] - 1 / Fr[big]) * Fr[big]
+    fin = np.isfinite(Ar)
+    rel_a = np.abs(Ac[fin] - Ar[fin]) / Ar[fin]
+    per_r = np.stack([orc.points(h)[1] for h in widened])
+    srt = np.sort(per_r, axis=0)
+    tie = np.abs(srt[-1] - srt[-2]) <= 2e-6 * srt[-1]
+    consulted = stats["certified"] + stats["fallback"]
+    print(f"surrogate C1: certified {stats['certified']} fallback {stats['fallback']} gated {stats['gated']} "
+          f"(fallback fraction of consulted {stats['fallback'] / consulted:.3f}); "
+          f"D_c max rel {rel.max():.2e}, a_coll max rel {rel_a.max():.2e}", flush=True)
+    assert rel.max() <= 1e-6
+    assert np.array_equal(np.isfinite(Ac), fin) and rel_a.max() <= 1e-6
+    assert np.all((R == Rr) | tie)
+    # the same certificate started from the Zel'dovich guess (a network that
+    # predicts w = 1 everywhere): what the trained network gains
+    got0, stats0 = _run_surrogate(Pk, A, surrogate.constant_blob(1.0), slabs32, a, D, sig)
+    c0 = stats0["certified"] / (stats0["certified"] + stats0["fallback"])
+    c1 = stats["certified"] / consulted
+    print(f"certified fraction: trained network {c1:.3f} vs Zel'dovich guess {c0:.3f}", flush=True)
+    F0 = got0[0]
+    assert np.max(np.abs(1 / F0[big] - 1 / Fr[big]) * Fr[big]) <= 1e-6
+    assert c1 > c0 + 0.2
