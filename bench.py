@@ -73,6 +73,8 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
     last = len(radii) - 1
     F64, R64, A64 = Fmax.clone(), Rmax.clone(), ac.clone()
 
+    sig = synth.grid_sigma_gauss(n_side, cfg["box"], radii)
+
     # mixed precision
     s32 = [h.to(torch.float32) for h in slabs]
     mcol = P.Collapse([(a, D)], precision=P.PINO_MIXED)
@@ -92,12 +94,13 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                                        "mean": float(rel.mean())},
                     "index_mismatch_frac": float((Rm != R64).double().mean().item())}
     mcol.close()
+
+    out["surrogate"] = measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps)
     del s32
 
     # Tabulated: fill each radius' table with the Classic kernel on the
     # table's sample points (diagonal Hessians), then interpolate
     knots = synth.table_knots(1.0, 64, 64, 128)
-    sig = [synth.grid_sigma_gauss(n_side, cfg["box"], R) for R in radii]
     tabs = []
     for sR in sig:
         grid = torch.from_numpy(synth.table_grid_hessians(*(np.asarray(k) * sR for k in knots))).cuda()
@@ -121,6 +124,80 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                         "rel_F_vs_classic_median": float(np.median(relt))}
     tcol.close()
     return out
+
+
+def measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps):
+    """Learned surrogate + certify on the same fields (FP32 inputs): train the
+    network with the library's kernels on 20M (inputs, target) pairs from the
+    benchmark fields and four perturbed cosmologies (untimed), then time the
+    certified collapse.  Reports evals/s, the certified / fallback / gated
+    counts and the error against the plain FP64 run (FP32 input rounding
+    included)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2510_02873_amd import _abi, surrogate
+
+    t0 = time.time()
+    om = cfg["cosmo"].omega_m
+    perturbed = [synth.Cosmology(0.27, 0.8), synth.Cosmology(0.33, 0.8), synth.Cosmology(0.30, 0.75),
+                 synth.Cosmology(0.30, 0.85)]
+    tables = [(a, D, om)] + [(*synth.growth_table(c.omega_m), c.omega_m) for c in perturbed]
+    pick = list(range(0, len(radii), 6))
+    n_slabs = len(pick) + 2 * len(perturbed)
+    per = 20_000_000 // n_slabs + 1
+    fields = [(slabs[r], sig[r], 0) for r in pick]
+    x0, w0 = surrogate.training_pairs(fields, tables, per_slab=per)
+    xs, ws = [x0], [w0]
+    for k, c in enumerate(perturbed):
+        fld = synth.fields.field(n_side, cfg["box"], 51 + k, c, device=slabs[0].device)
+        sp = synth.grid_sigma_gauss(n_side, cfg["box"], [4.0, 1.0], c)
+        pf = [(fld.hessian(R), sR, k + 1) for R, sR in zip([4.0, 1.0], sp)]
+        x, w = surrogate.training_pairs(pf, tables, per_slab=per)
+        xs.append(x)
+        ws.append(w)
+        del fld, pf
+    x = torch.cat(xs)[:20_000_000].contiguous()
+    w = torch.cat(ws)[:20_000_000].contiguous()
+    del xs, ws, x0, w0
+    n_pairs = x.shape[0]
+    log(f"surrogate: {n_pairs} training pairs in {time.time() - t0:.1f}s")
+    t1 = time.time()
+    blob, _, hist = surrogate.train(x, w, steps=10000, batch=16384, lr_max=3e-3, seed=7, log_every=2500,
+                                    log=lambda m: log(m))
+    train_s = time.time() - t1
+    del x, w
+    last = len(radii) - 1
+    scol = P.Collapse([(a, D, om)], precision=P.PINO_SURROGATE, mlp_blob=blob)
+    Fs, Rs, As = scol.outputs(n)
+    items = [scol.item(s32[r], Fs, Rs, As if r == last else None, radius_index=r, sigma_R=sig[r])
+             for r in range(len(radii))]
+
+    def sstep():
+        for r, it in enumerate(items):
+            scol.eval([it], reset=(r == 0), finalize=(r == last), stream=stream)
+
+    sstep()
+    _abi.pino_collapse_surrogate_stats(scol.ctx, reset=True)
+    sstep()
+    st = _abi.pino_collapse_surrogate_stats(scol.ctx, reset=True)
+    ms = _time_steps(sstep, steps, stream)
+    big = F64 > 1e-6
+    rel = ((1 / Fs[big] - 1 / F64[big]).abs() * F64[big]).cpu().numpy()
+    consulted = st["certified"] + st["fallback"]
+    res = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s", "ms_per_step": round(ms, 4),
+           "dtype": "bf16 MFMA network (fp32 accumulate), fp64 eigen + Newton certificate, f32 inputs",
+           "certified": st["certified"], "fallback": st["fallback"], "gated": st["gated"],
+           "fallback_fraction_of_consulted": round(st["fallback"] / max(consulted, 1), 4),
+           "rel_Dc_vs_fp64_field": {"max": float(rel.max()), "p99.9": float(np.percentile(rel, 99.9)),
+                                    "mean": float(rel.mean())},
+           "index_mismatch_frac": float((Rs != R64).double().mean().item()),
+           "training": {"pairs": int(n_pairs), "steps": 10000, "batch": 16384, "seconds": round(train_s, 1),
+                        "final_loss": hist[-1][1] if hist else None}}
+    scol.close()
+    log(f"surrogate+certify {res['value']:.3e} evals/s, fallback {res['fallback_fraction_of_consulted']:.3f}")
+    return res
 
 
 def main():

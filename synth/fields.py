@@ -122,15 +122,16 @@ def field(n_side: int, box: float, seed: int, cosmo: Cosmology = Cosmology(), de
     return _Field(n_side, box, seed, cosmo, device)
 
 
-def grid_sigma_gauss(n_side: int, box: float, R: float, cosmo: Cosmology = Cosmology()) -> float:
+def grid_sigma_gauss(n_side: int, box: float, R, cosmo: Cosmology = Cosmology()):
     """Expected rms of the smoothed field on this grid: sqrt(sum_k P W^2 / L^3)
-    over the kept modes (full complex grid, so each mode counts once)."""
+    over the kept modes (full complex grid, so each mode counts once).  R may
+    be a number or a sequence (then a list is returned)."""
+    radii = np.atleast_1d(np.asarray(R, dtype=np.float64))
     k1 = np.fft.fftfreq(n_side, d=1.0 / n_side) * (2.0 * np.pi / box)
     keep = np.ones(n_side)
     if n_side % 2 == 0:
         keep[n_side // 2] = 0.0
-    total = 0.0
-    # sum slab by slab to bound memory at large n
+    total = np.zeros(len(radii))
     ky = k1[:, None]
     kz = k1[None, :]
     for ix in range(n_side):
@@ -141,7 +142,8 @@ def grid_sigma_gauss(n_side: int, box: float, R: float, cosmo: Cosmology = Cosmo
         if ix == 0:
             w = w.copy()
             w[0, 0] = 0.0
-        kmag = np.sqrt(k2)
-        total += float(np.sum(w * power_spectrum(kmag.ravel(), cosmo).reshape(k2.shape)
-                              * np.exp(-k2 * R * R)))
-    return float(np.sqrt(total / box ** 3))
+        pk = w * power_spectrum(np.sqrt(k2).ravel(), cosmo).reshape(k2.shape)
+        for j, Rj in enumerate(radii):
+            total[j] += float(np.sum(pk * np.exp(-k2 * Rj * Rj)))
+    out = [float(np.sqrt(t / box ** 3)) for t in total]
+    return out if np.ndim(R) else out[0]
