@@ -275,3 +275,91 @@ def pino_collapse_surrogate_stats(ctx, reset=False):
     _check(_bind_mlp().pino_collapse_surrogate_stats(ctx, ctypes.byref(c), ctypes.byref(f), ctypes.byref(g),
                                                      int(bool(reset))), ctx)
     return {"certified": c.value, "fallback": f.value, "gated": g.value}
+
+
+# ---------------------------------------------------------------------------
+# include/pino_batch.h
+# ---------------------------------------------------------------------------
+class pino_realisation(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_radii", ctypes.c_int32), ("h", ctypes.POINTER(ctypes.c_void_p)),
+                ("cosmo", ctypes.c_int32), ("radius_offset", ctypes.c_int32), ("Fmax", ctypes.c_void_p),
+                ("Rmax", ctypes.c_void_p), ("a_coll", ctypes.c_void_p)]
+
+
+class pino_batch_tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int64), ("blocks_per_cu", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+
+
+_batch_bound = False
+
+
+def _bind_batch():
+    global _batch_bound
+    L = lib()
+    if not _batch_bound:
+        L.pino_collapse_batch_plan.argtypes = [ctypes.c_void_p, ctypes.POINTER(pino_realisation), ctypes.c_int32,
+                                               ctypes.c_uint32, ctypes.POINTER(pino_batch_tuning),
+                                               ctypes.POINTER(ctypes.c_void_p)]
+        L.pino_collapse_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.pino_collapse_batch_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.pino_collapse_batch_config.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int64)]
+        L.pino_collapse_batch_free.argtypes = [ctypes.c_void_p]
+        for name in ("pino_collapse_batch_plan", "pino_collapse_batch_run", "pino_collapse_batch_graph_launch",
+                     "pino_collapse_batch_config", "pino_collapse_batch_free"):
+            getattr(L, name).restype = ctypes.c_int
+        _batch_bound = True
+    return L
+
+
+class Batch:
+    """A planned batch.  realisations: list of dicts with keys h (list over
+    radii of 6-component device tensors or (6, n) tensors), Fmax, Rmax,
+    a_coll (optional), cosmo, radius_offset."""
+
+    def __init__(self, ctx, realisations, flags=0, tile=0, blocks_per_cu=0, autotune=False):
+        L = _bind_batch()
+        self._keep = []
+        arr = (pino_realisation * max(1, len(realisations)))()
+        for k, R in enumerate(realisations):
+            slabs = R["h"]
+            n = int(slabs[0][0].numel())
+            ptrs = (ctypes.c_void_p * (6 * len(slabs)))()
+            for r, h in enumerate(slabs):
+                for c in range(6):
+                    ptrs[6 * r + c] = h[c].data_ptr()
+            self._keep.append(ptrs)
+            ac = R.get("a_coll")
+            arr[k] = pino_realisation(n, len(slabs), ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)),
+                                      R.get("cosmo", 0), R.get("radius_offset", 0), R["Fmax"].data_ptr(),
+                                      R["Rmax"].data_ptr(), None if ac is None else ac.data_ptr())
+        tun = pino_batch_tuning(tile, blocks_per_cu, int(bool(autotune)))
+        out = ctypes.c_void_p()
+        _check(L.pino_collapse_batch_plan(ctx, arr, len(realisations), flags, ctypes.byref(tun), ctypes.byref(out)),
+               ctx)
+        self.plan = out.value
+        self.ctx = ctx
+
+    def run(self, stream=None):
+        _check(_bind_batch().pino_collapse_batch_run(self.plan, _stream(stream)), self.ctx)
+
+    def graph_launch(self, stream):
+        _check(_bind_batch().pino_collapse_batch_graph_launch(self.plan, _stream(stream)), self.ctx)
+
+    def config(self):
+        t, b, g, n = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(_bind_batch().pino_collapse_batch_config(self.plan, ctypes.byref(t), ctypes.byref(b), ctypes.byref(g),
+                                                        ctypes.byref(n)))
+        return {"tile": t.value, "blocks_per_cu": b.value, "grid": g.value, "n_tiles": n.value}
+
+    def close(self):
+        if self.plan is not None:
+            _check(_bind_batch().pino_collapse_batch_free(self.plan))
+            self.plan = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,126 @@
+// Persistent batched kernel: a static list of particle tiles over many
+// realisations, each particle carried through all of its radii with the
+// running maximum in registers.
+#pragma once
+
+#include "kernels_fp64.h"
+#include "kernels_mixed.h"
+
+namespace pino {
+
+struct RealDesc {
+    int64_t n;
+    int32_t n_radii;
+    int32_t cosmo;
+    int32_t radius_offset;
+    int32_t nk;
+    const void* const* h;  // device array, n_radii * 6 pointers, radius-major
+    double* Fmax;
+    int32_t* Rmax;
+    double* acoll;
+    const double* growth;  // [D | a | M] (FP64)
+    const float* growth32; // FP32 copy (mixed precision), or null
+    GrowthIndex gi;        // idx in global memory
+};
+
+struct Tile {
+    int32_t real;
+    int32_t pad;
+    int64_t start;
+    int64_t count;
+};
+
+// One pass over the tiles assigned to this block (b, b + grid, ...).  The
+// growth knots of a tile's cosmology are staged in LDS when the cosmology
+// changes from the previous tile's.
+template <bool F32>
+__global__ void __launch_bounds__(256) k_batch(const RealDesc* __restrict__ reals, const Tile* __restrict__ tiles,
+                                              int64_t n_tiles, uint32_t reset)
+{
+    extern __shared__ double lds[];
+    int staged = -1;
+    GrowthIndex gi{};
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const RealDesc& R = reals[tl.real];
+        const int nk = R.nk;
+        if (R.cosmo != staged) {
+            __syncthreads();
+            if (F32) {
+                float* g = reinterpret_cast<float*>(lds);
+                for (int k = threadIdx.x; k < 3 * nk; k += blockDim.x)
+                    g[k] = R.growth32[k];
+                int* idx = reinterpret_cast<int*>(g + 3 * nk);
+                for (int k = threadIdx.x; k < R.gi.nb; k += blockDim.x)
+                    idx[k] = R.gi.idx[k];
+                gi = R.gi;
+                gi.idx = idx;
+            } else {
+                for (int k = threadIdx.x; k < 3 * nk; k += blockDim.x)
+                    lds[k] = R.growth[k];
+                int* idx = reinterpret_cast<int*>(lds + 3 * nk);
+                for (int k = threadIdx.x; k < R.gi.nb; k += blockDim.x)
+                    idx[k] = R.gi.idx[k];
+                gi = R.gi;
+                gi.idx = idx;
+            }
+            __syncthreads();
+            staged = R.cosmo;
+        }
+        const int nr = R.n_radii;
+        for (int64_t j = threadIdx.x; j < tl.count; j += blockDim.x) {
+            const int64_t i = tl.start + j;
+            double fm = reset ? 0.0 : R.Fmax[i];
+            int32_t rm = reset ? -1 : R.Rmax[i];
+            for (int r = 0; r < nr; ++r) {
+                const void* const* hp = R.h + 6 * r;
+                double l1, s, pp;
+                if (F32) {
+                    Hess32 h;
+                    h.xx = __builtin_nontemporal_load(static_cast<const float*>(hp[0]) + i);
+                    h.yy = __builtin_nontemporal_load(static_cast<const float*>(hp[1]) + i);
+                    h.zz = __builtin_nontemporal_load(static_cast<const float*>(hp[2]) + i);
+                    h.xy = __builtin_nontemporal_load(static_cast<const float*>(hp[3]) + i);
+                    h.xz = __builtin_nontemporal_load(static_cast<const float*>(hp[4]) + i);
+                    h.yz = __builtin_nontemporal_load(static_cast<const float*>(hp[5]) + i);
+                    float l1f, sf, ppf;
+                    if (eig_top_f32(h, l1f, sf, ppf)) {
+                        l1 = l1f;
+                        s = sf;
+                        pp = ppf;
+                    } else {
+                        eig_top(widen(h), l1, s, pp);
+                    }
+                } else {
+                    Hess64 h;
+                    h.xx = __builtin_nontemporal_load(static_cast<const double*>(hp[0]) + i);
+                    h.yy = __builtin_nontemporal_load(static_cast<const double*>(hp[1]) + i);
+                    h.zz = __builtin_nontemporal_load(static_cast<const double*>(hp[2]) + i);
+                    h.xy = __builtin_nontemporal_load(static_cast<const double*>(hp[3]) + i);
+                    h.xz = __builtin_nontemporal_load(static_cast<const double*>(hp[4]) + i);
+                    h.yz = __builtin_nontemporal_load(static_cast<const double*>(hp[5]) + i);
+                    eig_top(h, l1, s, pp);
+                }
+                const double F = classic_F(l1, s, pp);
+                if (F > fm) {
+                    fm = F;
+                    rm = R.radius_offset + r;
+                }
+            }
+            R.Fmax[i] = fm;
+            R.Rmax[i] = rm;
+            if (R.acoll) {
+                double ac = kInf;
+                if (fm > 0.0) {
+                    if (F32)
+                        ac = (double)growth_invert_f32(reinterpret_cast<const float*>(lds), nk, (float)rcp2(fm), gi);
+                    else
+                        ac = growth_invert(lds, nk, rcp2(fm), gi);
+                }
+                R.acoll[i] = ac;
+            }
+        }
+    }
+}
+
+}  // namespace pino
