@@ -92,3 +92,14 @@ def _amplitude(omega_m, sigma8, n_s, h):
 def power_spectrum(k, cosmo: Cosmology):
     """P(k) in (Mpc/h)^3, normalised to cosmo.sigma8."""
     return cosmo.amplitude * _pk_shape(k, cosmo.omega_m, cosmo.n_s, cosmo.h)
+
+
+def power_spectrum_torch(k, cosmo: Cosmology):
+    """The same P(k) on a torch tensor (float64, any device)."""
+    import torch
+    q = k / (cosmo.omega_m * cosmo.h)
+    qs = torch.where(q > 0, q, torch.ones_like(q))
+    t = (torch.log1p(2.34 * qs) / (2.34 * qs)
+         * (1.0 + 3.89 * qs + (16.1 * qs) ** 2 + (5.46 * qs) ** 3 + (6.71 * qs) ** 4) ** -0.25)
+    t = torch.where(q > 0, t, torch.ones_like(t))
+    return cosmo.amplitude * torch.where(k > 0, k, torch.ones_like(k)) ** cosmo.n_s * t * t * (k > 0)

@@ -24,7 +24,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .cosmo import Cosmology, power_spectrum
+from .cosmo import Cosmology, power_spectrum, power_spectrum_torch
 
 HESSIAN_COMPONENTS = ("xx", "yy", "zz", "xy", "xz", "yz")
 _PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
@@ -79,8 +79,8 @@ class _Field:
         k2 = self.kx ** 2 + self.ky ** 2 + self.kz ** 2
         kmag = torch.sqrt(k2)
         vcell = (box / n_side) ** 3
-        pk = torch.from_numpy(power_spectrum(kmag.cpu().numpy().ravel(), cosmo)).to(self.device)
-        amp = torch.sqrt(pk.reshape(kmag.shape) / vcell) * _mode_mask(n_side, self.device)
+        pk = power_spectrum_torch(kmag, cosmo)
+        amp = torch.sqrt(pk / vcell) * _mode_mask(n_side, self.device)
         self.dk = dk * amp
         self.k2 = torch.where(k2 > 0, k2, torch.ones_like(k2))
         del dk, amp, pk, kmag
