@@ -23,6 +23,26 @@ struct RealDesc {
     GrowthIndex gi;        // idx in global memory
 };
 
+template <bool F32> struct HessSel { using type = Hess64; using elem = double; };
+template <> struct HessSel<true> { using type = Hess32; using elem = float; };
+template <bool F32> using HessT = typename HessSel<F32>::type;
+
+// Six streamed components of one particle; hp points at one radius' six
+// component pointers.
+template <bool F32>
+__device__ __forceinline__ HessT<F32> load_hess(const void* const* hp, int64_t i)
+{
+    using E = typename HessSel<F32>::elem;
+    HessT<F32> h;
+    h.xx = __builtin_nontemporal_load(static_cast<const E*>(hp[0]) + i);
+    h.yy = __builtin_nontemporal_load(static_cast<const E*>(hp[1]) + i);
+    h.zz = __builtin_nontemporal_load(static_cast<const E*>(hp[2]) + i);
+    h.xy = __builtin_nontemporal_load(static_cast<const E*>(hp[3]) + i);
+    h.xz = __builtin_nontemporal_load(static_cast<const E*>(hp[4]) + i);
+    h.yz = __builtin_nontemporal_load(static_cast<const E*>(hp[5]) + i);
+    return h;
+}
+
 struct Tile {
     int32_t real;
     int32_t pad;
@@ -72,17 +92,15 @@ __global__ void __launch_bounds__(256) k_batch(const RealDesc* __restrict__ real
             const int64_t i = tl.start + j;
             double fm = reset ? 0.0 : R.Fmax[i];
             int32_t rm = reset ? -1 : R.Rmax[i];
+            // The next radius' Hessian is loaded before the current one's
+            // arithmetic, so the loads of radius r+1 overlap the solve of r.
+            HessT<F32> hn = load_hess<F32>(R.h, i);
             for (int r = 0; r < nr; ++r) {
-                const void* const* hp = R.h + 6 * r;
+                const HessT<F32> h = hn;
+                if (r + 1 < nr)
+                    hn = load_hess<F32>(R.h + 6 * (r + 1), i);
                 double l1, s, pp;
-                if (F32) {
-                    Hess32 h;
-                    h.xx = __builtin_nontemporal_load(static_cast<const float*>(hp[0]) + i);
-                    h.yy = __builtin_nontemporal_load(static_cast<const float*>(hp[1]) + i);
-                    h.zz = __builtin_nontemporal_load(static_cast<const float*>(hp[2]) + i);
-                    h.xy = __builtin_nontemporal_load(static_cast<const float*>(hp[3]) + i);
-                    h.xz = __builtin_nontemporal_load(static_cast<const float*>(hp[4]) + i);
-                    h.yz = __builtin_nontemporal_load(static_cast<const float*>(hp[5]) + i);
+                if constexpr (F32) {
                     float l1f, sf, ppf;
                     if (eig_top_f32(h, l1f, sf, ppf)) {
                         l1 = l1f;
@@ -92,13 +110,6 @@ __global__ void __launch_bounds__(256) k_batch(const RealDesc* __restrict__ real
                         eig_top(widen(h), l1, s, pp);
                     }
                 } else {
-                    Hess64 h;
-                    h.xx = __builtin_nontemporal_load(static_cast<const double*>(hp[0]) + i);
-                    h.yy = __builtin_nontemporal_load(static_cast<const double*>(hp[1]) + i);
-                    h.zz = __builtin_nontemporal_load(static_cast<const double*>(hp[2]) + i);
-                    h.xy = __builtin_nontemporal_load(static_cast<const double*>(hp[3]) + i);
-                    h.xz = __builtin_nontemporal_load(static_cast<const double*>(hp[4]) + i);
-                    h.yz = __builtin_nontemporal_load(static_cast<const double*>(hp[5]) + i);
                     eig_top(h, l1, s, pp);
                 }
                 const double F = classic_F(l1, s, pp);

@@ -150,10 +150,25 @@ k_classic_f64(ItemArgs a)
     extern __shared__ double lds[];
     const GrowthIndex gi = stage_growth(lds, a);
     __syncthreads();
+    // Software pipeline: the loads of the next grid-stride element are issued
+    // before the eigen/root arithmetic of the current one, so their latency
+    // hides behind it (the kernel has registers to spare for the second set).
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-        const Hess64 h = load_h64(a, i);
-        const double fm = a.reset ? 0.0 : a.Fmax[i];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Hess64 hn{};
+    double fn = 0.0;
+    if (i < a.n) {
+        hn = load_h64(a, i);
+        fn = a.reset ? 0.0 : a.Fmax[i];
+    }
+    for (; i < a.n; i += stride) {
+        const Hess64 h = hn;
+        const double fm = fn;
+        const int64_t next = i + stride;
+        if (next < a.n) {
+            hn = load_h64(a, next);
+            fn = a.reset ? 0.0 : a.Fmax[next];
+        }
         double l1, s, pp;
         eig_top(h, l1, s, pp);
         const double F = classic_F(l1, s, pp);
@@ -222,14 +237,28 @@ __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
     for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
         ds[k] = t.dk[k] * t.scale;
     __syncthreads();
+    // Next element's loads issued ahead of the current arithmetic.
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-        const Hess64 h = load_h64(a, i);
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Hess64 hn{};
+    double fn = 0.0;
+    if (i < a.n) {
+        hn = load_h64(a, i);
+        fn = a.reset ? 0.0 : a.Fmax[i];
+    }
+    for (; i < a.n; i += stride) {
+        const Hess64 h = hn;
+        const double fm = fn;
+        const int64_t next = i + stride;
+        if (next < a.n) {
+            hn = load_h64(a, next);
+            fn = a.reset ? 0.0 : a.Fmax[next];
+        }
         double l1, l2, l3;
         eig_all(h, l1, l2, l3);
         const bool finite = isfinite(l1) && isfinite(l2) && isfinite(l3);
         const double F = finite ? table_F(t, xs, ys, ds, l1, l2, l3) : 0.0;
-        update_max(a, g, gi, i, F, a.reset ? 0.0 : a.Fmax[i]);
+        update_max(a, g, gi, i, F, fm);
     }
 }
 

@@ -59,10 +59,23 @@ __global__ void __launch_bounds__(256) k_classic_mixed(ItemArgs a, const float* 
     float* g = reinterpret_cast<float*>(lds);
     const GrowthIndex gi = stage_growth32(g, growth32, a);
     __syncthreads();
+    // Next element's loads issued ahead of the current arithmetic.
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-        const Hess32 h = load_h32(a, i);
-        const double fm = a.reset ? 0.0 : a.Fmax[i];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Hess32 hn{};
+    double fn = 0.0;
+    if (i < a.n) {
+        hn = load_h32(a, i);
+        fn = a.reset ? 0.0 : a.Fmax[i];
+    }
+    for (; i < a.n; i += stride) {
+        const Hess32 h = hn;
+        const double fm = fn;
+        const int64_t next = i + stride;
+        if (next < a.n) {
+            hn = load_h32(a, next);
+            fn = a.reset ? 0.0 : a.Fmax[next];
+        }
         float l1f, sf, ppf;
         double l1, s, pp;
         if (eig_top_f32(h, l1f, sf, ppf)) {
