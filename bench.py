@@ -383,19 +383,32 @@ def main():
     mean_launch_ms = float(launch_ms.mean())
     mean_bytes = float(np.mean(bytes_per_launch))
     achieved_gbs = mean_bytes / (mean_launch_ms * 1e-3) / 1e9
-    # measured HBM traffic per launch (scaled rocprofv3 counters), valid only
-    # while the kernel sources are the ones that were profiled
-    from paper_2510_02873_amd.profiling import read_traffic, source_digest
-    traffic, digest = read_traffic(PROFILE)
-    if digest != source_digest():
-        traffic = None
+    # measured HBM traffic and FP64 FLOPs per launch (scaled rocprofv3
+    # counters), valid only while the loaded kernel's machine code is the one
+    # that was profiled
+    from paper_2510_02873_amd.profiling import kernel_digest, read_profile
+    prof = read_profile(PROFILE)
+    valid = prof.get("kernel_digest") == kernel_digest("k_classic_f64", P._abi.LIB_PATH)
+    traffic = prof.get("traffic_bytes_per_launch") if valid else None
+    flops = prof.get("fp64_flops_per_launch") if valid else None
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 4),
                 "traffic_unit": "GB per launch",
                 "kernel": "k_classic_f64", "mean_launch_us": round(mean_launch_ms * 1e3, 2),
+                "median_launch_us": round(float(np.median(launch_ms)) * 1e3, 2),
+                "min_launch_us": round(float(launch_ms.min()) * 1e3, 2),
+                "launch_rsd": round(float(launch_ms.std() / launch_ms.mean()), 4),
                 "bytes_per_launch": int(mean_bytes), "update_fraction": round(
                     float(np.mean([u / n for u in updates[1:]])), 4)}
+    if traffic is not None:
+        roofline["traffic_GBps"] = round(traffic / (mean_launch_ms * 1e-3) / 1e9, 1)
+    # FP64 roofline of the same kernel: counter FLOPs per launch over the live
+    # mean launch duration, against the FP64 vector peak
+    roofline["fp64"] = None if flops is None else {
+        "achieved": round(flops / (mean_launch_ms * 1e-3) / 1e12, 3), "peak": FP64_PEAK_TFS,
+        "unit": "TFLOP/s", "frac": round(flops / (mean_launch_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
+        "flops_per_eval": round(flops / n, 1)}
 
     extras = {}
     if not args.no_extras:
@@ -420,6 +433,19 @@ def main():
                "kind": "oracle",
                "sample": f"{m} seeded-random particles of the same {n_side}^3 fields x all {len(radii)} radii "
                          f"({dt:.1f} s of oracle time)"}
+        # single-core rate on the first 2^16 sampled particles, all radii
+        m1 = min(m, 1 << 16)
+        nthreads = oracle.threads()
+        oracle.set_threads(1)
+        z = (np.zeros(m1), np.full(m1, -1, np.int32), np.full(m1, np.inf))
+        dt1 = 0.0
+        for r in range(len(radii)):
+            sample = slabs[r][:, idx[:m1]].cpu().numpy()
+            c0 = time.perf_counter()
+            oracle.update_radius(sample, r, g, *z, reset=(r == 0))
+            dt1 += time.perf_counter() - c0
+        oracle.set_threads(nthreads)
+        cpu["value_1core"] = round(m1 * len(radii) / dt1, 1)
         # the sampled particles also serve as a parity spot check of this run
         got_F = Fmax[idx].cpu().numpy()
         got_R = Rmax[idx].cpu().numpy()

@@ -69,9 +69,13 @@ typedef enum { PINO_CLASSIC = 0, PINO_TABULATED = 1 } pino_method;
  *                    FP64 for nearly degenerate eigenvalues and for the final
  *                    polish of the collapse root (Classic).
  *   PINO_SURROGATE : FP32 Hessians; a small network predicts the collapse
- *                    growth factor, one FP64 Newton step certifies it, and
- *                    particles that fail the certificate take the full FP64
- *                    solve (Classic only; weights from pino_mlp.h). */
+ *                    growth factor and one FP64 Newton step refines it; the
+ *                    result is accepted only if the first root of the
+ *                    collapse condition provably lies within certify_rtol of
+ *                    it.  Particles that fail are queued and take the full
+ *                    FP64 solve in a second kernel of the same eval (items
+ *                    are processed in chunks of 2^24 particles, the queue's
+ *                    size).  Classic only; weights from pino_mlp.h. */
 typedef enum { PINO_FP64 = 0, PINO_MIXED = 1, PINO_SURROGATE = 2 } pino_precision;
 
 /* eval flags */
@@ -112,8 +116,10 @@ typedef struct {
     const pino_table_knots *table;   /* PINO_TABULATED only, else NULL */
     const void *mlp;                 /* PINO_SURROGATE only: blob from pino_mlp_export */
     int64_t mlp_bytes;
-    double certify_rtol;             /* PINO_SURROGATE: accepted relative Newton
-                                        residual; <= 0 selects 1e-7 */
+    double certify_rtol;             /* PINO_SURROGATE: certified relative accuracy
+                                        of the collapse growth factor (the root is
+                                        bracketed within u (1 -/+ rtol)); <= 0
+                                        selects 5e-7 */
 } pino_config;
 
 /* One realisation at one smoothing radius. */

@@ -68,7 +68,8 @@ pino_status pino_mlp_free(pino_mlp *m);
  * precision): x [n][4] (device), w [n] (device, may be NULL) = 1/(l1 D_c)
  * from the full FP64 solve, or 0 where the particle never collapses or the
  * network is not consulted (l1 < 0.1 max|l|).  omega_m comes from the
- * item's growth table. */
+ * item's growth table.  At most 2^28 particles per call (PINO_ERR_ARG
+ * otherwise). */
 pino_status pino_collapse_features(pino_ctx *ctx, const pino_item *item, float *x, float *w, void *hip_stream);
 
 /* The BF16-MFMA network of a PINO_SURROGATE context on given inputs

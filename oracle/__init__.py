@@ -62,6 +62,7 @@ def lib():
         L.orc_table_build.argtypes = [ctypes.c_int] * 3 + [_D] * 3
         L.orc_table_build.restype = ctypes.c_int
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_update_radius.argtypes = ([ctypes.c_int64] + [_D] * 6 + [ctypes.c_int32, ctypes.c_int, ctypes.c_int]
                                         + [_D] * 3 + [ctypes.c_int] * 3 + [_D] * 5
                                         + [ctypes.c_int, _D, _I32, _D])
@@ -84,6 +85,11 @@ def _f64(a):
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads for the parallel loops that follow (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def eig3(h):

@@ -370,6 +370,17 @@ int orc_threads(void)
 #endif
 }
 
+/* Thread count used by later parallel loops (n >= 1). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void orc_update_radius(int64_t n, const double *hxx, const double *hyy, const double *hzz, const double *hxy,
                        const double *hxz, const double *hyz, int32_t radius_index, int method, int nk,
                        const double *gD, const double *ga, const double *gM, int nx, int ny, int nd,

@@ -43,6 +43,11 @@ struct pino_ctx {
     void* d_mlp = nullptr;
     double certify_rtol = 5e-7;
     int64_t* d_counters = nullptr;
+    // surrogate: queue of deferred particle indices (chunk-relative), one
+    // segment per block, and the segments' lengths
+    int32_t* d_queue = nullptr;
+    int32_t* d_qcount = nullptr;
+    int64_t queue_cap = 0;
     std::vector<double> omega;
 
     bool broken = false;

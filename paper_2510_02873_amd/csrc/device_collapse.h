@@ -33,22 +33,58 @@ __host__ __device__ __forceinline__ double rcp2(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// 1/sqrt(x) for normal x > 0: hardware estimate refined by two
+// Newton-Raphson steps y <- y + y (1 - x y^2)/2 (each squares the relative
+// error).
+__host__ __device__ __forceinline__ double rsq2(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// One refinement step: enough where the reciprocal scales a small
+// correction (a Newton or Halley step), whose own error it then barely moves.
+__host__ __device__ __forceinline__ double rcp1(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// cos(acos(r)/3) for r in [-1, 1], given h = (1 + r)/2 (which callers form in
+// FP64, so that it keeps its digits next to r = -1).  As a function of
+// t = sqrt(h) = cos(acos(r)/2) it is cos(2 acos(t)/3), analytic on [0, 1]
+// (the square-root branch point of c(r) at r = -1 becomes a regular point),
+// so a degree-7 polynomial in t holds it to 2.8e-8 relative (coefficients
+// from gen_cos_acos3.py); with FP32 rounding the result is within ~1e-7.
+__host__ __device__ __forceinline__ float cos_acos3(float h)
+{
+    const float t = sqrtf(fmaxf(h, 0.0f));
+    float c = 0.0012316048973092788f;
+    c = fmaf(c, t, -0.0064512453556797196f);
+    c = fmaf(c, t, 0.016541704297467527f);
+    c = fmaf(c, t, -0.030569944240758228f);
+    c = fmaf(c, t, 0.052957431674725962f);
+    c = fmaf(c, t, -0.11105763313282863f);
+    c = fmaf(c, t, 0.57734809605336668f);
+    return fmaf(c, t, 0.50000001420359497f);
+}
+
 // x = 2 cos(phi), the root of x^3 - 3x = 2r on [1, 2] (phi = acos(r)/3, the
-// largest eigenvalue) or on [-2, -1] (phi + 2 pi/3, the smallest): an FP32
-// estimate from the trigonometric form, then two FP64 Halley steps.  Outside
-// the nearly repeated band (|1 -+ r| < kNearRepeated, handled by deflation)
-// the estimate is within ~3e-5 and two steps leave < 1e-16.
+// largest eigenvalue) or on [-2, -1] (phi + 2 pi/3, the smallest, which is
+// minus the largest root for -r).  The FP32 estimate 2 cos_acos3 is within
+// ~2e-7; one FP64 Halley step (cubic convergence) leaves < 1e-20 where the
+// roots are well separated and ~1e-15 at the edge of the nearly repeated band
+// (|1 -+ r| < kNearRepeated, where the pair comes from deflation instead).
 __host__ __device__ __forceinline__ double depressed_root(double r, bool largest)
 {
-    const float th = acosf((float)r) * (1.0f / 3.0f) + (largest ? 0.0f : 2.0943951f);
-    double x = 2.0 * (double)__cosf(th);
-    for (int k = 0; k < 2; ++k) {
-        const double f = x * (x * x - 3.0) - 2.0 * r;
-        const double f1 = 3.0 * (x * x - 1.0);
-        const double f2 = 6.0 * x;
-        x -= (2.0 * f * f1) * rcp2(2.0 * f1 * f1 - f * f2);
-    }
-    return x;
+    const double rr = largest ? r : -r;
+    double x = 2.0 * (double)cos_acos3((float)(0.5 + 0.5 * rr));
+    const double f = x * (x * x - 3.0) - 2.0 * rr;
+    const double f1 = 3.0 * (x * x - 1.0);
+    const double f2 = 6.0 * x;
+    x -= (2.0 * f * f1) * rcp1(2.0 * f1 * f1 - f * f2);
+    return largest ? x : -x;
 }
 
 // ---------------------------------------------------------------------------
@@ -70,9 +106,14 @@ __host__ __device__ __forceinline__ void eig_moments(const Hess64& h, double& q,
     const double dx = h.xx - q, dy = h.yy - q, dz = h.zz - q;
     const double off = h.xy * h.xy + h.xz * h.xz + h.yz * h.yz;
     const double ss = dx * dx + dy * dy + dz * dz + 2.0 * off;
-    p = sqrt(ss * (1.0 / 6.0));
+    // p and 1/p from one refined reciprocal square root; below the normal
+    // range (no anisotropy to speak of) the matrix is taken as isotropic
+    const double v = ss * (1.0 / 6.0);
+    const bool iso = !(v >= 2.2250738585072014e-308);
+    const double iv = rsq2(iso ? 1.0 : v);
+    p = iso ? 0.0 : v * iv;
+    const double ip = iso ? 0.0 : iv;
     const double det = dx * (dy * dz - h.yz * h.yz) - h.xy * (h.xy * dz - h.yz * h.xz) + h.xz * (h.xy * h.yz - dy * h.xz);
-    const double ip = p > 0.0 ? rcp2(p) : 0.0;
     r = 0.5 * det * (ip * ip * ip);
     r = fmin(fmax(r, -1.0), 1.0);
 }
@@ -251,11 +292,14 @@ __host__ __device__ __forceinline__ float top_root_guess(double b, double c)
     float t;
     if (d <= 0.0f) {
         const float m = 2.0f * sqrtf(fmaxf(-p3, 0.0f));
-        const float arg = fminf(fmaxf(3.0f * Q / (P * m), -1.0f), 1.0f);
-        t = m * __cosf(acosf(arg) * (1.0f / 3.0f));
+        const float arg = fminf(fmaxf(3.0f * Q * __builtin_amdgcn_rcpf(P * m), -1.0f), 1.0f);
+        t = m * cos_acos3(0.5f + 0.5f * arg);
     } else {
-        const float A = -copysignf(cbrtf(0.5f * fabsf(Q) + sqrtf(d)), Q);
-        t = A != 0.0f ? A - P / (3.0f * A) : 0.0f;
+        // cube root from the hardware base-2 logarithm and exponential
+        // (a few ulp; the FP64 polish that follows absorbs it)
+        const float y = 0.5f * fabsf(Q) + sqrtf(d);
+        const float A = -copysignf(__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(y) * (1.0f / 3.0f)), Q);
+        t = A != 0.0f ? A - P * __builtin_amdgcn_rcpf(3.0f * A) : 0.0f;
     }
     return t + (1.0f / 3.0f);
 }
@@ -309,7 +353,7 @@ __host__ __device__ __forceinline__ bool top_root_w(const CubicU& k, double& w)
         const double q = ((w - 1.0) * w + k.b) * w + k.c;
         const double q1 = (3.0 * w - 2.0) * w + k.b;
         const double q2 = 6.0 * w - 2.0;
-        step = (2.0 * q * q1) * rcp2(2.0 * q1 * q1 - q * q2);
+        step = (2.0 * q * q1) * rcp1(2.0 * q1 * q1 - q * q2);
         w -= step;
     }
     const bool converged = fabs(step) <= 1e-7 * fabs(w);

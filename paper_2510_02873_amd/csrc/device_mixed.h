@@ -35,7 +35,7 @@ __host__ __device__ __forceinline__ bool eig_top_f32(const Hess32& h, float& l1,
     const float ip = p > 0.0f ? 1.0f / p : 0.0f;
     float r = 0.5f * det * (ip * ip * ip);
     r = fminf(fmaxf(r, -1.0f), 1.0f);
-    l1 = q + 2.0f * p * __cosf(acosf(r) * (1.0f / 3.0f));
+    l1 = q + 2.0f * p * cos_acos3(0.5f + 0.5f * r);
     const float mu2 = h.xx * h.yy + h.xx * h.zz + h.yy * h.zz - off;
     s = tr - l1;
     pp = mu2 - l1 * s;

@@ -66,9 +66,15 @@ __global__ void __launch_bounds__(64) k_spline_build(const double* __restrict__ 
 // staged once per workgroup in LDS.  Hessian loads are coalesced SoA reads
 // that bypass the caches' retention (each value is read once).
 // ---------------------------------------------------------------------------
+// Items reach the per-radius kernels in chunks of at most kChunk particles,
+// so that an element's byte offset i * sizeof(T) fits in 32 bits: loads and
+// stores then take the scalar-base + 32-bit vector-offset form, one offset
+// shared by every array with the same element size.
+constexpr int64_t kChunk = int64_t(1) << 28;
+
 struct ItemArgs {
     const double* h[6];
-    int64_t n;
+    int64_t n;                // <= kChunk in the per-radius kernels
     const double* growth;  // [D | a | M], nk each
     int nk;
     GrowthIndex gi;        // idx points to global memory; kernels stage it
@@ -79,6 +85,18 @@ struct ItemArgs {
     int32_t* Rmax;
     double* acoll;
 };
+
+template <typename T>
+__device__ __forceinline__ const T* elem(const T* base, uint32_t i)
+{
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ T* elem(T* base, uint32_t i)
+{
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T));
+}
 
 __device__ __forceinline__ void stage(double* dst, const double* __restrict__ src, int count)
 {
@@ -104,15 +122,15 @@ __host__ __device__ inline size_t growth_lds_bytes(int nk, int nb)
     return 3 * (size_t)nk * sizeof(double) + (((size_t)nb * sizeof(int) + 7) / 8) * 8;
 }
 
-__device__ __forceinline__ Hess64 load_h64(const ItemArgs& a, int64_t i)
+__device__ __forceinline__ Hess64 load_h64(const ItemArgs& a, uint32_t i)
 {
     Hess64 h;
-    h.xx = __builtin_nontemporal_load(a.h[0] + i);
-    h.yy = __builtin_nontemporal_load(a.h[1] + i);
-    h.zz = __builtin_nontemporal_load(a.h[2] + i);
-    h.xy = __builtin_nontemporal_load(a.h[3] + i);
-    h.xz = __builtin_nontemporal_load(a.h[4] + i);
-    h.yz = __builtin_nontemporal_load(a.h[5] + i);
+    h.xx = __builtin_nontemporal_load(elem(a.h[0], i));
+    h.yy = __builtin_nontemporal_load(elem(a.h[1], i));
+    h.zz = __builtin_nontemporal_load(elem(a.h[2], i));
+    h.xy = __builtin_nontemporal_load(elem(a.h[3], i));
+    h.xz = __builtin_nontemporal_load(elem(a.h[4], i));
+    h.yz = __builtin_nontemporal_load(elem(a.h[5], i));
     return h;
 }
 
@@ -122,20 +140,21 @@ __device__ __forceinline__ Hess64 load_h64(const ItemArgs& a, int64_t i)
 // a_coll are read to be written back).  a(D_c), D_c = 1/F, is evaluated only
 // where needed: on update, or for every element from the running maximum
 // when finalizing.
-__device__ __forceinline__ void update_max(const ItemArgs& a, const double* g, const GrowthIndex& gi, int64_t i,
+__device__ __forceinline__ void update_max(const ItemArgs& a, const double* g, const GrowthIndex& gi, uint32_t i,
                                            double F, double fm)
 {
     const bool upd = F > fm;
     const double fnew = upd ? F : fm;
-    const int32_t rm = a.reset ? -1 : a.Rmax[i];
-    a.Fmax[i] = fnew;
-    a.Rmax[i] = upd ? a.radius : rm;
+    const int32_t rm = a.reset ? -1 : *elem(a.Rmax, i);
+    *elem(a.Fmax, i) = fnew;
+    *elem(a.Rmax, i) = upd ? a.radius : rm;
     if (a.acoll) {
+        double* ac = elem(a.acoll, i);
         if (a.finalize) {
-            a.acoll[i] = fnew > 0.0 ? growth_invert(g, a.nk, rcp2(fnew), gi) : kInf;
+            *ac = fnew > 0.0 ? growth_invert(g, a.nk, rcp2(fnew), gi) : kInf;
         } else {
-            const double am = a.reset ? kInf : a.acoll[i];
-            a.acoll[i] = upd ? growth_invert(g, a.nk, rcp2(F), gi) : am;
+            const double am = a.reset ? kInf : *ac;
+            *ac = upd ? growth_invert(g, a.nk, rcp2(F), gi) : am;
         }
     }
 }
@@ -153,21 +172,22 @@ k_classic_f64(ItemArgs a)
     // Software pipeline: the loads of the next grid-stride element are issued
     // before the eigen/root arithmetic of the current one, so their latency
     // hides behind it (the kernel has registers to spare for the second set).
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     Hess64 hn{};
     double fn = 0.0;
-    if (i < a.n) {
+    if (i < n) {
         hn = load_h64(a, i);
-        fn = a.reset ? 0.0 : a.Fmax[i];
+        fn = a.reset ? 0.0 : *elem(a.Fmax, i);
     }
-    for (; i < a.n; i += stride) {
+    for (; i < n; i += stride) {
         const Hess64 h = hn;
         const double fm = fn;
-        const int64_t next = i + stride;
-        if (next < a.n) {
+        const uint32_t next = i + stride;
+        if (next < n) {
             hn = load_h64(a, next);
-            fn = a.reset ? 0.0 : a.Fmax[next];
+            fn = a.reset ? 0.0 : *elem(a.Fmax, next);
         }
         double l1, s, pp;
         eig_top(h, l1, s, pp);
@@ -238,21 +258,22 @@ __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
         ds[k] = t.dk[k] * t.scale;
     __syncthreads();
     // Next element's loads issued ahead of the current arithmetic.
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     Hess64 hn{};
     double fn = 0.0;
-    if (i < a.n) {
+    if (i < n) {
         hn = load_h64(a, i);
-        fn = a.reset ? 0.0 : a.Fmax[i];
+        fn = a.reset ? 0.0 : *elem(a.Fmax, i);
     }
-    for (; i < a.n; i += stride) {
+    for (; i < n; i += stride) {
         const Hess64 h = hn;
         const double fm = fn;
-        const int64_t next = i + stride;
-        if (next < a.n) {
+        const uint32_t next = i + stride;
+        if (next < n) {
             hn = load_h64(a, next);
-            fn = a.reset ? 0.0 : a.Fmax[next];
+            fn = a.reset ? 0.0 : *elem(a.Fmax, next);
         }
         double l1, l2, l3;
         eig_all(h, l1, l2, l3);

@@ -9,15 +9,15 @@
 
 namespace pino {
 
-__device__ __forceinline__ Hess32 load_h32(const ItemArgs& a, int64_t i)
+__device__ __forceinline__ Hess32 load_h32(const ItemArgs& a, uint32_t i)
 {
     Hess32 h;
-    h.xx = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[0]) + i);
-    h.yy = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[1]) + i);
-    h.zz = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[2]) + i);
-    h.xy = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[3]) + i);
-    h.xz = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[4]) + i);
-    h.yz = __builtin_nontemporal_load(reinterpret_cast<const float*>(a.h[5]) + i);
+    h.xx = __builtin_nontemporal_load(elem(reinterpret_cast<const float*>(a.h[0]), i));
+    h.yy = __builtin_nontemporal_load(elem(reinterpret_cast<const float*>(a.h[1]), i));
+    h.zz = __builtin_nontemporal_load(elem(reinterpret_cast<const float*>(a.h[2]), i));
+    h.xy = __builtin_nontemporal_load(elem(reinterpret_cast<const float*>(a.h[3]), i));
+    h.xz = __builtin_nontemporal_load(elem(reinterpret_cast<const float*>(a.h[4]), i));
+    h.yz = __builtin_nontemporal_load(elem(reinterpret_cast<const float*>(a.h[5]), i));
     return h;
 }
 
@@ -35,20 +35,21 @@ __device__ __forceinline__ GrowthIndex stage_growth32(float* lds, const float* _
 }
 
 // same whole-line update as update_max, with a(D) in FP32
-__device__ __forceinline__ void update_max_f32(const ItemArgs& a, const float* g, const GrowthIndex& gi, int64_t i,
+__device__ __forceinline__ void update_max_f32(const ItemArgs& a, const float* g, const GrowthIndex& gi, uint32_t i,
                                                double F, double fm)
 {
     const bool upd = F > fm;
     const double fnew = upd ? F : fm;
-    const int32_t rm = a.reset ? -1 : a.Rmax[i];
-    a.Fmax[i] = fnew;
-    a.Rmax[i] = upd ? a.radius : rm;
+    const int32_t rm = a.reset ? -1 : *elem(a.Rmax, i);
+    *elem(a.Fmax, i) = fnew;
+    *elem(a.Rmax, i) = upd ? a.radius : rm;
     if (a.acoll) {
+        double* ac = elem(a.acoll, i);
         if (a.finalize) {
-            a.acoll[i] = fnew > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew), gi) : kInf;
+            *ac = fnew > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew), gi) : kInf;
         } else {
-            const double am = a.reset ? kInf : a.acoll[i];
-            a.acoll[i] = upd ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F), gi) : am;
+            const double am = a.reset ? kInf : *ac;
+            *ac = upd ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F), gi) : am;
         }
     }
 }
@@ -60,21 +61,22 @@ __global__ void __launch_bounds__(256) k_classic_mixed(ItemArgs a, const float* 
     const GrowthIndex gi = stage_growth32(g, growth32, a);
     __syncthreads();
     // Next element's loads issued ahead of the current arithmetic.
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     Hess32 hn{};
     double fn = 0.0;
-    if (i < a.n) {
+    if (i < n) {
         hn = load_h32(a, i);
-        fn = a.reset ? 0.0 : a.Fmax[i];
+        fn = a.reset ? 0.0 : *elem(a.Fmax, i);
     }
-    for (; i < a.n; i += stride) {
+    for (; i < n; i += stride) {
         const Hess32 h = hn;
         const double fm = fn;
-        const int64_t next = i + stride;
-        if (next < a.n) {
+        const uint32_t next = i + stride;
+        if (next < n) {
             hn = load_h32(a, next);
-            fn = a.reset ? 0.0 : a.Fmax[next];
+            fn = a.reset ? 0.0 : *elem(a.Fmax, next);
         }
         float l1f, sf, ppf;
         double l1, s, pp;

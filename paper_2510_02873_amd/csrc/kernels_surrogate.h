@@ -8,21 +8,30 @@
 namespace pino {
 
 // The Hessian of an item as FP64 (FP64 inputs) or widened FP32 inputs.
-__device__ __forceinline__ Hess64 load_h(const ItemArgs& a, int64_t i, bool f32)
+__device__ __forceinline__ Hess64 load_h(const ItemArgs& a, uint32_t i, bool f32)
 {
     return f32 ? widen(load_h32(a, i)) : load_h64(a, i);
 }
 
 // Per particle: FP64 eigenvalues of the FP32 Hessian, the BF16 network's
-// prediction, one certified FP64 Newton step, or the full solve.  The loop is
+// prediction and the FP64 certificate.  Certified and gated particles (F from
+// the certificate, or 0) update the maxima here.  The others are deferred:
+// each block appends their indices to its own segment of `queue`
+// (queue + blockIdx.x * seg, seg >= the particles a block visits) through an
+// LDS counter, one LDS atomic per wave, and stores the segment's length in
+// qcount[blockIdx.x]; their maxima are carried over unchanged, for
+// k_surrogate_fallback to finish with the full solve.  The loop is
 // wave-uniform (all 64 lanes run the network together); lanes past the end
-// compute on zeros and store nothing.  counters: certified, fallback, gated
-// (wave totals added once per wave).
+// compute on zeros and store nothing.  counters: certified, consulted but not
+// certified, not consulted (wave totals added once per wave at the end).
 __global__ void __launch_bounds__(256) k_surrogate(ItemArgs a, const NetFrags* __restrict__ net, double sigma,
                                                   double omega_m, double rtol,
-                                                  unsigned long long* __restrict__ counters)
+                                                  unsigned long long* __restrict__ counters,
+                                                  int32_t* __restrict__ queue, int32_t* __restrict__ qcount,
+                                                  int64_t seg)
 {
     extern __shared__ double lds[];
+    __shared__ int fill;
     const GrowthIndex gi = stage_growth(lds, a);
     NetFrags* N = reinterpret_cast<NetFrags*>(lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double));
     {
@@ -31,18 +40,22 @@ __global__ void __launch_bounds__(256) k_surrogate(ItemArgs a, const NetFrags* _
         for (int k = threadIdx.x; k < (int)(sizeof(NetFrags) / sizeof(int4)); k += blockDim.x)
             dst[k] = src[k];
     }
+    if (threadIdx.x == 0)
+        fill = 0;
     __syncthreads();
+    int32_t* myq = queue + (int64_t)blockIdx.x * seg;
     const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned long long ncert = 0, nfall = 0, ngate = 0;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < a.n; base += stride) {
-        const int64_t i = base + lane;
-        const bool valid = i < a.n;
+        const bool valid = base + lane < a.n;
+        const uint32_t i = (uint32_t)(base + lane);
         Hess64 h{};
         double fm = 0.0;
         if (valid) {
             h = widen(load_h32(a, i));
-            fm = a.reset ? 0.0 : a.Fmax[i];
+            fm = a.reset ? 0.0 : *elem(a.Fmax, i);
         }
         double l1, s, pp;
         eig_top(h, l1, s, pp);
@@ -59,12 +72,21 @@ __global__ void __launch_bounds__(256) k_surrogate(ItemArgs a, const NetFrags* _
             if (consult && certify(k, (double)y, rtol, u1)) {
                 F = l1 * rcp2(u1);
                 cert = true;
-            } else {
-                F = classic_F(l1, s, pp);
             }
         }
+        // l1 > 0 and not certified: deferred to the full solve
+        const bool defer = valid && l1 > 0.0 && !cert;
+        const uint64_t dm = __ballot(defer);
+        if (dm) {
+            int slot = 0;
+            if (lane == 0)
+                slot = atomicAdd(&fill, (int)__popcll(dm));
+            slot = __shfl(slot, 0, 64);
+            if (defer)
+                myq[slot + (int)__popcll(dm & below)] = (int32_t)i;
+        }
         ncert += __popcll(__ballot(valid && cert));
-        nfall += __popcll(__ballot(valid && consult && !cert));
+        nfall += __popcll(__ballot(consult && !cert));
         ngate += __popcll(__ballot(valid && !consult));
         if (valid)
             update_max(a, lds, gi, i, F, fm);
@@ -73,6 +95,36 @@ __global__ void __launch_bounds__(256) k_surrogate(ItemArgs a, const NetFrags* _
         atomicAdd(counters + 0, ncert);
         atomicAdd(counters + 1, nfall);
         atomicAdd(counters + 2, ngate);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        qcount[blockIdx.x] = fill;
+}
+
+// The deferred particles of one k_surrogate pass (same grid: block b takes
+// the segment block b filled): FP64 eigenvalues of the same widened FP32
+// Hessian, the full Classic solve, and the max update against what
+// k_surrogate stored (the maxima carried over from the earlier radii, and at
+// FINALIZE their a(D_c), rewritten here when F wins).
+__global__ void __launch_bounds__(256) k_surrogate_fallback(ItemArgs a, const int32_t* __restrict__ queue,
+                                                           const int32_t* __restrict__ qcount, int64_t seg)
+{
+    extern __shared__ double lds[];
+    const GrowthIndex gi = stage_growth(lds, a);
+    __syncthreads();
+    const int count = qcount[blockIdx.x];
+    const int32_t* myq = queue + (int64_t)blockIdx.x * seg;
+    for (int q = threadIdx.x; q < count; q += blockDim.x) {
+        const uint32_t i = (uint32_t)myq[q];
+        double l1, s, pp;
+        eig_top(widen(load_h32(a, i)), l1, s, pp);
+        const double F = classic_F(l1, s, pp);
+        if (F > *elem(a.Fmax, i)) {
+            *elem(a.Fmax, i) = F;
+            *elem(a.Rmax, i) = a.radius;
+            if (a.acoll)
+                *elem(a.acoll, i) = growth_invert(lds, a.nk, rcp2(F), gi);
+        }
     }
 }
 
@@ -84,7 +136,7 @@ __global__ void __launch_bounds__(256) k_features(ItemArgs a, bool f32, double s
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n)
         return;
-    const Hess64 h = load_h(a, i, f32);
+    const Hess64 h = load_h(a, (uint32_t)i, f32);
     double l1, s, pp;
     eig_top(h, l1, s, pp);
     float x[4];

@@ -97,6 +97,14 @@ pino::NetFrags build_frags(const float* P)
     return f;
 }
 
+// Deferred-particle queue of the surrogate path: items are processed in
+// chunks of at most kQueueChunk particles, by at most kQueueBlocks blocks of
+// 256 threads, each block owning a queue segment as long as the particles it
+// visits; the segments then total less than kQueueChunk + 256 kQueueBlocks.
+constexpr int64_t kQueueChunk = int64_t(1) << 24;
+constexpr int64_t kQueueBlocks = 4096;
+constexpr int64_t kQueueCap = kQueueChunk + 256 * kQueueBlocks;
+
 pino_status mlp_upload(pino_ctx* c, const void* blob, int64_t)
 {
     std::vector<float> P(pino::kNParam);
@@ -109,6 +117,12 @@ pino_status mlp_upload(pino_ctx* c, const void* blob, int64_t)
         e = hipMalloc((void**)&c->d_counters, 4 * sizeof(int64_t));
     if (e == hipSuccess)
         e = hipMemset(c->d_counters, 0, 4 * sizeof(int64_t));
+    if (e == hipSuccess) {
+        c->queue_cap = kQueueCap;
+        e = hipMalloc((void**)&c->d_queue, (size_t)c->queue_cap * sizeof(int32_t));
+    }
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&c->d_qcount, (size_t)kQueueBlocks * sizeof(int32_t));
     if (e != hipSuccess) {
         c->broken = true;
         c->err = std::string("surrogate upload: ") + hipGetErrorString(e);
@@ -128,14 +142,39 @@ inline pino_status launch_fail(pino_ctx* c, const char* what)
     return PINO_OK;
 }
 
-pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemArgs& a, uint32_t, hipStream_t st,
-                             int grid, int block)
+// One item in chunks of at most kQueueChunk particles (queue indices are
+// chunk-relative int32): per chunk, the surrogate pass, then the full solve of
+// the deferred particles, block b of the second kernel taking the queue
+// segment that block b of the first filled.
+pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemArgs& a0, uint32_t, hipStream_t st,
+                             int, int block)
 {
-    const size_t lds = pino::growth_lds_bytes(a.nk, a.gi.nb) + sizeof(pino::NetFrags);
-    hipLaunchKernelGGL(pino::k_surrogate, dim3(grid), dim3(block), lds, st, a,
-                       static_cast<const pino::NetFrags*>(c->d_mlp), it.sigma_R, c->omega[it.cosmo],
-                       c->certify_rtol, reinterpret_cast<unsigned long long*>(c->d_counters));
-    return launch_fail(c, "k_surrogate launch");
+    const size_t lds_fb = pino::growth_lds_bytes(a0.nk, a0.gi.nb);
+    const size_t lds = lds_fb + sizeof(pino::NetFrags);
+    auto* cnt = reinterpret_cast<unsigned long long*>(c->d_counters);
+    const auto* net = static_cast<const pino::NetFrags*>(c->d_mlp);
+    const int64_t cap_blocks = std::min<int64_t>((int64_t)c->cu_count * c->blocks_per_cu, kQueueBlocks);
+    for (int64_t start = 0; start < a0.n; start += kQueueChunk) {
+        pino::ItemArgs a = a0;
+        a.n = std::min<int64_t>(kQueueChunk, a0.n - start);
+        for (int k = 0; k < 6; ++k)
+            a.h[k] = reinterpret_cast<const double*>(reinterpret_cast<const char*>(a0.h[k]) + start * sizeof(float));
+        a.Fmax = a0.Fmax + start;
+        a.Rmax = a0.Rmax + start;
+        a.acoll = a0.acoll ? a0.acoll + start : nullptr;
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((a.n + block - 1) / block, cap_blocks));
+        // a block visits at most ceil(n / stride) groups of `block` particles
+        const int64_t stride = grid * block;
+        const int64_t seg = (a.n + stride - 1) / stride * block;
+        hipLaunchKernelGGL(pino::k_surrogate, dim3((unsigned)grid), dim3(block), lds, st, a, net, it.sigma_R,
+                           c->omega[it.cosmo], c->certify_rtol, cnt, c->d_queue, c->d_qcount, seg);
+        hipLaunchKernelGGL(pino::k_surrogate_fallback, dim3((unsigned)grid), dim3(block), lds_fb, st, a,
+                           static_cast<const int32_t*>(c->d_queue), static_cast<const int32_t*>(c->d_qcount), seg);
+        const pino_status ps = launch_fail(c, "surrogate launch");
+        if (ps != PINO_OK)
+            return ps;
+    }
+    return PINO_OK;
 }
 
 pino_status mlp_fail(pino_mlp* m, hipError_t e, const char* what)

@@ -77,8 +77,8 @@ bool validate_config(const pino_config* cfg, std::string& why)
             return false;
         }
     }
-    if (cfg->certify_rtol < 0.0 || !std::isfinite(cfg->certify_rtol)) {
-        why = "certify_rtol must be finite and >= 0";
+    if (cfg->certify_rtol < 0.0 || !(cfg->certify_rtol < 1e-2)) {
+        why = "certify_rtol must be in [0, 1e-2)";
         return false;
     }
     if (cfg->precision == PINO_MIXED && cfg->method != PINO_CLASSIC) {
@@ -217,7 +217,8 @@ void free_all(pino_ctx* c)
 {
     if (!c)
         return;
-    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tab, c->d_dscaled, c->d_tmp, c->d_mlp, c->d_counters};
+    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tab,
+                    c->d_dscaled, c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_qcount};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -226,6 +227,8 @@ void free_all(pino_ctx* c)
     c->d_growth32 = nullptr;
     c->d_mlp = nullptr;
     c->d_counters = nullptr;
+    c->d_queue = nullptr;
+    c->d_qcount = nullptr;
 }
 
 pino_status init_impl(const pino_config* cfg, pino_ctx* c)
@@ -363,8 +366,7 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
     a.Rmax = it.Rmax;
     a.acoll = it.a_coll;
     const int block = 256;
-    const int grid = grid_for(c, it.n, block);
-    size_t lds = growth_lds_bytes(a.nk, a.gi.nb);
+    const size_t lds = growth_lds_bytes(a.nk, a.gi.nb);
 
     if (c->method == PINO_TABULATED) {
         // per-radius table: copy F into the interleaved table and rebuild the
@@ -383,28 +385,44 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
         PINO_HIP(c, hipGetLastError());
     }
 
-    if (c->precision == PINO_FP64) {
-        if (c->method == PINO_CLASSIC) {
-            hipLaunchKernelGGL(k_classic_f64, dim3(grid), dim3(block), lds, st, a);
+    // the kernels index with 32-bit byte offsets: chunks of at most kChunk
+    const size_t esize = c->precision == PINO_FP64 ? sizeof(double) : sizeof(float);
+    const ItemArgs a0 = a;
+    for (int64_t start = 0; start < a0.n; start += kChunk) {
+        a.n = std::min<int64_t>(kChunk, a0.n - start);
+        for (int k = 0; k < 6; ++k)
+            a.h[k] = reinterpret_cast<const double*>(reinterpret_cast<const char*>(a0.h[k]) + start * esize);
+        a.Fmax = a0.Fmax + start;
+        a.Rmax = a0.Rmax + start;
+        a.acoll = a0.acoll ? a0.acoll + start : nullptr;
+        const int g = grid_for(c, a.n, block);
+        pino_status ps = PINO_OK;
+        if (c->precision == PINO_FP64) {
+            if (c->method == PINO_CLASSIC) {
+                hipLaunchKernelGGL(k_classic_f64, dim3(g), dim3(block), lds, st, a);
+            } else {
+                TabArgs t;
+                t.xk = c->d_tknots;
+                t.yk = c->d_tknots + c->nx;
+                t.dk = c->d_tknots + c->nx + c->ny;
+                t.nx = c->nx;
+                t.ny = c->ny;
+                t.nd = c->nd;
+                t.scale = it.sigma_R;
+                t.tab = c->d_tab;
+                const size_t lds_t = lds + (size_t)(c->nx + c->ny + c->nd) * sizeof(double);
+                hipLaunchKernelGGL(k_tabulated_f64, dim3(g), dim3(block), lds_t, st, a, t);
+            }
+            PINO_HIP(c, hipGetLastError());
+        } else if (c->precision == PINO_MIXED) {
+            ps = launch_mixed(c, it, a, flags, st, g, block);
         } else {
-            TabArgs t;
-            t.xk = c->d_tknots;
-            t.yk = c->d_tknots + c->nx;
-            t.dk = c->d_tknots + c->nx + c->ny;
-            t.nx = c->nx;
-            t.ny = c->ny;
-            t.nd = c->nd;
-            t.scale = it.sigma_R;
-            t.tab = c->d_tab;
-            lds += (size_t)(c->nx + c->ny + c->nd) * sizeof(double);
-            hipLaunchKernelGGL(k_tabulated_f64, dim3(grid), dim3(block), lds, st, a, t);
+            ps = launch_surrogate(c, it, a, flags, st, g, block);
         }
-        PINO_HIP(c, hipGetLastError());
-        return PINO_OK;
+        if (ps != PINO_OK)
+            return ps;
     }
-    if (c->precision == PINO_MIXED)
-        return launch_mixed(c, it, a, flags, st, grid, block);
-    return launch_surrogate(c, it, a, flags, st, grid, block);
+    return PINO_OK;
 }
 
 }  // namespace
@@ -524,6 +542,10 @@ pino_status pino_collapse_features(pino_ctx* ctx, const pino_item* item, float* 
     }
     if (!(std::isfinite(it.sigma_R) && it.sigma_R > 0.0)) {
         ctx->err = "sigma_R must be finite and > 0";
+        return PINO_ERR_ARG;
+    }
+    if (it.n > kChunk) {
+        ctx->err = "pino_collapse_features takes at most 2^28 particles per call";
         return PINO_ERR_ARG;
     }
     if (it.n == 0)

@@ -342,14 +342,24 @@ __device__ __forceinline__ float net_bf16(const NetFrags& N, const float x[4])
 
 // ---------------------------------------------------------------------------
 // Certificate.  From the prediction u0 = 1/y (u = l1 D), one FP64 Newton
-// step u1 = u0 - g(u0)/g'(u0).  u1 is accepted as the collapse when
-//   (i)   |g(u1)/g'(u1)| <= rtol u1 (the next Newton correction, i.e. the
-//         error of u1 to first order, is below rtol),
-//   (ii)  g'(u1) < 0 (a downward crossing),
-//   (iii) no local minimum of g with g <= 0 lies in (0, u1) (so no earlier
-//         crossing): the first positive critical point of g is its first
-//         local minimum, u_m = 1/(b + sqrt(b^2 + 3c)).
+// step u1 = u0 - g(u0)/g'(u0).  u1 is accepted as the collapse when the
+// smallest positive root of g provably lies in [lo, hi] = u1 (1 -/+ rtol):
+//   (i)   g(lo) > e and g(hi) < -e, with e a bound on the rounding error of
+//         the evaluation of g (so g changes sign downward inside [lo, hi]);
+//   (ii)  g has no local minimum with g <= 0 below lo.  g(0) = 1 and
+//         g'(0) = -1, so the first positive critical point of g,
+//         u_m = 1/(b + sqrt(b^2 + 3c)), is a local minimum; if g(u_m) > 0 or
+//         u_m >= lo, g stays positive on (0, lo] (after u_m, g rises to its
+//         local maximum and then falls monotonically to g(lo) > 0).
+// Together (i) and (ii) put the first crossing within rtol of u1, whatever
+// the prediction was; a prediction near another root is rejected by (ii).
 // ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ double g_bound(const CubicU& k, double u)
+{
+    // 8 ulp of the sum of the magnitudes of the Horner terms
+    return 8.0 * 1.1102230246251565e-16 * (1.0 + u * (1.0 + u * (fabs(k.b) + fabs(k.c) * u)));
+}
+
 __host__ __device__ __forceinline__ bool certify(const CubicU& k, double y, double rtol, double& u1)
 {
     if (!(y > 0.0) || !isfinite(y))
@@ -358,18 +368,17 @@ __host__ __device__ __forceinline__ bool certify(const CubicU& k, double y, doub
     const double g0 = g_u(k, u0);
     const double d0 = -1.0 + u0 * (2.0 * k.b + 3.0 * k.c * u0);
     u1 = u0 - g0 * rcp2(d0);
-    const double g1 = g_u(k, u1);
-    const double d1 = -1.0 + u1 * (2.0 * k.b + 3.0 * k.c * u1);
-    const bool small = fabs(g1) <= rtol * u1 * fabs(d1);
-    const bool down = d1 < 0.0;
+    const double lo = u1 * (1.0 - rtol);
+    const double hi = u1 * (1.0 + rtol);
+    const bool bracket = g_u(k, lo) > g_bound(k, lo) && g_u(k, hi) < -g_bound(k, hi);
     const double disc = k.b * k.b + 3.0 * k.c;
     const double den = k.b + sqrt(fmax(disc, 0.0));
     bool earlier = false;
     if (disc >= 0.0 && den > 0.0) {
         const double um = rcp2(den);
-        earlier = um < u1 && g_u(k, um) <= 0.0;
+        earlier = um < lo && g_u(k, um) <= 0.0;
     }
-    return u1 > 0.0 && small && down && !earlier && isfinite(u1);
+    return lo > 0.0 && bracket && !earlier && isfinite(u1);
 }
 
 }  // namespace pino

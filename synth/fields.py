@@ -122,10 +122,14 @@ def field(n_side: int, box: float, seed: int, cosmo: Cosmology = Cosmology(), de
     return _Field(n_side, box, seed, cosmo, device)
 
 
-def grid_sigma_gauss(n_side: int, box: float, R, cosmo: Cosmology = Cosmology()):
+def grid_sigma_gauss(n_side: int, box: float, R, cosmo: Cosmology = Cosmology(), device=None):
     """Expected rms of the smoothed field on this grid: sqrt(sum_k P W^2 / L^3)
     over the kept modes (full complex grid, so each mode counts once).  R may
-    be a number or a sequence (then a list is returned)."""
+    be a number or a sequence (then a list is returned).  With a torch
+    `device` the sum runs there over the real-FFT half grid (the kz = 0 plane
+    once, the other kept kz planes twice), which is what large grids need."""
+    if device is not None:
+        return _grid_sigma_gauss_torch(n_side, box, R, cosmo, device)
     radii = np.atleast_1d(np.asarray(R, dtype=np.float64))
     k1 = np.fft.fftfreq(n_side, d=1.0 / n_side) * (2.0 * np.pi / box)
     keep = np.ones(n_side)
@@ -146,4 +150,18 @@ def grid_sigma_gauss(n_side: int, box: float, R, cosmo: Cosmology = Cosmology())
         for j, Rj in enumerate(radii):
             total[j] += float(np.sum(pk * np.exp(-k2 * Rj * Rj)))
     out = [float(np.sqrt(t / box ** 3)) for t in total]
+    return out if np.ndim(R) else out[0]
+
+
+def _grid_sigma_gauss_torch(n_side, box, R, cosmo, device):
+    radii = np.atleast_1d(np.asarray(R, dtype=np.float64))
+    dev = torch.device(device)
+    k1, kz = _wavenumbers(n_side, box, dev)
+    mask = _mode_mask(n_side, dev)
+    wz = torch.full((n_side // 2 + 1,), 2.0, dtype=torch.float64, device=dev)
+    wz[0] = 1.0
+    weight = mask * wz[None, None, :]
+    k2 = k1[:, None, None] ** 2 + k1[None, :, None] ** 2 + kz[None, None, :] ** 2
+    pk = power_spectrum_torch(torch.sqrt(k2), cosmo) * weight
+    out = [float(torch.sqrt(torch.sum(pk * torch.exp(-k2 * (Rj * Rj))) / box ** 3)) for Rj in radii]
     return out if np.ndim(R) else out[0]

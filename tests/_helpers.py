@@ -71,3 +71,30 @@ def compare(ref, got, rel=REL_TOL, tie_mask=None, label=""):
             assert np.all(da <= rel), f"{label}: max rel a_coll err {da.max():.3e}"
             stats["max_rel_a"] = float(da.max())
     return stats
+
+
+EPS32 = 2.0 ** -24
+
+
+def rel_stats(x):
+    """max, p99.9 and mean of an array of relative errors."""
+    x = np.asarray(x)
+    if x.size == 0:
+        return {"max": 0.0, "p99.9": 0.0, "mean": 0.0}
+    return {"max": float(np.max(x)), "p99.9": float(np.percentile(x, 99.9)), "mean": float(np.mean(x))}
+
+
+def mixed_bound(orc, slabs):
+    """Per-particle tolerance on D_c of the mixed-precision path over the
+    given radii (FP64 arrays (6, n)): D_c is homogeneous of degree -1 in the
+    eigenvalues and the FP32 eigenvalue is off by a few eps32 |H|_F, so
+    |dD_c/D_c| <= 64 eps32 |H|_F / l1; the max over radii is taken, since
+    which radius wins is not known in advance."""
+    b = None
+    for h in slabs:
+        lam, _ = orc.points(h)
+        hn = np.sqrt(np.sum(h[:3] ** 2, axis=0) + 2 * np.sum(h[3:] ** 2, axis=0))
+        with np.errstate(divide="ignore"):
+            br = np.where(lam[:, 0] > 0, 64 * EPS32 * hn / np.maximum(lam[:, 0], 1e-300), np.inf)
+        b = br if b is None else np.maximum(b, br)
+    return b

@@ -17,3 +17,24 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def trained_net():
+    """(blob, params, loss history) of a network trained by the library's
+    kernels on pairs from 96^3 fields of two cosmologies (small and quick;
+    the benchmark trains the full one)."""
+    import synth
+    from paper_2510_02873_amd import surrogate
+    cosmos = [synth.Cosmology(0.3, 0.8), synth.Cosmology(0.27, 0.8)]
+    tables = [(*synth.growth_table(c.omega_m), c.omega_m) for c in cosmos]
+    fields = []
+    for k, c in enumerate(cosmos):
+        fld = synth.fields.field(96, 150.0, 31 + k, c, device="cuda")
+        for R in (6.0, 3.0, 1.5, 0.8):
+            fields.append((fld.hessian(R).float(), synth.grid_sigma_gauss(96, 150.0, R, c), k))
+    x, w = surrogate.training_pairs(fields, tables)
+    print(f"training pairs: {x.shape[0]}", flush=True)
+    blob, params, hist = surrogate.train(x, w, steps=3000, batch=8192, lr_max=3e-3, seed=1, log_every=1000)
+    print("loss history", hist, flush=True)
+    return blob, params, hist

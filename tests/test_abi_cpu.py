@@ -3,6 +3,7 @@ exports every function the header declares, and argument validation (a pure
 host step that runs before any HIP call) rejects bad configurations."""
 
 import ctypes
+import struct
 import os
 import re
 import subprocess
@@ -44,7 +45,7 @@ def _cfg(P, **kw):
 
 
 @pytest.mark.parametrize("bad", ["version", "method", "precision", "device", "nonmono", "short", "table",
-                                 "surrogate_blob"])
+                                 "surrogate_blob", "rtol_big", "rtol_nan", "rtol_negative"])
 def test_init_rejects_bad_config(bad):
     import paper_2510_02873_amd as P
     a = np.geomspace(1e-3, 1.0, 16)
@@ -64,12 +65,21 @@ def test_init_rejects_bad_config(bad):
         cfg = P.Config([(a[:3], a[:3])])
     elif bad == "table":
         cfg = _cfg(P, method=P.PINO_TABULATED)
+    elif bad.startswith("rtol"):
+        rtol = {"rtol_big": 0.5, "rtol_nan": float("nan"), "rtol_negative": -1e-7}[bad]
+        # a well-formed blob (header + 8705 zero parameters), so only the
+        # tolerance is at fault
+        from paper_2510_02873_amd import _abi
+        blob = b"PINOMLP1" + struct.pack("<ii", 1, _abi.PINO_MLP_PARAMS) + bytes(4 * _abi.PINO_MLP_PARAMS)
+        cfg = _cfg(P, precision=P.PINO_SURROGATE, mlp_blob=blob, certify_rtol=rtol)
     else:
         cfg = _cfg(P, precision=P.PINO_SURROGATE, mlp_blob=b"\x00" * 16)
     with pytest.raises(P.PinoError) as e:
         P.pino_collapse_init(cfg)
     assert e.value.status == P.PINO_ERR_ARG
     assert P.pino_collapse_last_error(None)
+    if bad.startswith("rtol"):
+        assert "certify_rtol" in P.pino_collapse_last_error(None)
 
 
 def test_init_null_and_nan():

@@ -15,11 +15,9 @@ import pytest
 import torch
 
 import synth
-from tests._helpers import c1_inputs
+from tests._helpers import EPS32, c1_inputs, mixed_bound, rel_stats
 
 pytestmark = pytest.mark.gpu
-
-EPS32 = 2.0 ** -24
 
 
 @pytest.fixture(scope="module")
@@ -32,22 +30,11 @@ def _rel(a, b):
     return np.abs(a - b) / np.abs(b)
 
 
-def _stats(x):
-    return {"max": float(np.max(x)), "p99.9": float(np.percentile(x, 99.9)), "mean": float(np.mean(x))}
+_stats = rel_stats
 
 
 def _bound(orc, slabs32):
-    """Per-particle tolerance on D_c over all radii (the smallest l1 seen on
-    the winning side is not known in advance, so use each radius' bound and
-    take the max over radii)."""
-    b = None
-    for h in slabs32:
-        lam, _ = orc.points(h)
-        hn = np.sqrt(np.sum(h[:3] ** 2, axis=0) + 2 * np.sum(h[3:] ** 2, axis=0))
-        with np.errstate(divide="ignore"):
-            br = np.where(lam[:, 0] > 0, 64 * EPS32 * hn / np.maximum(lam[:, 0], 1e-300), np.inf)
-        b = br if b is None else np.maximum(b, br)
-    return b
+    return mixed_bound(orc, slabs32)
 
 
 def test_mixed_c1(pkg, orc):

@@ -118,21 +118,8 @@ def _orc():
 
 
 @pytest.fixture(scope="module")
-def trained(P):
-    """A network trained by the library's kernels on pairs from 96^3 fields
-    of two cosmologies (small and quick; the benchmark trains the full one)."""
-    Pk, A = P
-    from paper_2510_02873_amd import surrogate
-    cosmos = [synth.Cosmology(0.3, 0.8), synth.Cosmology(0.27, 0.8)]
-    tables = [(*synth.growth_table(c.omega_m), c.omega_m) for c in cosmos]
-    fields = []
-    for k, c in enumerate(cosmos):
-        for h, sig in _fields(96, 150.0, [6.0, 3.0, 1.5, 0.8], 31 + k, c):
-            fields.append((h, sig, k))
-    x, w = surrogate.training_pairs(fields, tables)
-    print(f"training pairs: {x.shape[0]}", flush=True)
-    blob, params, hist = surrogate.train(x, w, steps=3000, batch=8192, lr_max=3e-3, seed=1, log_every=1000)
-    print("loss history", hist, flush=True)
+def trained(P, trained_net):
+    blob, params, hist = trained_net
     assert hist[-1][1] < 0.2 * hist[0][1]
     return blob, params
 

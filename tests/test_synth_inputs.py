@@ -55,6 +55,19 @@ def test_trace_and_covariance():
     assert abs(np.mean(h[3] * h[4])) < 0.1 * s2 / 15
 
 
+def test_grid_sigma_half_grid_sum_equals_full_grid_sum():
+    """The real-FFT half-grid sum (device version) counts every kept mode of
+    the full complex grid exactly once, for even and odd sides."""
+    c = Cosmology(0.27, 0.85)
+    for n, box in ((24, 90.0), (17, 60.0)):
+        radii = [0.7, 2.0, 5.0]
+        full = grid_sigma_gauss(n, box, radii, c)
+        half = grid_sigma_gauss(n, box, radii, c, device="cpu")
+        assert half == pytest.approx(full, rel=1e-12)
+    assert grid_sigma_gauss(24, 90.0, 2.0, c, device="cpu") == pytest.approx(grid_sigma_gauss(24, 90.0, 2.0, c),
+                                                                              rel=1e-12)
+
+
 def test_doroshkevich_all_negative_fraction():
     f = make_field(64, 200.0, 6, Cosmology())
     h = f.hessian(3.0).numpy()
