@@ -71,22 +71,22 @@ pino::NetFrags build_frags(const float* P)
     NetFrags f;
     std::memset(&f, 0, sizeof(f));
     for (int mt = 0; mt < 4; ++mt)
-        for (int l = 0; l < 64; ++l)
-            for (int j = 0; j < 4; ++j) {
-                const int o = 16 * mt + l % 16;
-                const int k = 4 * (l / 16) + j;
-                // layer 1: lane groups 0, 1 carry W_hi, group 2 W_lo (see NetFrags)
-                const float wv = P[kOffW1 + o * kIn + j];
+        for (int l = 0; l < 64; ++l) {
+            const int o = 16 * mt + l % 16;
+            const int g = l / 16;
+            for (int j = 0; j < 8; ++j) {
+                // layer 1: group 0 (W_hi, W_hi), group 1 (W_lo, 0) (see NetFrags)
+                const float wv = P[kOffW1 + o * kIn + (j & 3)];
                 const short whi = bf16_bits(wv);
                 const short wlo = bf16_bits(wv - bf16_value(whi));
-                const int grp = l / 16;
-                f.w1[mt][l][j] = grp <= 1 ? whi : (grp == 2 ? wlo : (short)0);
-                for (int kt = 0; kt < 4; ++kt) {
-                    const int kk = 16 * kt + k;
+                f.w1[mt][l][j] = g == 0 ? whi : (g == 1 && j < 4 ? wlo : (short)0);
+                for (int kt = 0; kt < 2; ++kt) {
+                    const int kk = k32_neuron(kt, g, j);
                     f.w2[mt][kt][l][j] = bf16_bits(P[kOffW2 + o * kH + kk]);
                     f.w3[mt][kt][l][j] = bf16_bits(P[kOffW3 + o * kH + kk]);
                 }
             }
+        }
     for (int o = 0; o < kH; ++o) {
         f.b1[o] = P[kOffB1 + o];
         f.b2[o] = P[kOffB2 + o];

@@ -234,32 +234,42 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ P
 }
 
 // ---------------------------------------------------------------------------
-// BF16 MFMA inference.  v_mfma_f32_16x16x16bf16_1k: lane l holds
-// A[i = l%16][k = 4(l/16)+j], B[k = 4(l/16)+j][n = l%16] and returns
-// D[i = 4(l/16)+j][n = l%16], j = 0..3.  With weights as A (rows = output
-// neurons, 16 per tile mt) and activations as B (columns = 16 particles of
-// tile nt), a layer's output tile (mt, nt) is exactly the B operand of the
-// next layer's k-tile kt = mt: the whole network stays in registers.
-// The weight fragments are laid out at init so that each lane reads its 8
-// bytes contiguously from LDS.
+// BF16 MFMA inference with v_mfma_f32_16x16x32_bf16: lane l (g = l/16,
+// q = l%16) holds A[i = q][k = 8g + j] and B[k = 8g + j][n = q], j = 0..7, and
+// receives D[i = 4g + j][n = q], j = 0..3.  Weights are A (rows = 16 output
+// neurons of tile mt), activations B (columns = the 16 particles of group nt).
+// A layer's output tiles mt = 2kt and 2kt + 1 hold, in lane (g, q), neurons
+// 32kt + 4g + j and 32kt + 16 + 4g + j of particle q: together, the 8 values
+// the lane supplies as B of the next layer's K tile kt, once the next layer's
+// weight columns are permuted to match (done when the fragments are built).
+// So the network stays in registers; the FP32 -> BF16 step is the hardware
+// packed convert (round to nearest even).
 // ---------------------------------------------------------------------------
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Layer 1 has K = 4 inputs and the MFMA K = 16: the padding carries a hi/lo
-// split of inputs and weights, k = 0..3: W_hi x_hi, 4..7: W_hi x_lo,
-// 8..11: W_lo x_hi (12..15 zero), so the first layer is accurate to ~2^-16
-// although its operands are BF16.
+// Layer 1 has K = 4 inputs in a K = 32 tile: lanes of group 0 carry
+// (x_hi, x_lo) against (W_hi, W_hi), group 1 carries (x_hi, 0) against
+// (W_lo, 0), groups 2 and 3 are zero, so the first layer is accurate to
+// ~2^-16 although its operands are BF16.
 struct NetFrags {
-    bf16x4 w1[4][64];     // [mt][lane]
-    bf16x4 w2[4][4][64];  // [mt][kt][lane]
-    bf16x4 w3[4][4][64];
+    s16x8 w1[4][64];     // [mt][lane], BF16 bits
+    s16x8 w2[4][2][64];  // [mt][kt][lane]
+    s16x8 w3[4][2][64];
     float b1[kH], b2[kH], b3[kH], w4[kH];
     float b4;
     float pad[3];
 };
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs)
+// Input neuron of K tile kt carried at slot j of lane group g (see above).
+__host__ __device__ __forceinline__ int k32_neuron(int kt, int g, int j)
+{
+    return 32 * kt + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+}
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs; host side)
 __host__ __device__ __forceinline__ short bf16_bits(float f)
 {
     uint32_t u = __builtin_bit_cast(uint32_t, f);
@@ -272,19 +282,29 @@ __host__ __device__ __forceinline__ float bf16_value(short b)
     return __builtin_bit_cast(float, (uint32_t)(uint16_t)b << 16);
 }
 
-__device__ __forceinline__ bf16x4 pack_relu(f32x4 v)
+__device__ __forceinline__ bf16x4 to_bf16(f32x4 v)
 {
-    bf16x4 r;
-    r[0] = bf16_bits(fmaxf(v[0], 0.0f));
-    r[1] = bf16_bits(fmaxf(v[1], 0.0f));
-    r[2] = bf16_bits(fmaxf(v[2], 0.0f));
-    r[3] = bf16_bits(fmaxf(v[3], 0.0f));
-    return r;
+    return __builtin_convertvector(v, bf16x4);
+}
+
+__device__ __forceinline__ f32x4 relu4(f32x4 v)
+{
+    return f32x4{fmaxf(v[0], 0.0f), fmaxf(v[1], 0.0f), fmaxf(v[2], 0.0f), fmaxf(v[3], 0.0f)};
+}
+
+__device__ __forceinline__ bf16x8 join(bf16x4 a, bf16x4 b)
+{
+    return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 __device__ __forceinline__ f32x4 bias4(const float* b, int mt, int g)
 {
     return *reinterpret_cast<const f32x4*>(b + 16 * mt + 4 * g);
+}
+
+__device__ __forceinline__ bf16x8 frag(const s16x8& w)
+{
+    return __builtin_bit_cast(bf16x8, w);
 }
 
 // Network output for this lane's particle (all 64 lanes of the wave must
@@ -294,35 +314,31 @@ __device__ __forceinline__ float net_bf16(const NetFrags& N, const float x[4])
     const int l = threadIdx.x & 63;
     const int q = l & 15;
     const int g = l >> 4;
+    const bf16x4 zero4 = to_bf16(f32x4{0.0f, 0.0f, 0.0f, 0.0f});
     float out = 0.0f;
     for (int nt = 0; nt < 4; ++nt) {
         const int src = 16 * nt + q;
-        bf16x4 bx;
-        for (int j = 0; j < 4; ++j) {
-            const float f = __shfl(x[j], src, 64);
-            const short hi = bf16_bits(f);
-            const short lo = bf16_bits(f - bf16_value(hi));
-            bx[j] = (g == 0 || g == 2) ? hi : (g == 1 ? lo : (short)0);
-        }
+        const f32x4 f{__shfl(x[0], src, 64), __shfl(x[1], src, 64), __shfl(x[2], src, 64), __shfl(x[3], src, 64)};
+        const bf16x4 hi = to_bf16(f);
+        const bf16x4 lo = to_bf16(f - __builtin_convertvector(hi, f32x4));
+        const bf16x8 bx = join(g <= 1 ? hi : zero4, g == 0 ? lo : zero4);
         f32x4 acc[4];
-        bf16x4 hb[4];
-        for (int mt = 0; mt < 4; ++mt) {
-            acc[mt] = bias4(N.b1, mt, g);
-            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w1[mt][l], bx, acc[mt], 0, 0, 0);
-        }
         for (int mt = 0; mt < 4; ++mt)
-            hb[mt] = pack_relu(acc[mt]);
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(N.w1[mt][l]), bx, bias4(N.b1, mt, g), 0, 0, 0);
+        bf16x8 hb[2];
+        for (int kt = 0; kt < 2; ++kt)
+            hb[kt] = join(to_bf16(relu4(acc[2 * kt])), to_bf16(relu4(acc[2 * kt + 1])));
         for (int mt = 0; mt < 4; ++mt) {
             acc[mt] = bias4(N.b2, mt, g);
-            for (int kt = 0; kt < 4; ++kt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w2[mt][kt][l], hb[kt], acc[mt], 0, 0, 0);
+            for (int kt = 0; kt < 2; ++kt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(N.w2[mt][kt][l]), hb[kt], acc[mt], 0, 0, 0);
         }
-        for (int mt = 0; mt < 4; ++mt)
-            hb[mt] = pack_relu(acc[mt]);
+        for (int kt = 0; kt < 2; ++kt)
+            hb[kt] = join(to_bf16(relu4(acc[2 * kt])), to_bf16(relu4(acc[2 * kt + 1])));
         for (int mt = 0; mt < 4; ++mt) {
             acc[mt] = bias4(N.b3, mt, g);
-            for (int kt = 0; kt < 4; ++kt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w3[mt][kt][l], hb[kt], acc[mt], 0, 0, 0);
+            for (int kt = 0; kt < 2; ++kt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(N.w3[mt][kt][l]), hb[kt], acc[mt], 0, 0, 0);
         }
         // output layer in FP32: this lane's 16 neurons of column q, then
         // the sum over the four lanes that share the column
