@@ -10,7 +10,8 @@ window W = exp(-k^2 R^2 / 2),
 
     H_ij(k) = (k_i k_j / k^2) W(kR) delta(k),     H_ij(k = 0) = 0,
 
-so that tr H = delta_R.  delta(k) is the real-FFT half grid of delta(x) on a
+so that tr H = delta_R; modes at the Nyquist index of an even side are
+dropped (see kept_modes).  delta(k) is the real-FFT half grid of delta(x) on a
 periodic n^3 grid of side L (numpy.fft.rfftn convention: forward transform
 unnormalised, axes x, y, z with z halved), wavenumbers numpy.fft.fftfreq
 (the Nyquist index of an even side carries -n/2) along x and y and
@@ -33,13 +34,27 @@ def wavenumbers(n_side: int, box: float):
     return k1[:, None, None], k1[None, :, None], kz[None, None, :]
 
 
+def kept_modes(n_side: int):
+    """1 where a mode enters the Hessian, 0 at k = 0 and, for an even side, at
+    the Nyquist index along any axis (a wave at the Nyquist frequency has no
+    defined derivative on the grid: +n/2 and -n/2 alias)."""
+    keep1 = np.ones(n_side)
+    keepz = np.ones(n_side // 2 + 1)
+    if n_side % 2 == 0:
+        keep1[n_side // 2] = 0.0
+        keepz[n_side // 2] = 0.0
+    keep = keep1[:, None, None] * keep1[None, :, None] * keepz[None, None, :]
+    keep[0, 0, 0] = 0.0
+    return keep
+
+
 def hessian(delta_k: np.ndarray, n_side: int, box: float, R: float) -> np.ndarray:
     """(6, n^3) FP64 Hessian of the potential smoothed at radius R."""
     kx, ky, kz = wavenumbers(n_side, box)
     k2 = kx ** 2 + ky ** 2 + kz ** 2
     kv = (kx, ky, kz)
     with np.errstate(divide="ignore", invalid="ignore"):
-        base = np.where(k2 > 0, np.exp(-0.5 * k2 * R * R) / k2, 0.0) * delta_k
+        base = np.where(kept_modes(n_side) > 0, np.exp(-0.5 * k2 * R * R) / k2, 0.0) * delta_k
     out = np.empty((6, n_side ** 3))
     for c, (i, j) in enumerate(PAIRS):
         out[c] = np.fft.irfftn(base * (kv[i] * kv[j]), s=(n_side,) * 3, axes=(0, 1, 2)).reshape(-1)

@@ -61,3 +61,23 @@ def test_constant_field_has_no_hessian():
     n = 10
     delta_k = np.fft.rfftn(np.full((n, n, n), 3.0))
     assert np.max(np.abs(ofield.hessian(delta_k, n, 50.0, 2.0))) <= 1e-15
+
+
+def test_nyquist_waves_are_dropped():
+    """A wave at the Nyquist index of an even side has no defined derivative
+    on the grid (+n/2 and -n/2 alias); the stage drops it, and keeps the
+    neighbouring modes."""
+    n, box = 12, 60.0
+    x = np.arange(n) * (box / n)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    kn = np.pi / (box / n)                       # Nyquist wavenumber
+    k1 = 2 * np.pi / box
+    nyq = np.cos(kn * X + k1 * Y) + np.cos(k1 * X + kn * Z)
+    # (only the forward transform's rounding leaks into kept modes)
+    assert np.max(np.abs(ofield.hessian(np.fft.rfftn(nyq), n, box, 1.0))) <= 1e-13
+    mode = (n // 2 - 1, 2, -1)
+    k0 = k1 * np.asarray(mode, dtype=float)
+    wave = np.cos(k0[0] * X + k0[1] * Y + k0[2] * Z)
+    got = ofield.hessian(np.fft.rfftn(wave + nyq), n, box, 1.0)
+    want = ofield.plane_wave_hessian(n, box, mode, 1.0)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
