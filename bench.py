@@ -58,7 +58,7 @@ def _time_steps(step, steps, stream):
     return t0.elapsed_time(t1) / steps
 
 
-def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, steps):
+def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, steps, dk=None):
     """Secondary rates on the same resident fields: mixed precision (FP32
     copies of the Hessians) and the Tabulated method (64 x 64 x 128 tables
     filled per radius by the library's Classic kernel on the table's sample
@@ -123,7 +123,44 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                         "ms_per_step": round(ms, 4), "table": "64x64x128 per radius, rebuilt on device",
                         "rel_F_vs_classic_median": float(np.median(relt))}
     tcol.close()
+
+    if dk is not None:
+        out["field_fused"] = measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps)
     return out
+
+
+def measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps):
+    """The Hessian stage on the device feeding the collapse with no host
+    round trip (pino_field_collapse): per radius, delta(k) -> six weighted
+    copies -> six inverse real FFTs (hipFFT) -> the same FP64 collapse
+    kernel.  Reports evaluations/s with the FFTs included, the Hessian stage
+    alone, and the agreement with the plain run on the generator's Hessians."""
+    import torch
+
+    last = len(radii) - 1
+    flags = P.PINO_EVAL_RESET | P.PINO_EVAL_FINALIZE
+    with P.Field(n_side, cfg["box"]) as f:
+        Ff, Rf, Af = col.outputs(n)
+        items = [P.make_item(None, Ff, Rf, Af if r == last else None, radius_index=r, n=n)
+                 for r in range(len(radii))]
+        ms = _time_steps(lambda: f.collapse(col.ctx, dk, radii, items, flags=flags, stream=stream), steps, stream)
+        H = torch.empty((6, n), dtype=torch.float64, device=dk.device)
+
+        def hstep():
+            for R in radii:
+                f.hessian(dk, R, H, stream=stream)
+
+        ms_h = _time_steps(hstep, steps, stream)
+        del H
+    big = F64 > 1e-6
+    rel = ((1 / Ff[big] - 1 / F64[big]).abs() * F64[big]).max().item()
+    res = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s", "ms_per_step": round(ms, 4),
+           "hessian_stage_ms_per_step": round(ms_h, 4),
+           "workload": f"delta(k) of the same {n_side}^3 field -> {len(radii)} radii, FFTs included",
+           "max_rel_Dc_vs_generator_hessians": rel,
+           "index_mismatch_frac": float((Rf != R64).double().mean().item())}
+    log(f"field-fed collapse {res['value']:.3e} evals/s ({ms:.2f} ms/step, Hessian stage {ms_h:.2f} ms)")
+    return res
 
 
 def measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps):
@@ -310,6 +347,7 @@ def main():
     a, D = synth.growth_table(cfg["cosmo"].omega_m, cfg["n_growth"])
     fld = synth.fields.field(n_side, cfg["box"], cfg["seed"], cfg["cosmo"], device=dev)
     slabs = [fld.hessian(R) for R in radii]
+    dk = fld.dk.contiguous()      # delta(k), for the device Hessian stage leg
     del fld
     torch.cuda.synchronize()
     log(f"inputs ready: n={n} radii={len(radii)} in {time.time() - t0:.1f}s "
@@ -412,7 +450,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras = measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, args.steps)
+        extras = measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, args.steps, dk)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -143,12 +143,16 @@ def pino_collapse_free(ctx):
 
 
 def make_item(h, Fmax, Rmax, a_coll=None, radius_index=0, cosmo=0, sigma_R=1.0, table_F=None, n=None):
-    """h: sequence of 6 device tensors (or a (6, n) tensor); outputs device tensors."""
+    """h: sequence of 6 device tensors (or a (6, n) tensor), or None with n
+    given (items of pino_field_collapse); outputs device tensors."""
     it = pino_item()
-    comps = [h[c] for c in range(6)]
-    it.n = int(comps[0].numel()) if n is None else int(n)
-    for c in range(6):
-        it.h[c] = comps[c].data_ptr()
+    if h is None:
+        it.n = int(n)
+    else:
+        comps = [h[c] for c in range(6)]
+        it.n = int(comps[0].numel()) if n is None else int(n)
+        for c in range(6):
+            it.h[c] = comps[c].data_ptr()
     it.cosmo = cosmo
     it.radius_index = radius_index
     it.sigma_R = sigma_R
@@ -357,6 +361,86 @@ class Batch:
         if self.plan is not None:
             _check(_bind_batch().pino_collapse_batch_free(self.plan))
             self.plan = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# include/pino_field.h
+# ---------------------------------------------------------------------------
+_field_bound = False
+
+
+def _bind_field():
+    global _field_bound
+    L = lib()
+    if not _field_bound:
+        c_p = ctypes.c_void_p
+        L.pino_field_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(c_p)]
+        L.pino_field_hessian.argtypes = [c_p, c_p, ctypes.c_double, c_p, c_p]
+        L.pino_field_hessian_f32.argtypes = [c_p, c_p, ctypes.c_double, c_p, c_p]
+        L.pino_field_collapse.argtypes = [c_p, c_p, c_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(pino_item),
+                                          ctypes.c_int32, ctypes.c_uint32, c_p]
+        L.pino_field_free.argtypes = [c_p]
+        L.pino_field_last_error.argtypes = [c_p]
+        L.pino_field_last_error.restype = ctypes.c_char_p
+        for name in ("pino_field_create", "pino_field_hessian", "pino_field_hessian_f32", "pino_field_collapse",
+                     "pino_field_free"):
+            getattr(L, name).restype = ctypes.c_int
+        _field_bound = True
+    return L
+
+
+def pino_field_last_error(f=None) -> str:
+    return _bind_field().pino_field_last_error(f).decode()
+
+
+def _check_field(status, f=None):
+    if status != PINO_OK:
+        raise PinoError(status, pino_field_last_error(f))
+
+
+class Field:
+    """A planned Hessian stage for an n^3 grid of side box (pino_field.h).
+    delta_k: complex128 device tensor of shape (n, n, n//2 + 1)."""
+
+    def __init__(self, n_side, box, device=0):
+        out = ctypes.c_void_p()
+        _check_field(_bind_field().pino_field_create(device, n_side, box, ctypes.byref(out)))
+        self.f = out.value
+        self.n = n_side
+
+    def _dk(self, delta_k):
+        n = self.n
+        if tuple(delta_k.shape) != (n, n, n // 2 + 1) or not delta_k.is_contiguous() or \
+                str(delta_k.dtype) != "torch.complex128":
+            raise ValueError("delta_k must be a contiguous complex128 tensor of shape (n, n, n//2+1)")
+        return delta_k.data_ptr()
+
+    def hessian(self, delta_k, R, H, stream=None):
+        """H: (6, n^3) float64 or float32 device tensor, written in place."""
+        if H.shape != (6, self.n ** 3) or not H.is_contiguous():
+            raise ValueError("H must be a contiguous (6, n^3) tensor")
+        fn = _bind_field().pino_field_hessian if str(H.dtype) == "torch.float64" else \
+            _bind_field().pino_field_hessian_f32
+        _check_field(fn(self.f, self._dk(delta_k), float(R), H.data_ptr(), _stream(stream)), self.f)
+        return H
+
+    def collapse(self, ctx, delta_k, radii, items, flags=0, stream=None):
+        """items: list of pino_item (h ignored), one per radius."""
+        r = (ctypes.c_double * max(1, len(radii)))(*[float(x) for x in radii])
+        arr = (pino_item * max(1, len(items)))(*items)
+        _check_field(_bind_field().pino_field_collapse(self.f, ctx, self._dk(delta_k), r, arr, len(items), flags,
+                                                       _stream(stream)), self.f)
+
+    def close(self):
+        if self.f is not None:
+            _check_field(_bind_field().pino_field_free(self.f))
+            self.f = None
 
     def __enter__(self):
         return self

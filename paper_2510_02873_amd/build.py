@@ -22,10 +22,14 @@ FLAGS = [
 ]
 
 
+# hipFFT for the Hessian stage (pino_field.h)
+LINK = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lhipfft"]
+
+
 def build(verbose: bool = False) -> str:
     src = os.path.join(CSRC, "pino_collapse.hip")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, src, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, src, "-o", tmp, *LINK]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

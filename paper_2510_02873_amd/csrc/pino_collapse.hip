@@ -615,3 +615,4 @@ pino_status pino_collapse_surrogate_stats(pino_ctx* ctx, int64_t* certified, int
 }  // extern "C"
 
 #include "batch_api.h"
+#include "field_api.h"

@@ -100,3 +100,13 @@ def test_eval_and_free_null_ctx():
     L = P.lib()
     assert L.pino_collapse_eval(None, None, 0, 0, None) == P.PINO_ERR_ARG
     assert L.pino_collapse_free(None) == P.PINO_OK
+
+
+@pytest.mark.parametrize("n_side,box", [(1, 100.0), (2000, 100.0), (32, 0.0), (32, float("nan")), (32, -5.0)])
+def test_field_create_rejects_bad_grid(n_side, box):
+    """pino_field_create validates before any HIP call."""
+    import paper_2510_02873_amd as P
+    with pytest.raises(P.PinoError) as e:
+        P.Field(n_side, box)
+    assert e.value.status == P.PINO_ERR_ARG
+    assert "n_side" in P._abi.pino_field_last_error(None)

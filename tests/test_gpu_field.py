@@ -1,0 +1,165 @@
+"""Hessian stage on the device (pino_field.h) against the oracle's numpy-FFT
+Hessians, and the collapse fed from it without leaving the device against
+the oracle's collapse of the oracle's Hessians.
+
+Gates: FP64 Hessians within 1e-12 of max|H| (two FFT libraries in FP64);
+FP32 Hessians within 2e-6 of max|H| (FP32 transform rounding, ~eps32 log n);
+collapse through the FP64 stage: the plain-path gate (1e-9 relative on D_c
+and a_coll, radius index exact except at near-ties)."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import field as ofield
+from tests._helpers import compare, near_tie_mask, rel_stats
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2510_02873_amd as P
+    return P
+
+
+def _dk_generator(n, box, seed):
+    """delta(k) of the input generator (k = 0 and Nyquist modes zeroed)."""
+    return synth.fields.field(n, box, seed, synth.Cosmology(), device="cuda").dk.contiguous()
+
+
+def _dk_white(n, seed):
+    """rfftn of white noise: power in every mode, Nyquist and k = 0 included."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    return torch.fft.rfftn(torch.randn((n, n, n), dtype=torch.float64, device="cuda", generator=g)).contiguous()
+
+
+@pytest.mark.parametrize("n,source", [(32, "generator"), (33, "white"), (48, "white"), (20, "generator")])
+def test_hessian_vs_oracle(pkg, n, source):
+    box = 3.0 * n
+    dk = _dk_generator(n, box, 7) if source == "generator" else _dk_white(n, 8)
+    dk_host = dk.cpu().numpy()
+    print(f"field {n}^3 ({source})", flush=True)
+    with pkg.Field(n, box) as f:
+        for R in (0.0, 2.0, 7.5):
+            ref = ofield.hessian(dk_host, n, box, R)
+            scale = np.max(np.abs(ref))
+            H = torch.empty((6, n ** 3), dtype=torch.float64, device="cuda")
+            f.hessian(dk, R, H)
+            H32 = torch.empty((6, n ** 3), dtype=torch.float32, device="cuda")
+            f.hessian(dk, R, H32)
+            torch.cuda.synchronize()
+            e64 = np.max(np.abs(H.cpu().numpy() - ref)) / scale
+            e32 = np.max(np.abs(H32.double().cpu().numpy() - ref)) / scale
+            print(f"  R={R}: FP64 {e64:.2e}  FP32 {e32:.2e} (of max|H|)", flush=True)
+            assert e64 <= 1e-12
+            assert e32 <= 2e-6
+    assert torch.equal(dk.cpu(), torch.from_numpy(dk_host))   # input not modified
+
+
+def test_plane_wave_on_device(pkg):
+    n, box, R = 24, 120.0, 3.0
+    mode = (3, -2, 5)
+    x = np.arange(n) * (box / n)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    k0 = 2 * np.pi / box * np.asarray(mode, dtype=float)
+    dk = torch.from_numpy(np.fft.rfftn(np.cos(k0[0] * X + k0[1] * Y + k0[2] * Z))).cuda().contiguous()
+    want = ofield.plane_wave_hessian(n, box, mode, R)
+    with pkg.Field(n, box) as f:
+        H = torch.empty((6, n ** 3), dtype=torch.float64, device="cuda")
+        f.hessian(dk, R, H)
+        torch.cuda.synchronize()
+    assert np.max(np.abs(H.cpu().numpy() - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def _items(P, n, Fmax, Rmax, ac, count):
+    return [P.make_item(None, Fmax, Rmax, ac if r == count - 1 else None, radius_index=r, n=n) for r in range(count)]
+
+
+def test_field_collapse_c1_vs_oracle(pkg, orc):
+    cfg = synth.config("C1")
+    n, box, radii = cfg["n_side"], cfg["box"], cfg["radii"]
+    a, D = synth.growth_table(cfg["cosmo"].omega_m, cfg["n_growth"])
+    dk = synth.fields.field(n, box, cfg["seed"], cfg["cosmo"], device="cuda").dk.contiguous()
+    slabs = [ofield.hessian(dk.cpu().numpy(), n, box, R) for R in radii]
+    ref = orc.collapse(slabs, orc.Growth(a, D))
+    ties = near_tie_mask([orc.points(s)[1] for s in slabs])
+    with pkg.Collapse([(a, D)]) as col, pkg.Field(n, box) as f:
+        N = n ** 3
+        Fm, Rm, ac = col.outputs(N)
+        f.collapse(col.ctx, dk, radii, _items(pkg, N, Fm, Rm, ac, len(radii)),
+                   flags=pkg.PINO_EVAL_RESET | pkg.PINO_EVAL_FINALIZE | pkg.PINO_EVAL_SYNC)
+        got = (Fm.cpu().numpy(), Rm.cpu().numpy(), ac.cpu().numpy())
+        # the same through the separate calls: identical results
+        F2, R2, A2 = col.outputs(N)
+        H = torch.empty((6, N), dtype=torch.float64, device="cuda")
+        last = len(radii) - 1
+        for r, R in enumerate(radii):
+            f.hessian(dk, R, H)
+            col.apply(H, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last))
+        torch.cuda.synchronize()
+        assert torch.equal(Fm, F2) and torch.equal(Rm, R2) and torch.equal(ac, A2)
+    st = compare(ref, got, tie_mask=ties, label="field C1")
+    print("field C1", st, flush=True)
+
+
+def test_field_collapse_256cube_sampled(pkg, orc):
+    """256^3 at three of the benchmark's radii: the oracle builds its own
+    Hessians with numpy and collapses a seeded sample of particles."""
+    cfg = synth.config("C2")
+    n, box = cfg["n_side"], cfg["box"]
+    radii = [cfg["radii"][0], cfg["radii"][12], cfg["radii"][24]]
+    a, D = synth.growth_table(cfg["cosmo"].omega_m, cfg["n_growth"])
+    dk = synth.fields.field(n, box, cfg["seed"], cfg["cosmo"], device="cuda").dk.contiguous()
+    N = n ** 3
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([np.sort(rng.choice(N, size=20000, replace=False)), [0, N - 1]])
+    with pkg.Collapse([(a, D)]) as col, pkg.Field(n, box) as f:
+        Fm, Rm, ac = col.outputs(N)
+        f.collapse(col.ctx, dk, radii, _items(pkg, N, Fm, Rm, ac, len(radii)),
+                   flags=pkg.PINO_EVAL_RESET | pkg.PINO_EVAL_FINALIZE | pkg.PINO_EVAL_SYNC)
+        got = tuple(t.cpu().numpy()[idx] for t in (Fm, Rm, ac))
+    dk_host = dk.cpu().numpy()
+    del dk
+    sample = []
+    for R in radii:
+        sample.append(ofield.hessian(dk_host, n, box, R)[:, idx].copy())
+        print(f"  oracle Hessian R={R:.3f} done", flush=True)
+    ref = orc.collapse(sample, orc.Growth(a, D))
+    ties = near_tie_mask([orc.points(s)[1] for s in sample])
+    st = compare(ref, got, tie_mask=ties, label="field 256^3 sample")
+    print("field 256^3 sample", st, flush=True)
+
+
+def test_field_collapse_mixed_precision(pkg, orc):
+    """A PINO_MIXED context takes the FP32 Hessian stage; its error against
+    the oracle (FP64 Hessians) is reported per output.  Gate: the FP32
+    transform error (2e-6 of max|H|) over l1 for D_c, as in the mixed bound."""
+    cfg = synth.config("C1")
+    n, box, radii = cfg["n_side"], cfg["box"], cfg["radii"]
+    a, D = synth.growth_table(cfg["cosmo"].omega_m, cfg["n_growth"])
+    dk = synth.fields.field(n, box, cfg["seed"], cfg["cosmo"], device="cuda").dk.contiguous()
+    slabs = [ofield.hessian(dk.cpu().numpy(), n, box, R) for R in radii]
+    Fr, Rr, Ar = orc.collapse(slabs, orc.Growth(a, D))
+    # per particle: max over radii of (2e-6 max|H_r| + 64 eps32 |H|_F) / l1
+    bound = np.zeros(n ** 3)
+    for h in slabs:
+        lam, _ = orc.points(h)
+        hn = np.sqrt(np.sum(h[:3] ** 2, axis=0) + 2 * np.sum(h[3:] ** 2, axis=0))
+        with np.errstate(divide="ignore"):
+            b = np.where(lam[:, 0] > 0, (8 * 2e-6 * np.max(np.abs(h)) + 64 * 2.0 ** -24 * hn) / lam[:, 0], np.inf)
+        bound = np.maximum(bound, b)
+    with pkg.Collapse([(a, D)], precision=pkg.PINO_MIXED) as col, pkg.Field(n, box) as f:
+        N = n ** 3
+        Fm, Rm, ac = col.outputs(N)
+        f.collapse(col.ctx, dk, radii, _items(pkg, N, Fm, Rm, ac, len(radii)),
+                   flags=pkg.PINO_EVAL_RESET | pkg.PINO_EVAL_FINALIZE | pkg.PINO_EVAL_SYNC)
+        F, R, A = (t.cpu().numpy() for t in (Fm, Rm, ac))
+    big = (Fr >= 1e-6) & (F > 0)
+    rD = np.abs(1 / F[big] - 1 / Fr[big]) * Fr[big]
+    fin = np.isfinite(Ar) & np.isfinite(A)
+    ra = np.abs(A[fin] - Ar[fin]) / Ar[fin]
+    print(f"field mixed vs oracle: D_c {rel_stats(rD)} a_coll {rel_stats(ra)} "
+          f"index mismatches {int(np.sum(R != Rr))}/{N}", flush=True)
+    assert np.all(rD <= bound[big] + 1e-12)
