@@ -447,3 +447,59 @@ class Field:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# include/pino_interp.h
+# ---------------------------------------------------------------------------
+_interp_bound = False
+
+
+def _bind_interp():
+    global _interp_bound
+    L = lib()
+    if not _interp_bound:
+        c_p, c_i32, c_i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.pino_spline_build.argtypes = [c_i32, c_p, c_p, c_i32, c_p, c_p, c_p]
+        L.pino_spline_eval.argtypes = [c_i32, c_p, c_p, c_p, c_i32, c_p, c_p, c_i64, c_p]
+        L.pino_table_build.argtypes = [c_i32, c_i32, c_i32, c_i32, c_p, c_p, c_p, c_p, c_p]
+        L.pino_table_eval.argtypes = [c_i32, c_p, c_i32, c_p, c_i32, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p]
+        L.pino_interp_last_error.argtypes = []
+        L.pino_interp_last_error.restype = ctypes.c_char_p
+        for name in ("pino_spline_build", "pino_spline_eval", "pino_table_build", "pino_table_eval"):
+            getattr(L, name).restype = ctypes.c_int
+        _interp_bound = True
+    return L
+
+
+def _check_interp(status):
+    if status != PINO_OK:
+        raise PinoError(status, _bind_interp().pino_interp_last_error().decode())
+
+
+def _dev(t):
+    return t.device.index if t.device.index is not None else 0
+
+
+def pino_spline_build(x, y, M, work, stream=None):
+    """Natural-spline second derivatives of (x, y) into M (device float64)."""
+    _check_interp(_bind_interp().pino_spline_build(_dev(x), _ptr(x), _ptr(y), x.numel(), _ptr(M), _ptr(work),
+                                                   _stream(stream)))
+
+
+def pino_spline_eval(x, y, M, q, out, stream=None):
+    _check_interp(_bind_interp().pino_spline_eval(_dev(x), _ptr(x), _ptr(y), _ptr(M), x.numel(), _ptr(q),
+                                                  _ptr(out), q.numel(), _stream(stream)))
+
+
+def pino_table_build(dk, F, tab, work, stream=None):
+    """F shaped (nx, ny, nd) on the device -> interleaved (F, M) table tab."""
+    nx, ny, nd = F.shape
+    _check_interp(_bind_interp().pino_table_build(_dev(F), nx, ny, nd, _ptr(dk), _ptr(F), _ptr(tab), _ptr(work),
+                                                  _stream(stream)))
+
+
+def pino_table_eval(xk, yk, dk, tab, qx, qy, qd, out, stream=None):
+    _check_interp(_bind_interp().pino_table_eval(_dev(xk), _ptr(xk), xk.numel(), _ptr(yk), yk.numel(), _ptr(dk),
+                                                 dk.numel(), _ptr(tab), _ptr(qx), _ptr(qy), _ptr(qd), _ptr(out),
+                                                 qx.numel(), _stream(stream)))

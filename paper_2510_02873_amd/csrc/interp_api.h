@@ -1,0 +1,129 @@
+// pino_interp.h implementation.  Included once, by pino_collapse.hip.
+#pragma once
+
+#include <string>
+
+#include "../../include/pino_interp.h"
+#include "kernels_interp.h"
+
+namespace {
+
+thread_local std::string g_interp_error = "no error";
+
+pino_status interp_arg(const std::string& why)
+{
+    g_interp_error = why;
+    return PINO_ERR_ARG;
+}
+
+pino_status interp_hip(hipError_t e, const char* what)
+{
+    g_interp_error = std::string(what) + ": " + hipGetErrorString(e);
+    return PINO_ERR_HIP;
+}
+
+#define INTERP_HIP(call)                        \
+    do {                                        \
+        hipError_t e_ = (call);                 \
+        if (e_ != hipSuccess)                   \
+            return interp_hip(e_, #call);       \
+    } while (0)
+
+// enough workgroups to fill the device, no more than the queries need
+pino_status interp_grid(int32_t device, int64_t m, unsigned& grid)
+{
+    int cus = 0;
+    INTERP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    const int64_t need = (m + 255) / 256;
+    grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * 8));
+    return PINO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pino_status pino_spline_build(int32_t device, const double* x, const double* y, int32_t n, double* M, double* work,
+                              void* hip_stream)
+{
+    if (device < 0 || !x || !y || !M || !work || n < 2 || n > 2048)
+        return interp_arg("need device >= 0, non-NULL x, y, M, work and 2 <= n <= 2048");
+    INTERP_HIP(hipSetDevice(device));
+    hipLaunchKernelGGL(pino::k_spline_build, dim3(1), dim3(64), 0, static_cast<hipStream_t>(hip_stream), x, n, y,
+                       (int64_t)n, 1, M, (int64_t)n, 1, work, 1);
+    INTERP_HIP(hipGetLastError());
+    return PINO_OK;
+}
+
+pino_status pino_spline_eval(int32_t device, const double* x, const double* y, const double* M, int32_t n,
+                             const double* q, double* out, int64_t m, void* hip_stream)
+{
+    if (device < 0 || !x || !y || !M || n < 2 || n > 2048 || m < 0 || (m > 0 && (!q || !out)))
+        return interp_arg("need device >= 0, non-NULL knots (2 <= n <= 2048), m >= 0 and q, out for m > 0");
+    if (m == 0)
+        return PINO_OK;
+    INTERP_HIP(hipSetDevice(device));
+    unsigned grid = 0;
+    const pino_status st = interp_grid(device, m, grid);
+    if (st != PINO_OK)
+        return st;
+    hipLaunchKernelGGL(pino::k_spline_eval, dim3(grid), dim3(256), (size_t)3 * n * sizeof(double),
+                       static_cast<hipStream_t>(hip_stream), x, y, M, n, q, out, m);
+    INTERP_HIP(hipGetLastError());
+    return PINO_OK;
+}
+
+pino_status pino_table_build(int32_t device, int32_t nx, int32_t ny, int32_t nd, const double* dk, const double* F,
+                             double* tab, double* work, void* hip_stream)
+{
+    if (device < 0 || !dk || !F || !tab || !work || nx < 2 || ny < 2 || nx > 1024 || ny > 1024 || nd < 2 ||
+        nd > 4096)
+        return interp_arg("need device >= 0, non-NULL arrays, 2 <= nx, ny <= 1024 and 2 <= nd <= 4096");
+    INTERP_HIP(hipSetDevice(device));
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t rows = (int64_t)nx * ny;
+    const int64_t cells = rows * nd;
+    hipLaunchKernelGGL(pino::k_table_copy_F, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, F, tab, cells);
+    INTERP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(pino::k_spline_build, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, dk, nd, F,
+                       (int64_t)nd, 1, tab + 1, (int64_t)2 * nd, 2, work, (int)rows);
+    INTERP_HIP(hipGetLastError());
+    return PINO_OK;
+}
+
+pino_status pino_table_eval(int32_t device, const double* xk, int32_t nx, const double* yk, int32_t ny,
+                            const double* dk, int32_t nd, const double* tab, const double* qx, const double* qy,
+                            const double* qd, double* out, int64_t m, void* hip_stream)
+{
+    if (device < 0 || !xk || !yk || !dk || !tab || nx < 2 || ny < 2 || nx > 1024 || ny > 1024 || nd < 2 ||
+        nd > 4096 || m < 0 || (m > 0 && (!qx || !qy || !qd || !out)))
+        return interp_arg("need device >= 0, non-NULL knots and table, 2 <= nx, ny <= 1024, 2 <= nd <= 4096, "
+                          "m >= 0 and non-NULL queries and out for m > 0");
+    if (m == 0)
+        return PINO_OK;
+    INTERP_HIP(hipSetDevice(device));
+    unsigned grid = 0;
+    const pino_status st = interp_grid(device, m, grid);
+    if (st != PINO_OK)
+        return st;
+    pino::TabArgs t;
+    t.xk = xk;
+    t.yk = yk;
+    t.dk = dk;
+    t.nx = nx;
+    t.ny = ny;
+    t.nd = nd;
+    t.scale = 1.0;
+    t.tab = tab;
+    hipLaunchKernelGGL(pino::k_table_eval, dim3(grid), dim3(256), (size_t)(nx + ny + nd) * sizeof(double),
+                       static_cast<hipStream_t>(hip_stream), t, qx, qy, qd, out, m);
+    INTERP_HIP(hipGetLastError());
+    return PINO_OK;
+}
+
+const char* pino_interp_last_error(void)
+{
+    return g_interp_error.c_str();
+}
+
+}  // extern "C"

@@ -220,12 +220,11 @@ __device__ __forceinline__ double corner(const double* __restrict__ tab, int64_t
     return spline_piece(d0, d1, lo.x, hi.x, lo.y, hi.y, q);
 }
 
-__device__ __forceinline__ double table_F(const TabArgs& t, const double* xs, const double* ys, const double* ds,
-                                          double l1, double l2, double l3)
+// The table at (x, y, delta): splines in delta at the four corners of the
+// (x, y) cell, then bilinear; knots xs, ys, ds (in LDS).
+__device__ __forceinline__ double table_at(const TabArgs& t, const double* xs, const double* ys, const double* ds,
+                                           double x, double y, double delta)
 {
-    const double delta = l1 + l2 + l3;
-    const double x = l1 - l2;
-    const double y = l2 - l3;
     const int ix = locate(xs, t.nx, x);
     const int iy = locate(ys, t.ny, y);
     const double tt = fmin(fmax((x - xs[ix]) * rcp2(xs[ix + 1] - xs[ix]), 0.0), 1.0);
@@ -240,6 +239,13 @@ __device__ __forceinline__ double table_F(const TabArgs& t, const double* xs, co
     const double v11 = corner(t.tab, r00 + t.ny + 1, t.nd, j, d0, d1, dq);
     const double f = (1.0 - tt) * (1.0 - uu) * v00 + tt * (1.0 - uu) * v10 + (1.0 - tt) * uu * v01 + tt * uu * v11;
     return f > 0.0 ? f : 0.0;
+}
+
+// F from the eigenvalues: delta = l1 + l2 + l3, x = l1 - l2, y = l2 - l3.
+__device__ __forceinline__ double table_F(const TabArgs& t, const double* xs, const double* ys, const double* ds,
+                                          double l1, double l2, double l3)
+{
+    return table_at(t, xs, ys, ds, l1 - l2, l2 - l3, l1 + l2 + l3);
 }
 
 __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)

@@ -616,3 +616,4 @@ pino_status pino_collapse_surrogate_stats(pino_ctx* ctx, int64_t* certified, int
 
 #include "batch_api.h"
 #include "field_api.h"
+#include "interp_api.h"

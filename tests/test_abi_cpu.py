@@ -110,3 +110,22 @@ def test_field_create_rejects_bad_grid(n_side, box):
         P.Field(n_side, box)
     assert e.value.status == P.PINO_ERR_ARG
     assert "n_side" in P._abi.pino_field_last_error(None)
+
+
+def test_interp_calls_reject_bad_sizes():
+    """The interpolation entry points validate before any HIP call."""
+    import torch
+    import paper_2510_02873_amd as P
+    from paper_2510_02873_amd import _abi
+    one = torch.zeros(1, dtype=torch.float64)
+    many = torch.zeros(8, dtype=torch.float64)
+    with pytest.raises(P.PinoError) as e:
+        _abi.pino_spline_eval(one, one, one, many, many)            # a single knot
+    assert e.value.status == P.PINO_ERR_ARG and "2 <= n" in str(e.value)
+    with pytest.raises(P.PinoError) as e:
+        _abi.pino_spline_build(torch.zeros(4096, dtype=torch.float64), torch.zeros(4096, dtype=torch.float64),
+                               torch.zeros(4096, dtype=torch.float64), torch.zeros(4096, dtype=torch.float64))
+    assert e.value.status == P.PINO_ERR_ARG
+    with pytest.raises(P.PinoError) as e:
+        _abi.pino_table_build(many, torch.zeros((1, 4, 8), dtype=torch.float64), many, many)   # nx = 1
+    assert e.value.status == P.PINO_ERR_ARG

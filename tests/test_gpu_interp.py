@@ -1,0 +1,140 @@
+"""Stand-alone interpolators (pino_interp.h) against the oracle's natural
+spline and table routines, on the analytic functions of the paper's
+interpolation benchmark (Sec. 4.3: y = x^2 on 512 random knots; z = x^2 + y^2
+on a 64 x 64 table of 128-knot splines, here with a dependence on the spline
+coordinate added) and on data they must reproduce exactly.
+
+Gates: 1e-12 of the value scale against the oracle (the same formulas,
+evaluated in a different order), 1e-13 on data a cubic spline or a bilinear
+cell reproduces exactly."""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_2510_02873_amd import _abi
+    return _abi
+
+
+def _knots(rng, n, lo=0.0, hi=1.0):
+    return np.concatenate([[lo], np.sort(rng.uniform(lo, hi, n - 2)), [hi]])
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _spline_gpu(A, x, y, q):
+    xd, yd, qd = _cuda(x), _cuda(y), _cuda(q)
+    M = torch.empty_like(xd)
+    work = torch.empty_like(xd)
+    out = torch.empty_like(qd)
+    A.pino_spline_build(xd, yd, M, work)
+    A.pino_spline_eval(xd, yd, M, qd, out)
+    torch.cuda.synchronize()
+    return M.cpu().numpy(), out.cpu().numpy()
+
+
+def test_spline_x_squared_vs_oracle(A, orc):
+    rng = np.random.default_rng(21)
+    x = _knots(rng, 512)
+    y = x * x
+    q = np.concatenate([rng.uniform(-0.05, 1.05, 100003), x])   # extrapolation and exact knots too
+    M, got = _spline_gpu(A, x, y, q)
+    Mr = orc.spline_natural(x, y)
+    assert np.max(np.abs(M - Mr)) <= 1e-12 * np.max(np.abs(Mr))
+    ref = orc.spline_eval(x, y, Mr, q)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    inside = (q >= 0) & (q <= 1)
+    res = np.abs(got[inside] - q[inside] ** 2)
+    print(f"spline y=x^2, 512 random knots: mean |residual| vs analytic {res.mean():.2e}, "
+          f"mean relative {np.mean(res / np.maximum(q[inside] ** 2, 1e-300)):.2e}", flush=True)
+
+
+def test_spline_exact_on_linear_data(A):
+    rng = np.random.default_rng(3)
+    x = _knots(rng, 37, -2.0, 5.0)
+    y = 3.0 * x - 2.0
+    q = rng.uniform(-2.0, 5.0, 4097)
+    M, got = _spline_gpu(A, x, y, q)
+    # (only the rounding of the knot slopes feeds the right-hand side)
+    assert np.max(np.abs(M)) <= 1e-11
+    assert np.max(np.abs(got - (3.0 * q - 2.0))) <= 1e-12
+
+
+def _table_gpu(A, xk, yk, dk, F, qx, qy, qd):
+    nx, ny, nd = F.shape
+    Fd = _cuda(F)
+    tab = torch.empty(2 * F.size, dtype=torch.float64, device="cuda")
+    work = torch.empty(F.size, dtype=torch.float64, device="cuda")
+    A.pino_table_build(_cuda(dk), Fd, tab, work)
+    out = torch.empty(qx.size, dtype=torch.float64, device="cuda")
+    A.pino_table_eval(_cuda(xk), _cuda(yk), _cuda(dk), tab, _cuda(qx), _cuda(qy), _cuda(qd), out)
+    torch.cuda.synchronize()
+    return tab.cpu().numpy().reshape(nx, ny, nd, 2), out.cpu().numpy()
+
+
+def _oracle_table(orc, xk, yk, dk, F, M, qx, qy, qd):
+    # the oracle takes eigenvalues: d = l1 + l2 + l3, x = l1 - l2, y = l2 - l3
+    lam = np.stack([(qd + 2 * qx + qy) / 3, (qd - qx + qy) / 3, (qd - qx - 2 * qy) / 3], axis=1)
+    return np.array([orc.table_F(xk, yk, dk, F, M, l) for l in lam])
+
+
+def test_table_vs_oracle(A, orc):
+    rng = np.random.default_rng(8)
+    xk, yk, dk = _knots(rng, 64), _knots(rng, 64), _knots(rng, 128, -1.0, 2.0)
+    X, Y, Dd = np.meshgrid(xk, yk, dk, indexing="ij")
+    F = X ** 2 + Y ** 2 + 0.3 * Dd ** 2 + 0.1 * np.sin(3 * Dd)
+    m = 20000
+    qx, qy, qd = rng.uniform(0, 1, m), rng.uniform(0, 1, m), rng.uniform(-1, 2, m)
+    tab, got = _table_gpu(A, xk, yk, dk, F, qx, qy, qd)
+    M = orc.table_build(dk, F)
+    assert np.array_equal(tab[..., 0], F)
+    assert np.max(np.abs(tab[..., 1] - M)) <= 1e-12 * np.max(np.abs(M))
+    ref = _oracle_table(orc, xk, yk, dk, F, M, qx, qy, qd)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # the paper's function z = x^2 + y^2 (no dependence on d)
+    F2 = X ** 2 + Y ** 2
+    _, got2 = _table_gpu(A, xk, yk, dk, F2, qx, qy, qd)
+    z = qx ** 2 + qy ** 2
+    print(f"table z=x^2+y^2, 64x64 random knots: mean relative residual vs analytic "
+          f"{np.mean(np.abs(got2 - z) / z):.2e}", flush=True)
+
+
+def test_table_exact_on_bilinear_times_linear(A):
+    rng = np.random.default_rng(9)
+    xk, yk, dk = _knots(rng, 9, 0, 2), _knots(rng, 7, 0, 3), _knots(rng, 11, -1, 1)
+    X, Y, Dd = np.meshgrid(xk, yk, dk, indexing="ij")
+
+    def f(x, y, d):
+        return (1.5 + 0.5 * x + 0.25 * y + 0.125 * x * y) * (2.0 + 0.5 * d)
+
+    m = 5001
+    qx, qy, qd = rng.uniform(0, 2, m), rng.uniform(0, 3, m), rng.uniform(-1, 1, m)
+    _, got = _table_gpu(A, xk, yk, dk, f(X, Y, Dd), qx, qy, qd)
+    assert np.max(np.abs(got - f(qx, qy, qd))) <= 1e-13 * 20
+
+
+@pytest.mark.parametrize("m", [0, 1, 255, 257, 1000003])
+def test_ragged_query_counts(A, orc, m):
+    rng = np.random.default_rng(m)
+    x = _knots(rng, 512)
+    y = np.cos(4 * x)
+    q = rng.uniform(0, 1, m)
+    if m == 0:
+        xd, yd = _cuda(x), _cuda(y)
+        M = torch.empty_like(xd)
+        A.pino_spline_build(xd, yd, M, torch.empty_like(xd))
+        A.pino_spline_eval(xd, yd, M, torch.empty(0, dtype=torch.float64, device="cuda"),
+                           torch.empty(0, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        return
+    _, got = _spline_gpu(A, x, y, q)
+    pick = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, min(m, 2000))]))
+    ref = orc.spline_eval(x, y, orc.spline_natural(x, y), q[pick])
+    assert np.max(np.abs(got[pick] - ref)) <= 1e-12
