@@ -24,7 +24,7 @@ __device__ __forceinline__ Hess64 load_h(const ItemArgs& a, uint32_t i, bool f32
 // wave-uniform (all 64 lanes run the network together); lanes past the end
 // compute on zeros and store nothing.  counters: certified, consulted but not
 // certified, not consulted (wave totals added once per wave at the end).
-__global__ void __launch_bounds__(256) k_surrogate(ItemArgs a, const NetFrags* __restrict__ net, double sigma,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_surrogate(ItemArgs a, const NetFrags* __restrict__ net, double sigma,
                                                   double omega_m, double rtol,
                                                   unsigned long long* __restrict__ counters,
                                                   int32_t* __restrict__ queue, int32_t* __restrict__ qcount,

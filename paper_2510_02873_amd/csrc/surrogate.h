@@ -307,51 +307,86 @@ __device__ __forceinline__ bf16x8 frag(const s16x8& w)
     return __builtin_bit_cast(bf16x8, w);
 }
 
+__device__ __forceinline__ bf16x8 pack_pair(f32x4 a, f32x4 b)
+{
+    return join(to_bf16(relu4(a)), to_bf16(relu4(b)));
+}
+
+#ifndef PINO_NET_GROUPS
+#define PINO_NET_GROUPS 2
+#endif
+
 // Network output for this lane's particle (all 64 lanes of the wave must
-// call it together; x of inactive lanes may be anything finite).
+// call it together; x of inactive lanes may be anything finite).  The four
+// 16-particle groups of the wave go through the layers two at a time: each
+// weight fragment read from LDS feeds two independent MFMA chains, which
+// hides the MFMA latency without the register cost of four.
 __device__ __forceinline__ float net_bf16(const NetFrags& N, const float x[4])
 {
+    constexpr int G = PINO_NET_GROUPS;  // groups per pass
     const int l = threadIdx.x & 63;
     const int q = l & 15;
     const int g = l >> 4;
     const bf16x4 zero4 = to_bf16(f32x4{0.0f, 0.0f, 0.0f, 0.0f});
     float out = 0.0f;
-    for (int nt = 0; nt < 4; ++nt) {
-        const int src = 16 * nt + q;
-        const f32x4 f{__shfl(x[0], src, 64), __shfl(x[1], src, 64), __shfl(x[2], src, 64), __shfl(x[3], src, 64)};
-        const bf16x4 hi = to_bf16(f);
-        const bf16x4 lo = to_bf16(f - __builtin_convertvector(hi, f32x4));
-        const bf16x8 bx = join(g <= 1 ? hi : zero4, g == 0 ? lo : zero4);
-        f32x4 acc[4];
-        for (int mt = 0; mt < 4; ++mt)
-            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(N.w1[mt][l]), bx, bias4(N.b1, mt, g), 0, 0, 0);
-        bf16x8 hb[2];
-        for (int kt = 0; kt < 2; ++kt)
-            hb[kt] = join(to_bf16(relu4(acc[2 * kt])), to_bf16(relu4(acc[2 * kt + 1])));
-        for (int mt = 0; mt < 4; ++mt) {
-            acc[mt] = bias4(N.b2, mt, g);
+    for (int p = 0; p < 4; p += G) {
+        bf16x8 hb[G][2];
+        f32x4 acc[G][4];
+        {
+            bf16x8 bx[G];
+            for (int e = 0; e < G; ++e) {
+                const int src = 16 * (p + e) + q;
+                const f32x4 f{__shfl(x[0], src, 64), __shfl(x[1], src, 64), __shfl(x[2], src, 64),
+                              __shfl(x[3], src, 64)};
+                const bf16x4 hi = to_bf16(f);
+                const bf16x4 lo = to_bf16(f - __builtin_convertvector(hi, f32x4));
+                bx[e] = join(g <= 1 ? hi : zero4, g == 0 ? lo : zero4);
+            }
+            for (int mt = 0; mt < 4; ++mt) {
+                const bf16x8 w = frag(N.w1[mt][l]);
+                const f32x4 b = bias4(N.b1, mt, g);
+                for (int e = 0; e < G; ++e)
+                    acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, bx[e], b, 0, 0, 0);
+            }
+        }
+        for (int e = 0; e < G; ++e)
             for (int kt = 0; kt < 2; ++kt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(N.w2[mt][kt][l]), hb[kt], acc[mt], 0, 0, 0);
-        }
-        for (int kt = 0; kt < 2; ++kt)
-            hb[kt] = join(to_bf16(relu4(acc[2 * kt])), to_bf16(relu4(acc[2 * kt + 1])));
+                hb[e][kt] = pack_pair(acc[e][2 * kt], acc[e][2 * kt + 1]);
         for (int mt = 0; mt < 4; ++mt) {
-            acc[mt] = bias4(N.b3, mt, g);
+            const f32x4 b = bias4(N.b2, mt, g);
+            const bf16x8 w0 = frag(N.w2[mt][0][l]);
+            const bf16x8 w1 = frag(N.w2[mt][1][l]);
+            for (int e = 0; e < G; ++e) {
+                const f32x4 t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, hb[e][0], b, 0, 0, 0);
+                acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, hb[e][1], t, 0, 0, 0);
+            }
+        }
+        for (int e = 0; e < G; ++e)
             for (int kt = 0; kt < 2; ++kt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(N.w3[mt][kt][l]), hb[kt], acc[mt], 0, 0, 0);
-        }
-        // output layer in FP32: this lane's 16 neurons of column q, then
-        // the sum over the four lanes that share the column
-        float part = 0.0f;
+                hb[e][kt] = pack_pair(acc[e][2 * kt], acc[e][2 * kt + 1]);
         for (int mt = 0; mt < 4; ++mt) {
-            const f32x4 w = bias4(N.w4, mt, g);
-            for (int j = 0; j < 4; ++j)
-                part += w[j] * fmaxf(acc[mt][j], 0.0f);
+            const f32x4 b = bias4(N.b3, mt, g);
+            const bf16x8 w0 = frag(N.w3[mt][0][l]);
+            const bf16x8 w1 = frag(N.w3[mt][1][l]);
+            for (int e = 0; e < G; ++e) {
+                const f32x4 t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, hb[e][0], b, 0, 0, 0);
+                acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, hb[e][1], t, 0, 0, 0);
+            }
         }
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        if (g == nt)
-            out = part + N.b4;
+        // output layer in FP32: this lane's 16 neurons of column q, then the
+        // sum over the four lanes that share the column
+        for (int e = 0; e < G; ++e) {
+            float part = 0.0f;
+            for (int mt = 0; mt < 4; ++mt) {
+                const f32x4 w = bias4(N.w4, mt, g);
+                for (int j = 0; j < 4; ++j)
+                    part += w[j] * fmaxf(acc[e][mt][j], 0.0f);
+            }
+            part += __shfl_xor(part, 16, 64);
+            part += __shfl_xor(part, 32, 64);
+            if (g == p + e)
+                out = part + N.b4;
+        }
     }
     return out;
 }
