@@ -193,7 +193,7 @@ def kernel_table(trace, out, command, pattern=r"pino::"):
     for r in stats:
         if not re.search(pattern, r["Name"]):
             continue
-        short = re.sub(r"\(.*", "", r["Name"]).replace("pino::", "")
+        short = re.sub(r"\(.*", "", r["Name"]).replace("pino::", "").replace("void ", "")
         try:
             dig = kernel_digest(short.split("<")[0])
         except (KeyError, ValueError):
