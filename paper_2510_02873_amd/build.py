@@ -18,6 +18,9 @@ FLAGS = [
     # FP32 divide and square root as the hardware approximations (FP32 only
     # feeds starting guesses and the mixed-precision path, polished in FP64)
     "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+    # multiply-adds fused only within one source expression, so every kernel
+    # that inlines the same device function computes the same bits
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -164,14 +164,15 @@ __device__ __forceinline__ void update_max(const ItemArgs& a, const double* g, c
 #endif
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PINO_WAVES_PER_EU)))
-k_classic_f64(ItemArgs a)
+k_classic_f64_1(ItemArgs a)
 {
     extern __shared__ double lds[];
     const GrowthIndex gi = stage_growth(lds, a);
     __syncthreads();
-    // Software pipeline: the loads of the next grid-stride element are issued
-    // before the eigen/root arithmetic of the current one, so their latency
-    // hides behind it (the kernel has registers to spare for the second set).
+    // One particle per lane (arrays not 16-byte aligned).  Software pipeline:
+    // the loads of the next grid-stride element are issued before the
+    // eigen/root arithmetic of the current one, so their latency hides
+    // behind it.
     const uint32_t n = (uint32_t)a.n;
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,6 +194,94 @@ k_classic_f64(ItemArgs a)
         eig_top(h, l1, s, pp);
         const double F = classic_F(l1, s, pp);
         update_max(a, lds, gi, i, F, fm);
+    }
+}
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// Two adjacent particles per lane: one 16-byte load per Hessian component
+// (and per output array) instead of two 8-byte ones.
+struct Hess2 {
+    d2v xx, yy, zz, xy, xz, yz;
+};
+
+__device__ __forceinline__ Hess2 load_h2(const ItemArgs& a, uint32_t p)
+{
+    Hess2 h;
+    h.xx = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(elem(a.h[0], 2 * p)));
+    h.yy = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(elem(a.h[1], 2 * p)));
+    h.zz = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(elem(a.h[2], 2 * p)));
+    h.xy = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(elem(a.h[3], 2 * p)));
+    h.xz = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(elem(a.h[4], 2 * p)));
+    h.yz = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(elem(a.h[5], 2 * p)));
+    return h;
+}
+
+__device__ __forceinline__ double classic_of(const Hess64& h)
+{
+    double l1, s, pp;
+    eig_top(h, l1, s, pp);
+    return classic_F(l1, s, pp);
+}
+
+// The headline kernel: pairs (2p, 2p + 1) over a grid-stride loop, the next
+// pair's loads issued before the current pair's arithmetic; the update is
+// update_max's, element for element, with whole-line paired stores.  Needs
+// 16-byte aligned Hessian, Fmax and a_coll arrays and an 8-byte aligned Rmax
+// (checked by the host); an odd last element is done by one lane at the end.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PINO_WAVES_PER_EU)))
+k_classic_f64(ItemArgs a)
+{
+    extern __shared__ double lds[];
+    const GrowthIndex gi = stage_growth(lds, a);
+    __syncthreads();
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t np = n / 2;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    Hess2 hn{};
+    d2v fn{0.0, 0.0};
+    if (p < np) {
+        hn = load_h2(a, p);
+        if (!a.reset)
+            fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * p));
+    }
+    for (; p < np; p += stride) {
+        const Hess2 h = hn;
+        const d2v fm = fn;
+        const uint32_t next = p + stride;
+        if (next < np) {
+            hn = load_h2(a, next);
+            if (!a.reset)
+                fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * next));
+        }
+        const double F0 = classic_of(Hess64{h.xx.x, h.yy.x, h.zz.x, h.xy.x, h.xz.x, h.yz.x});
+        const double F1 = classic_of(Hess64{h.xx.y, h.yy.y, h.zz.y, h.xy.y, h.xz.y, h.yz.y});
+        const bool u0 = F0 > fm.x, u1 = F1 > fm.y;
+        const d2v fnew{u0 ? F0 : fm.x, u1 ? F1 : fm.y};
+        int2 rm{-1, -1};
+        if (!a.reset)
+            rm = *reinterpret_cast<const int2*>(elem(a.Rmax, 2 * p));
+        *reinterpret_cast<d2v*>(elem(a.Fmax, 2 * p)) = fnew;
+        *reinterpret_cast<int2*>(elem(a.Rmax, 2 * p)) = int2{u0 ? a.radius : rm.x, u1 ? a.radius : rm.y};
+        if (a.acoll) {
+            d2v* ac = reinterpret_cast<d2v*>(elem(a.acoll, 2 * p));
+            d2v v;
+            if (a.finalize) {
+                v.x = fnew.x > 0.0 ? growth_invert(lds, a.nk, rcp2(fnew.x), gi) : kInf;
+                v.y = fnew.y > 0.0 ? growth_invert(lds, a.nk, rcp2(fnew.y), gi) : kInf;
+            } else {
+                const d2v am = a.reset ? d2v{kInf, kInf} : *ac;
+                v.x = u0 ? growth_invert(lds, a.nk, rcp2(F0), gi) : am.x;
+                v.y = u1 ? growth_invert(lds, a.nk, rcp2(F1), gi) : am.y;
+            }
+            *ac = v;
+        }
+    }
+    if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t i = n - 1;
+        const double fm = a.reset ? 0.0 : *elem(a.Fmax, i);
+        update_max(a, lds, gi, i, classic_of(load_h64(a, i)), fm);
     }
 }
 

@@ -206,6 +206,11 @@ bool lds_fits(const pino_config* cfg, std::string& why)
     return true;
 }
 
+bool aligned(const void* p, uintptr_t bytes)
+{
+    return (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
+}
+
 int grid_for(const pino_ctx* ctx, int64_t n, int block)
 {
     const int64_t need = (n + block - 1) / block;
@@ -399,7 +404,16 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
         pino_status ps = PINO_OK;
         if (c->precision == PINO_FP64) {
             if (c->method == PINO_CLASSIC) {
-                hipLaunchKernelGGL(k_classic_f64, dim3(g), dim3(block), lds, st, a);
+                // pairs of particles per lane need 16-byte aligned arrays
+                bool al = aligned(a.Fmax, 16) && aligned(a.Rmax, 8) && (!a.acoll || aligned(a.acoll, 16));
+                for (int k = 0; k < 6; ++k)
+                    al = al && aligned(a.h[k], 16);
+                if (al) {
+                    const int gp = grid_for(c, (a.n + 1) / 2, block);
+                    hipLaunchKernelGGL(k_classic_f64, dim3(gp), dim3(block), lds, st, a);
+                } else {
+                    hipLaunchKernelGGL(k_classic_f64_1, dim3(g), dim3(block), lds, st, a);
+                }
             } else {
                 TabArgs t;
                 t.xk = c->d_tknots;

@@ -69,8 +69,9 @@ def _device_code_object(lib_path):
 
 def kernel_digest(kernel, lib_path=None):
     """sha256 (16 hex digits) over the machine code and kernel descriptor of
-    the first kernel whose mangled name contains `kernel` (the descriptor's
-    code-entry offset, which moves with other kernels, is left out)."""
+    the kernel named `kernel` (the first template instance for a template;
+    the descriptor's code-entry offset, which moves with other kernels, is
+    left out)."""
     if lib_path is None:
         lib_path = os.path.join(HERE, "libpino_collapse.so")
     co = _device_code_object(lib_path)
@@ -80,12 +81,15 @@ def kernel_digest(kernel, lib_path=None):
         raise ValueError("code object has no symbol table")
     st = symtab[0]
     strtab = heads[st[6]]
+    # the name as a whole mangled component (length prefix, then the end of
+    # the nested name or a template argument list), so k_x does not match k_x_1
+    pat = re.compile(r"\d" + re.escape(kernel) + r"[EI]")
     found = {}
     for k in range(st[5] // 24):
         st_name, st_info, _, st_shndx, st_value, st_size = struct.unpack_from("<IBBHQQ", co, st[4] + 24 * k)
         end = co.index(b"\0", strtab[4] + st_name)
         nm = co[strtab[4] + st_name:end].decode()
-        if kernel in nm and st_size and st_shndx < len(heads):
+        if pat.search(nm) and st_size and st_shndx < len(heads):
             sec = heads[st_shndx]
             start = sec[4] + (st_value - sec[3])
             found.setdefault(nm, co[start:start + st_size])
@@ -109,9 +113,15 @@ def _csv(directory, suffix):
     return list(csv.DictReader(open(hits[0])))
 
 
+def _named(kernel):
+    """Regex for a kernel's demangled name (followed by its argument or
+    template list, so k_x does not match k_x_1)."""
+    return re.compile(re.escape(kernel) + r"[(<]")
+
+
 def _counter(rows, counter, kernel):
-    vals = [(float(r["Counter_Value"]), r) for r in rows if r["Counter_Name"] == counter and re.search(kernel, r["Kernel_Name"])]
-    return vals
+    pat = _named(kernel)
+    return [(float(r["Counter_Value"]), r) for r in rows if r["Counter_Name"] == counter and pat.search(r["Kernel_Name"])]
 
 
 FLOP_COUNTERS = ("SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP64_TRANS", "SQ_INSTS_VALU_ADD_F64",
@@ -126,7 +136,7 @@ def _mean_counter(rows, counter, kernel):
 
 def summarize(kernel, trace, fetch, write, calib_mib, out, command, flops=None, evals_per_launch=None):
     stats = _csv(trace, "kernel_stats.csv")
-    ks = [r for r in stats if re.search(kernel, r["Name"])]
+    ks = [r for r in stats if _named(kernel).search(r["Name"])]
     lines = [f"# rocprofv3 summary: {kernel}", f"command: {command}", f"kernel_digest: {kernel_digest(kernel)}", ""]
     lines.append("kernel stats (--kernel-trace --stats):")
     for r in ks:
@@ -195,7 +205,7 @@ def kernel_table(trace, out, command, pattern=r"pino::"):
             continue
         short = re.sub(r"\(.*", "", r["Name"]).replace("pino::", "").replace("void ", "")
         try:
-            dig = kernel_digest(short.split("<")[0])
+            dig = kernel_digest(short.split("<")[0].strip())
         except (KeyError, ValueError):
             dig = "-"
         lines.append(f"{r['Name']} | {r['Calls']} | {float(r['AverageNs']):.1f} | {r['MinNs']} | {r['MaxNs']} | "

@@ -181,3 +181,32 @@ def test_finalize_equals_per_update(pkg):
         with pytest.raises(pkg.PinoError) as e:
             col.apply(slabs[0].cuda(), 0, F2, R2, None, finalize=True)
         assert e.value.status == pkg.PINO_ERR_ARG
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 1001])
+def test_unaligned_arrays_match_aligned(pkg, orc, n):
+    """Arrays that are 8- but not 16-byte aligned take the one-particle-per-
+    lane kernel; its results equal the paired kernel's bit for bit (same
+    arithmetic) and the oracle's.  Odd and tiny sizes exercise the paired
+    kernel's last-element path."""
+    cfg, slabs, a, D = c1_inputs()
+    hs = [s[:, :n].contiguous() for s in slabs]
+    with pkg.Collapse([(a, D)]) as col:
+        F1, R1, A1 = col.outputs(n)
+        bufF = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+        bufR = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        bufA = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+        F2, R2, A2 = bufF[1:], bufR[1:], bufA[1:]       # 8 (4) bytes past an aligned start
+        last = len(hs) - 1
+        for r, h in enumerate(hs):
+            hd = h.cuda()
+            buf = torch.empty((6, n + 1), dtype=torch.float64, device="cuda")
+            buf[:, 1:] = hd
+            hu = [buf[c, 1:] for c in range(6)]
+            assert hu[0].data_ptr() % 16 == 8
+            col.apply(hd, r, F1, R1, A1 if r == last else None, reset=(r == 0), finalize=(r == last))
+            col.apply(hu, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last))
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F2) and torch.equal(R1, R2) and torch.equal(A1, A2)
+    ref = orc.collapse([h.numpy() for h in hs], orc.Growth(a, D))
+    compare(ref, (F1.cpu().numpy(), R1.cpu().numpy(), A1.cpu().numpy()), label=f"n={n}")
