@@ -54,13 +54,14 @@ __device__ __forceinline__ void update_max_f32(const ItemArgs& a, const float* g
     }
 }
 
-__global__ void __launch_bounds__(256) k_classic_mixed(ItemArgs a, const float* __restrict__ growth32)
+__global__ void __launch_bounds__(256) k_classic_mixed_1(ItemArgs a, const float* __restrict__ growth32)
 {
     extern __shared__ double lds[];
     float* g = reinterpret_cast<float*>(lds);
     const GrowthIndex gi = stage_growth32(g, growth32, a);
     __syncthreads();
-    // Next element's loads issued ahead of the current arithmetic.
+    // One particle per lane (arrays not 8/16-byte aligned); the next
+    // element's loads issued ahead of the current arithmetic.
     const uint32_t n = (uint32_t)a.n;
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -89,6 +90,84 @@ __global__ void __launch_bounds__(256) k_classic_mixed(ItemArgs a, const float* 
         }
         const double F = classic_F(l1, s, pp);
         update_max_f32(a, g, gi, i, F, fm);
+    }
+}
+
+// F of one particle from its FP32 Hessian: FP32 eigenvalues, or FP64 ones
+// where the FP32 closed form is not trusted; FP64 root.
+__device__ __forceinline__ double mixed_F(const Hess32& h)
+{
+    float l1f, sf, ppf;
+    double l1, s, pp;
+    if (eig_top_f32(h, l1f, sf, ppf)) {
+        l1 = l1f;
+        s = sf;
+        pp = ppf;
+    } else {
+        eig_top(widen(h), l1, s, pp);
+    }
+    return classic_F(l1, s, pp);
+}
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// Two adjacent particles per lane (8-byte component loads, 16-byte Fmax and
+// a_coll, 8-byte Rmax; alignment checked by the host), as k_classic_f64.
+__global__ void __launch_bounds__(256) k_classic_mixed(ItemArgs a, const float* __restrict__ growth32)
+{
+    extern __shared__ double lds[];
+    float* g = reinterpret_cast<float*>(lds);
+    const GrowthIndex gi = stage_growth32(g, growth32, a);
+    __syncthreads();
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t np = n / 2;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    f2v hn[6];
+    d2v fn{0.0, 0.0};
+    auto load = [&](uint32_t q) {
+        for (int c = 0; c < 6; ++c)
+            hn[c] = __builtin_nontemporal_load(
+                reinterpret_cast<const f2v*>(elem(reinterpret_cast<const float*>(a.h[c]), 2 * q)));
+        if (!a.reset)
+            fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * q));
+    };
+    if (p < np)
+        load(p);
+    for (; p < np; p += stride) {
+        f2v h[6];
+        for (int c = 0; c < 6; ++c)
+            h[c] = hn[c];
+        const d2v fm = fn;
+        if (p + stride < np)
+            load(p + stride);
+        const double F0 = mixed_F(Hess32{h[0].x, h[1].x, h[2].x, h[3].x, h[4].x, h[5].x});
+        const double F1 = mixed_F(Hess32{h[0].y, h[1].y, h[2].y, h[3].y, h[4].y, h[5].y});
+        const bool u0 = F0 > fm.x, u1 = F1 > fm.y;
+        const d2v fnew{u0 ? F0 : fm.x, u1 ? F1 : fm.y};
+        int2 rm{-1, -1};
+        if (!a.reset)
+            rm = *reinterpret_cast<const int2*>(elem(a.Rmax, 2 * p));
+        *reinterpret_cast<d2v*>(elem(a.Fmax, 2 * p)) = fnew;
+        *reinterpret_cast<int2*>(elem(a.Rmax, 2 * p)) = int2{u0 ? a.radius : rm.x, u1 ? a.radius : rm.y};
+        if (a.acoll) {
+            d2v* ac = reinterpret_cast<d2v*>(elem(a.acoll, 2 * p));
+            d2v v;
+            if (a.finalize) {
+                v.x = fnew.x > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew.x), gi) : kInf;
+                v.y = fnew.y > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew.y), gi) : kInf;
+            } else {
+                const d2v am = a.reset ? d2v{kInf, kInf} : *ac;
+                v.x = u0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F0), gi) : am.x;
+                v.y = u1 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F1), gi) : am.y;
+            }
+            *ac = v;
+        }
+    }
+    if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t i = n - 1;
+        const double fm = a.reset ? 0.0 : *elem(a.Fmax, i);
+        update_max_f32(a, g, gi, i, mixed_F(load_h32(a, i)), fm);
     }
 }
 

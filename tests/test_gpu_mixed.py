@@ -103,3 +103,26 @@ def test_mixed_rejects_tabulated(pkg):
         pkg.Collapse([(a, D)], precision=pkg.PINO_MIXED, method=pkg.PINO_TABULATED,
                      table_knots=synth.table_knots())
     assert e.value.status == pkg.PINO_ERR_ARG
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 1001])
+def test_mixed_unaligned_arrays_match_aligned(pkg, n):
+    """FP32 components that are 4- but not 8-byte aligned take the
+    one-particle-per-lane kernel; it equals the paired kernel bit for bit.
+    Odd and tiny sizes exercise the paired kernel's last element."""
+    cfg, slabs, a, D = c1_inputs()
+    hs = [s[:, :n].to(torch.float32).contiguous() for s in slabs]
+    with pkg.Collapse([(a, D)], precision=pkg.PINO_MIXED) as col:
+        F1, R1, A1 = col.outputs(n)
+        F2, R2, A2 = col.outputs(n)
+        last = len(hs) - 1
+        for r, h in enumerate(hs):
+            hd = h.cuda()
+            buf = torch.empty((6, n + 1), dtype=torch.float32, device="cuda")
+            buf[:, 1:] = hd
+            hu = [buf[c, 1:] for c in range(6)]
+            assert hu[0].data_ptr() % 8 == 4
+            col.apply(hd, r, F1, R1, A1 if r == last else None, reset=(r == 0), finalize=(r == last))
+            col.apply(hu, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last))
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F2) and torch.equal(R1, R2) and torch.equal(A1, A2)
