@@ -356,9 +356,12 @@ def measure_batched(P, steps):
     descs, n_tot = [], 0
     for k, r in enumerate(reals):
         fld = synth.fields.field(r["n_side"], r["box"], r["seed"], r["cosmo"], device="cuda")
-        slabs = [fld.hessian(R) for R in radii]
-        del fld
         n = r["n_side"] ** 3
+        # component rows padded to an even length: every row starts 16-byte
+        # aligned, which the two-particles-per-lane path needs
+        slabs = [fld.hessian(R, out=torch.empty((6, n + (n & 1)), dtype=torch.float64, device="cuda")[:, :n])
+                 for R in radii]
+        del fld
         F, Rm, A = col.outputs(n)
         descs.append({"h": slabs, "Fmax": F, "Rmax": Rm, "a_coll": A, "cosmo": k})
         n_tot += n

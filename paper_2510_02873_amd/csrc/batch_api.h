@@ -179,6 +179,16 @@ pino_status pino_collapse_batch_plan(pino_ctx* ctx, const pino_realisation* real
         d.acoll = (flags & PINO_EVAL_FINALIZE) ? R.a_coll : nullptr;
         d.growth = ctx->d_growth + (size_t)R.cosmo * 3 * ctx->nk_max;
         d.growth32 = ctx->d_growth32 ? ctx->d_growth32 + (size_t)R.cosmo * 3 * ctx->nk_max : nullptr;
+        // two particles per lane need every Hessian array aligned to two
+        // elements, Fmax and a_coll to 16 bytes and Rmax to 8
+        {
+            const uintptr_t two = ctx->precision == PINO_FP64 ? 16 : 8;
+            auto al = [](const void* p, uintptr_t b) { return reinterpret_cast<uintptr_t>(p) % b == 0; };
+            bool ok = al(R.Fmax, 16) && al(R.Rmax, 8) && (!d.acoll || al(d.acoll, 16));
+            for (int k = 0; R.n > 0 && k < 6 * R.n_radii; ++k)
+                ok = ok && al(R.h[k], two);
+            d.paired = ok ? 1 : 0;
+        }
         d.gi.idx = ctx->d_gidx + (size_t)R.cosmo * 2 * ctx->nb_max;
         d.gi.nb = ctx->nb[R.cosmo];
         d.gi.L0 = ctx->gL0[R.cosmo];

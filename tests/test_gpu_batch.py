@@ -142,3 +142,34 @@ def test_batch_rejects_bad_input(P):
             A.Batch(col.ctx, [{"h": reals[0], "Fmax": F, "Rmax": R}], flags=Pk.PINO_EVAL_FINALIZE)
         with pytest.raises(Pk.PinoError):
             A.Batch(col.ctx, [{"h": reals[0], "Fmax": F, "Rmax": R}], tile=100)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_paired_odd_tail_and_unaligned(P, precision):
+    """Separately allocated (aligned) component arrays put realisations of
+    odd size on the two-particles-per-lane path, whose last tile ends in a
+    single particle; components packed back to back with an odd size are not
+    aligned and take the one-per-lane path.  Both equal the per-radius
+    results bit for bit."""
+    Pk, A = P
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    prec = Pk.PINO_FP64 if precision == "fp64" else Pk.PINO_MIXED
+    reals, tables = _realisations(count=4, seed=21, dtype=dtype)
+    with Pk.Collapse(tables, precision=prec) as col:
+        for split in (True, False):
+            outs, descs = [], []
+            for k, slabs in enumerate(reals):
+                hs = [[h[c].clone() for c in range(6)] for h in slabs] if split else slabs
+                F, R, Ac = col.outputs(slabs[0].shape[1])
+                outs.append((F, R, Ac))
+                descs.append({"h": hs, "Fmax": F, "Rmax": R, "a_coll": Ac, "cosmo": k})
+            with A.Batch(col.ctx, descs, flags=Pk.PINO_EVAL_RESET | Pk.PINO_EVAL_FINALIZE, tile=256) as b:
+                b.run()
+                torch.cuda.synchronize()
+            for k, slabs in enumerate(reals):
+                F1, R1, A1 = _per_radius(col, slabs, k)
+                torch.cuda.synchronize()
+                F, R, Ac = outs[k]
+                assert torch.equal(F, F1) and torch.equal(R, R1) and torch.equal(Ac, A1), \
+                    f"realisation {k} (n = {slabs[0].shape[1]}, split {split})"
+        print("sizes", [s[0].shape[1] for s in reals], flush=True)
