@@ -217,6 +217,33 @@ __device__ __forceinline__ Hess2 load_h2(const ItemArgs& a, uint32_t p)
     return h;
 }
 
+// update_max for the pair (2p, 2p + 1), element for element, with paired
+// (whole-line) loads and stores
+__device__ __forceinline__ void update_pair(const ItemArgs& a, const double* g, const GrowthIndex& gi, uint32_t p,
+                                            double F0, double F1, d2v fm)
+{
+    const bool u0 = F0 > fm.x, u1 = F1 > fm.y;
+    const d2v fnew{u0 ? F0 : fm.x, u1 ? F1 : fm.y};
+    int2 rm{-1, -1};
+    if (!a.reset)
+        rm = *reinterpret_cast<const int2*>(elem(a.Rmax, 2 * p));
+    *reinterpret_cast<d2v*>(elem(a.Fmax, 2 * p)) = fnew;
+    *reinterpret_cast<int2*>(elem(a.Rmax, 2 * p)) = int2{u0 ? a.radius : rm.x, u1 ? a.radius : rm.y};
+    if (a.acoll) {
+        d2v* ac = reinterpret_cast<d2v*>(elem(a.acoll, 2 * p));
+        d2v v;
+        if (a.finalize) {
+            v.x = fnew.x > 0.0 ? growth_invert(g, a.nk, rcp2(fnew.x), gi) : kInf;
+            v.y = fnew.y > 0.0 ? growth_invert(g, a.nk, rcp2(fnew.y), gi) : kInf;
+        } else {
+            const d2v am = a.reset ? d2v{kInf, kInf} : *ac;
+            v.x = u0 ? growth_invert(g, a.nk, rcp2(F0), gi) : am.x;
+            v.y = u1 ? growth_invert(g, a.nk, rcp2(F1), gi) : am.y;
+        }
+        *ac = v;
+    }
+}
+
 __device__ __forceinline__ double classic_of(const Hess64& h)
 {
     double l1, s, pp;
@@ -257,26 +284,7 @@ k_classic_f64(ItemArgs a)
         }
         const double F0 = classic_of(Hess64{h.xx.x, h.yy.x, h.zz.x, h.xy.x, h.xz.x, h.yz.x});
         const double F1 = classic_of(Hess64{h.xx.y, h.yy.y, h.zz.y, h.xy.y, h.xz.y, h.yz.y});
-        const bool u0 = F0 > fm.x, u1 = F1 > fm.y;
-        const d2v fnew{u0 ? F0 : fm.x, u1 ? F1 : fm.y};
-        int2 rm{-1, -1};
-        if (!a.reset)
-            rm = *reinterpret_cast<const int2*>(elem(a.Rmax, 2 * p));
-        *reinterpret_cast<d2v*>(elem(a.Fmax, 2 * p)) = fnew;
-        *reinterpret_cast<int2*>(elem(a.Rmax, 2 * p)) = int2{u0 ? a.radius : rm.x, u1 ? a.radius : rm.y};
-        if (a.acoll) {
-            d2v* ac = reinterpret_cast<d2v*>(elem(a.acoll, 2 * p));
-            d2v v;
-            if (a.finalize) {
-                v.x = fnew.x > 0.0 ? growth_invert(lds, a.nk, rcp2(fnew.x), gi) : kInf;
-                v.y = fnew.y > 0.0 ? growth_invert(lds, a.nk, rcp2(fnew.y), gi) : kInf;
-            } else {
-                const d2v am = a.reset ? d2v{kInf, kInf} : *ac;
-                v.x = u0 ? growth_invert(lds, a.nk, rcp2(F0), gi) : am.x;
-                v.y = u1 ? growth_invert(lds, a.nk, rcp2(F1), gi) : am.y;
-            }
-            *ac = v;
-        }
+        update_pair(a, lds, gi, p, F0, F1, fm);
     }
     if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t i = n - 1;
@@ -337,7 +345,7 @@ __device__ __forceinline__ double table_F(const TabArgs& t, const double* xs, co
     return table_at(t, xs, ys, ds, l1 - l2, l2 - l3, l1 + l2 + l3);
 }
 
-__global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
+__global__ void __launch_bounds__(256) k_tabulated_f64_1(ItemArgs a, TabArgs t)
 {
     extern __shared__ double lds[];
     double* g = lds;
@@ -352,7 +360,8 @@ __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
     for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
         ds[k] = t.dk[k] * t.scale;
     __syncthreads();
-    // Next element's loads issued ahead of the current arithmetic.
+    // One particle per lane (arrays not 16-byte aligned); the next element's
+    // loads issued ahead of the current arithmetic.
     const uint32_t n = (uint32_t)a.n;
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -375,6 +384,64 @@ __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
         const bool finite = isfinite(l1) && isfinite(l2) && isfinite(l3);
         const double F = finite ? table_F(t, xs, ys, ds, l1, l2, l3) : 0.0;
         update_max(a, g, gi, i, F, fm);
+    }
+}
+
+// Table value of one particle: all three eigenvalues, then table_F
+__device__ __forceinline__ double tabulated_of(const TabArgs& t, const double* xs, const double* ys,
+                                              const double* ds, const Hess64& h)
+{
+    double l1, l2, l3;
+    eig_all(h, l1, l2, l3);
+    const bool finite = isfinite(l1) && isfinite(l2) && isfinite(l3);
+    return finite ? table_F(t, xs, ys, ds, l1, l2, l3) : 0.0;
+}
+
+// Two adjacent particles per lane, as k_classic_f64 (eight corner gathers
+// in flight per lane instead of four).
+__global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
+{
+    extern __shared__ double lds[];
+    double* g = lds;
+    const GrowthIndex gi = stage_growth(lds, a);
+    double* xs = lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
+    double* ys = xs + t.nx;
+    double* ds = ys + t.ny;
+    for (int k = threadIdx.x; k < t.nx; k += blockDim.x)
+        xs[k] = t.xk[k] * t.scale;
+    for (int k = threadIdx.x; k < t.ny; k += blockDim.x)
+        ys[k] = t.yk[k] * t.scale;
+    for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
+        ds[k] = t.dk[k] * t.scale;
+    __syncthreads();
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t np = n / 2;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    Hess2 hn{};
+    d2v fn{0.0, 0.0};
+    if (p < np) {
+        hn = load_h2(a, p);
+        if (!a.reset)
+            fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * p));
+    }
+    for (; p < np; p += stride) {
+        const Hess2 h = hn;
+        const d2v fm = fn;
+        const uint32_t next = p + stride;
+        if (next < np) {
+            hn = load_h2(a, next);
+            if (!a.reset)
+                fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * next));
+        }
+        const double F0 = tabulated_of(t, xs, ys, ds, Hess64{h.xx.x, h.yy.x, h.zz.x, h.xy.x, h.xz.x, h.yz.x});
+        const double F1 = tabulated_of(t, xs, ys, ds, Hess64{h.xx.y, h.yy.y, h.zz.y, h.xy.y, h.xz.y, h.yz.y});
+        update_pair(a, g, gi, p, F0, F1, fm);
+    }
+    if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t i = n - 1;
+        const double fm = a.reset ? 0.0 : *elem(a.Fmax, i);
+        update_max(a, g, gi, i, tabulated_of(t, xs, ys, ds, load_h64(a, i)), fm);
     }
 }
 

@@ -403,13 +403,13 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
         const int g = grid_for(c, a.n, block);
         pino_status ps = PINO_OK;
         if (c->precision == PINO_FP64) {
+            // pairs of particles per lane need 16-byte aligned arrays
+            bool al = aligned(a.Fmax, 16) && aligned(a.Rmax, 8) && (!a.acoll || aligned(a.acoll, 16));
+            for (int k = 0; k < 6; ++k)
+                al = al && aligned(a.h[k], 16);
+            const int gp = grid_for(c, (a.n + 1) / 2, block);
             if (c->method == PINO_CLASSIC) {
-                // pairs of particles per lane need 16-byte aligned arrays
-                bool al = aligned(a.Fmax, 16) && aligned(a.Rmax, 8) && (!a.acoll || aligned(a.acoll, 16));
-                for (int k = 0; k < 6; ++k)
-                    al = al && aligned(a.h[k], 16);
                 if (al) {
-                    const int gp = grid_for(c, (a.n + 1) / 2, block);
                     hipLaunchKernelGGL(k_classic_f64, dim3(gp), dim3(block), lds, st, a);
                 } else {
                     hipLaunchKernelGGL(k_classic_f64_1, dim3(g), dim3(block), lds, st, a);
@@ -425,7 +425,10 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
                 t.scale = it.sigma_R;
                 t.tab = c->d_tab;
                 const size_t lds_t = lds + (size_t)(c->nx + c->ny + c->nd) * sizeof(double);
-                hipLaunchKernelGGL(k_tabulated_f64, dim3(g), dim3(block), lds_t, st, a, t);
+                if (al)
+                    hipLaunchKernelGGL(k_tabulated_f64, dim3(gp), dim3(block), lds_t, st, a, t);
+                else
+                    hipLaunchKernelGGL(k_tabulated_f64_1, dim3(g), dim3(block), lds_t, st, a, t);
             }
             PINO_HIP(c, hipGetLastError());
         } else if (c->precision == PINO_MIXED) {
