@@ -411,7 +411,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="particles in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24,
+                    help="particles in the oracle sample (2^24: every particle of the 256^3 field, ~15 s of oracle time)")
     ap.add_argument("--n-side", type=int, default=None, help="override the grid side (testing only)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (mixed precision, Tabulated) on the same fields")
