@@ -38,13 +38,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(n, updates, reset, finalize):
-    """HBM bytes one launch must move: 6 FP64 Hessian components (48 B), the
-    running Fmax (8 B, not read on the RESET radius), Fmax + Rmax (12 B) for
-    every particle whose maximum changes (all of them on RESET), and a_coll
-    (8 B per particle) on the finalizing launch."""
-    b = n * 48 + (0 if reset else n * 8) + (n if reset else updates) * 12
+def algorithmic_bytes(n, updates, reset, finalize, hess_bytes=48):
+    """HBM bytes one launch must move: 6 Hessian components (48 B in FP64,
+    24 B in FP32), the running Fmax (8 B, not read on the RESET radius),
+    Fmax + Rmax (12 B) for every particle whose maximum changes (all of them
+    on RESET), and a_coll (8 B per particle) on the finalizing launch."""
+    b = n * hess_bytes + (0 if reset else n * 8) + (n if reset else updates) * 12
     return b + (n * 8 if finalize else 0)
+
+
+def step_roofline(bytes_per_step, ms):
+    """HBM roofline of a leg from its algorithmic bytes per step and its
+    measured time per step (launch gaps included, so a lower bound)."""
+    gbs = bytes_per_step / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_step": int(bytes_per_step)}
 
 
 def _time_steps(step, steps, stream):
@@ -61,7 +69,8 @@ def _time_steps(step, steps, stream):
     return t0.elapsed_time(t1) / steps
 
 
-def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, steps, dk=None):
+def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, steps, dk=None,
+                   updates=None):
     """Secondary rates on the same resident fields: mixed precision (FP32
     copies of the Hessians) and the Tabulated method (64 x 64 x 128 tables
     filled per radius by the library's Classic kernel on the table's sample
@@ -75,6 +84,10 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
     out = {}
     last = len(radii) - 1
     F64, R64, A64 = Fmax.clone(), Rmax.clone(), ac.clone()
+    ups = updates or [n] * len(radii)
+
+    def step_bytes(hess_bytes):
+        return sum(algorithmic_bytes(n, u, r == 0, r == last, hess_bytes) for r, u in enumerate(ups))
 
     sig = synth.grid_sigma_gauss(n_side, cfg["box"], radii)
 
@@ -95,10 +108,14 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                     "dtype": "f32 inputs/eigen/interp, f64 root", "workload": f"same {n_side}^3 x {len(radii)} fields",
                     "rel_Dc_vs_fp64": {"max": float(rel.max()), "p99.9": float(np.percentile(rel, 99.9)),
                                        "mean": float(rel.mean())},
-                    "index_mismatch_frac": float((Rm != R64).double().mean().item())}
+                    "index_mismatch_frac": float((Rm != R64).double().mean().item()),
+                    "roofline": step_roofline(step_bytes(24), ms)}
     mcol.close()
 
     out["surrogate"] = measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps)
+    # stream floor: FP32 Hessians once per particle (the deferred particles'
+    # second read by the fallback kernel is not counted)
+    out["surrogate"]["roofline"] = step_roofline(step_bytes(24), out["surrogate"]["ms_per_step"])
     del s32
 
     # Tabulated: fill each radius' table with the Classic kernel on the
@@ -124,7 +141,10 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
     relt = ((Ft[both] - F64[both]).abs() / F64[both]).cpu().numpy()
     out["tabulated"] = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s",
                         "ms_per_step": round(ms, 4), "table": "64x64x128 per radius, rebuilt on device",
-                        "rel_F_vs_classic_median": float(np.median(relt))}
+                        "rel_F_vs_classic_median": float(np.median(relt)),
+                        "roofline": step_roofline(step_bytes(48), ms),
+                        "roofline_note": "HBM streams only; the corner gathers (128 B per evaluation) are served "
+                                         "from L2/MALL (8.4 MB table)"}
     tcol.close()
 
     if dk is not None:
@@ -553,7 +573,8 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras = measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, args.steps, dk)
+        extras = measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, args.steps, dk,
+                                updates)
 
     cpu = None
     if not args.no_cpu_baseline:
