@@ -68,7 +68,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
-                               "(run __graft_entry__.build() or python paper_2510_02873_amd/build.py)")
+                               "(build it with: python paper_2510_02873_amd/build.py)")
         L = ctypes.CDLL(LIB_PATH)
         L.pino_collapse_init.argtypes = [ctypes.POINTER(pino_config), ctypes.POINTER(ctypes.c_void_p)]
         L.pino_collapse_init.restype = ctypes.c_int
