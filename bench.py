@@ -148,7 +148,7 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
     tcol.close()
 
     if dk is not None:
-        out["field_fused"] = measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps)
+        out["field_fused"] = measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps, [(a, D)])
     out["interp_sweep"] = measure_interp()
     return out
 
@@ -248,7 +248,7 @@ def measure_interp(reps=10):
     return out
 
 
-def measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps):
+def measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps, col_tables):
     """The Hessian stage on the device feeding the collapse with no host
     round trip (pino_field_collapse): per radius, delta(k) -> six weighted
     copies -> six inverse real FFTs (hipFFT) -> the same FP64 collapse
@@ -271,14 +271,25 @@ def measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps):
 
         ms_h = _time_steps(hstep, steps, stream)
         del H
+        # the same from a mixed-precision context: FP32 products and FP32
+        # inverse transforms feed the mixed kernel
+        mcol = P.Collapse(col_tables, precision=P.PINO_MIXED)
+        Fm, Rm, Am = mcol.outputs(n)
+        mitems = [P.make_item(None, Fm, Rm, Am if r == last else None, radius_index=r, n=n)
+                  for r in range(len(radii))]
+        ms_m = _time_steps(lambda: f.collapse(mcol.ctx, dk, radii, mitems, flags=flags, stream=stream), steps,
+                           stream)
+        mcol.close()
     big = F64 > 1e-6
     rel = ((1 / Ff[big] - 1 / F64[big]).abs() * F64[big]).max().item()
     res = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s", "ms_per_step": round(ms, 4),
+           "mixed_value": round(n * len(radii) / (ms_m * 1e-3), 1), "mixed_ms_per_step": round(ms_m, 4),
            "hessian_stage_ms_per_step": round(ms_h, 4),
            "workload": f"delta(k) of the same {n_side}^3 field -> {len(radii)} radii, FFTs included",
            "max_rel_Dc_vs_generator_hessians": rel,
            "index_mismatch_frac": float((Rf != R64).double().mean().item())}
-    log(f"field-fed collapse {res['value']:.3e} evals/s ({ms:.2f} ms/step, Hessian stage {ms_h:.2f} ms)")
+    log(f"field-fed collapse {res['value']:.3e} evals/s ({ms:.2f} ms/step, Hessian stage {ms_h:.2f} ms); "
+        f"mixed {res['mixed_value']:.3e}")
     return res
 
 

@@ -163,3 +163,41 @@ def test_field_collapse_mixed_precision(pkg, orc):
     print(f"field mixed vs oracle: D_c {rel_stats(rD)} a_coll {rel_stats(ra)} "
           f"index mismatches {int(np.sum(R != Rr))}/{N}", flush=True)
     assert np.all(rD <= bound[big] + 1e-12)
+
+
+def test_field_collapse_equals_two_step_for_every_context(pkg, orc):
+    """pino_field_collapse is the Hessian stage followed by pino_collapse_eval:
+    for Tabulated (FP64 stage) and surrogate (FP32 stage) contexts its
+    results equal those of the two calls made separately, bit for bit."""
+    from paper_2510_02873_amd import surrogate
+    cfg = synth.config("C1")
+    n, box, radii = cfg["n_side"], cfg["box"], cfg["radii"]
+    a, D = synth.growth_table(cfg["cosmo"].omega_m, cfg["n_growth"])
+    dk = synth.fields.field(n, box, cfg["seed"], cfg["cosmo"], device="cuda").dk.contiguous()
+    N = n ** 3
+    sig = synth.grid_sigma_gauss(n, box, radii)
+    knots = synth.table_knots(1.0, 16, 12, 40)
+    tabs = []
+    for sR in sig:
+        xk, yk, dkn = (np.asarray(k) * sR for k in knots)
+        _, Ft = orc.points(synth.table_grid_hessians(xk, yk, dkn))
+        tabs.append(torch.from_numpy(Ft).cuda())
+    cases = [("tabulated", dict(method=pkg.PINO_TABULATED, table_knots=knots), torch.float64),
+             ("surrogate", dict(precision=pkg.PINO_SURROGATE, mlp_blob=surrogate.constant_blob(1.0)),
+              torch.float32)]
+    last = len(radii) - 1
+    with pkg.Field(n, box) as f:
+        for name, kw, dt in cases:
+            with pkg.Collapse([(a, D, 0.3)], **kw) as col:
+                F1, R1, A1 = col.outputs(N)
+                items = [pkg.make_item(None, F1, R1, A1 if r == last else None, radius_index=r, n=N,
+                                       sigma_R=sig[r], table_F=tabs[r]) for r in range(len(radii))]
+                f.collapse(col.ctx, dk, radii, items, flags=pkg.PINO_EVAL_RESET | pkg.PINO_EVAL_FINALIZE)
+                F2, R2, A2 = col.outputs(N)
+                H = torch.empty((6, N), dtype=dt, device="cuda")
+                for r, R in enumerate(radii):
+                    f.hessian(dk, R, H)
+                    col.apply(H, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last),
+                              sigma_R=sig[r], table_F=tabs[r])
+                torch.cuda.synchronize()
+                assert torch.equal(F1, F2) and torch.equal(R1, R2) and torch.equal(A1, A2), name
