@@ -307,9 +307,15 @@ __device__ __forceinline__ bf16x8 frag(const s16x8& w)
     return __builtin_bit_cast(bf16x8, w);
 }
 
+// ReLU and BF16 packing of two output tiles.  The ReLU is applied to the
+// rounded values as a packed signed 16-bit max with 0: a negative BF16 (or
+// -0) has its sign bit set, so exactly those become +0, which is what
+// rounding after the FP32 ReLU gives.
 __device__ __forceinline__ bf16x8 pack_pair(f32x4 a, f32x4 b)
 {
-    return join(to_bf16(relu4(a)), to_bf16(relu4(b)));
+    typedef short s16x8v __attribute__((ext_vector_type(8)));
+    const s16x8v v = __builtin_bit_cast(s16x8v, join(to_bf16(a), to_bf16(b)));
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(v, s16x8v{0, 0, 0, 0, 0, 0, 0, 0}));
 }
 
 #ifndef PINO_NET_GROUPS
