@@ -21,6 +21,7 @@ struct pino_mlp {
     float* d_m2 = nullptr;
     float* d_grad = nullptr;
     float* d_partial = nullptr;
+    float* d_partial2 = nullptr;  // per-group sums of the partials
     int64_t step = 0;
     bool broken = false;
     std::string err = "no error";
@@ -239,11 +240,19 @@ pino_status pino_mlp_create(int32_t device, uint64_t seed, pino_mlp** out)
     };
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) fail(e, "hipSetDevice");
+    // the gradient kernel's LDS (about 99 KiB) exceeds the default dynamic limit
+    if (st == PINO_OK &&
+        (e = hipFuncSetAttribute((const void*)k_mlp_grad_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)mlp_grad_lds_bytes())) != hipSuccess)
+        fail(e, "hipFuncSetAttribute");
     if (st == PINO_OK && (e = hipMalloc(&m->d_params, kNParam * sizeof(float))) != hipSuccess) fail(e, "hipMalloc");
     if (st == PINO_OK && (e = hipMalloc(&m->d_m1, kNParam * sizeof(float))) != hipSuccess) fail(e, "hipMalloc");
     if (st == PINO_OK && (e = hipMalloc(&m->d_m2, kNParam * sizeof(float))) != hipSuccess) fail(e, "hipMalloc");
     if (st == PINO_OK && (e = hipMalloc(&m->d_grad, kNParam * sizeof(float))) != hipSuccess) fail(e, "hipMalloc");
     if (st == PINO_OK && (e = hipMalloc(&m->d_partial, nblk * (kNParam + 1) * sizeof(float))) != hipSuccess)
+        fail(e, "hipMalloc");
+    if (st == PINO_OK &&
+        (e = hipMalloc(&m->d_partial2, (size_t)kReduceGroups * (kNParam + 1) * sizeof(float))) != hipSuccess)
         fail(e, "hipMalloc");
     if (st == PINO_OK && (e = hipMemcpy(m->d_params, P.data(), kNParam * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
         fail(e, "hipMemcpy");
@@ -313,11 +322,14 @@ pino_status pino_mlp_grad(pino_mlp* m, const float* x, const float* w, int64_t n
     MLP_HIP(m, hipSetDevice(m->device));
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const int nblk = (int)((n + pino::kTB - 1) / pino::kTB);
-    hipLaunchKernelGGL(pino::k_mlp_grad_block, dim3(nblk), dim3(pino::kTB), pino::mlp_grad_lds_bytes(), st,
+    hipLaunchKernelGGL(pino::k_mlp_grad_block, dim3(nblk), dim3(pino::kGradThreads), pino::mlp_grad_lds_bytes(), st,
                        m->d_params, x, w, n, m->d_partial);
     MLP_HIP(m, hipGetLastError());
-    hipLaunchKernelGGL(pino::k_mlp_reduce, dim3((pino::kNParam + 1 + 255) / 256), dim3(256), 0, st, m->d_partial,
-                       nblk, n, grad, loss);
+    const unsigned cols = (unsigned)((pino::kNParam + 1 + 255) / 256);
+    hipLaunchKernelGGL(pino::k_mlp_reduce_groups, dim3(cols, pino::kReduceGroups), dim3(256), 0, st, m->d_partial,
+                       nblk, m->d_partial2);
+    MLP_HIP(m, hipGetLastError());
+    hipLaunchKernelGGL(pino::k_mlp_reduce, dim3(cols), dim3(256), 0, st, m->d_partial2, n, grad, loss);
     MLP_HIP(m, hipGetLastError());
     return PINO_OK;
 }
@@ -379,7 +391,7 @@ pino_status pino_mlp_free(pino_mlp* m)
         return PINO_OK;
     (void)hipSetDevice(m->device);
     (void)hipDeviceSynchronize();
-    float* ptrs[] = {m->d_params, m->d_m1, m->d_m2, m->d_grad, m->d_partial};
+    float* ptrs[] = {m->d_params, m->d_m1, m->d_m2, m->d_grad, m->d_partial, m->d_partial2};
     for (float* p : ptrs)
         if (p)
             (void)hipFree(p);

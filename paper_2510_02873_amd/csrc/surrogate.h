@@ -45,24 +45,64 @@ __host__ __device__ __forceinline__ bool net_inputs(double l1, double s, double 
 }
 
 // ---------------------------------------------------------------------------
-// FP32 training kernels.  A block of kTB samples (one per lane) keeps the
-// block's activations and back-propagated errors in LDS; the parameters are
-// read at lane-uniform addresses from global memory.  Per-sample forward and
-// backward passes run one sample per lane; weight gradients are sums over the
-// block's samples, each lane owning two output rows, written as a per-block
-// partial that k_mlp_reduce sums in fixed order (deterministic).
+// FP32 training kernels.  A block takes kTB samples (one per lane) and
+// kWaves waves; wave q owns hidden units [q kUw, (q + 1) kUw) of every layer,
+// so the weight rows it reads are wave-uniform (scalar loads) while the
+// activations and back-propagated errors of the block's samples sit in LDS
+// as [unit][sample].  The weight gradients, sums over the block's samples,
+// are spread over all threads and written as a per-block partial that
+// k_mlp_reduce_groups and k_mlp_reduce sum in a fixed order
+// (deterministic).
 // ---------------------------------------------------------------------------
-constexpr int kTB = 32;
-constexpr int kLd = kTB + 1;  // padded row stride of [unit][sample] arrays
+constexpr int kTB = 64;                 // samples per block
+constexpr int kWaves = 8;               // waves per block
+constexpr int kGradThreads = kTB * kWaves;
+constexpr int kUw = kH / kWaves;        // hidden units per wave
+constexpr int kLd = kTB + 1;            // padded row stride of [unit][sample] arrays
 
 __host__ __device__ inline size_t mlp_grad_lds_bytes()
 {
     return sizeof(float) * ((size_t)6 * kH * kLd + kIn * kLd + 2 * kTB);
 }
 
-__global__ void __launch_bounds__(kTB) k_mlp_grad_block(const float* __restrict__ p, const float* __restrict__ X,
-                                                       const float* __restrict__ Wt, int64_t n,
-                                                       float* __restrict__ partial)
+// out[u] = b[u0 + u] + sum_k W[(u0 + u) * K + k] in[k][s], u < kUw
+template <int K>
+__device__ __forceinline__ void dense_rows(const float* __restrict__ W, const float* __restrict__ b, int u0,
+                                           const float* in, int s, float out[kUw])
+{
+#pragma unroll
+    for (int u = 0; u < kUw; ++u)
+        out[u] = b[u0 + u];
+#pragma unroll 8
+    for (int k = 0; k < K; ++k) {
+        const float v = in[k * kLd + s];
+#pragma unroll
+        for (int u = 0; u < kUw; ++u)
+            out[u] = fmaf(W[(u0 + u) * K + k], v, out[u]);
+    }
+}
+
+// out[u] = sum_o W[o * kH + u0 + u] d[o][s]: the transposed product of the
+// backward pass
+__device__ __forceinline__ void dense_cols(const float* __restrict__ W, int u0, const float* d, int s,
+                                           float out[kUw])
+{
+#pragma unroll
+    for (int u = 0; u < kUw; ++u)
+        out[u] = 0.0f;
+#pragma unroll 8
+    for (int o = 0; o < kH; ++o) {
+        const float v = d[o * kLd + s];
+#pragma unroll
+        for (int u = 0; u < kUw; ++u)
+            out[u] = fmaf(W[o * kH + u0 + u], v, out[u]);
+    }
+}
+
+__global__ void __launch_bounds__(kGradThreads) k_mlp_grad_block(const float* __restrict__ p,
+                                                                const float* __restrict__ X,
+                                                                const float* __restrict__ Wt, int64_t n,
+                                                                float* __restrict__ partial)
 {
     extern __shared__ float sm[];
     float* h1 = sm;
@@ -74,110 +114,156 @@ __global__ void __launch_bounds__(kTB) k_mlp_grad_block(const float* __restrict_
     float* xs = d3 + kH * kLd;
     float* dys = xs + kIn * kLd;
     float* ls = dys + kTB;
-    const int t = threadIdx.x;
-    const int64_t smp = (int64_t)blockIdx.x * kTB + t;
+    const int tid = threadIdx.x;
+    const int s = tid % kTB;
+    const int u0 = __builtin_amdgcn_readfirstlane(tid / kTB) * kUw;
+    const int64_t smp = (int64_t)blockIdx.x * kTB + s;
     const bool valid = smp < n;
-    const float w = valid ? Wt[smp] : 0.0f;
-    const bool use = valid && w > 0.0f;
-    for (int k = 0; k < kIn; ++k)
-        xs[k * kLd + t] = valid ? X[smp * kIn + k] : 0.0f;
-    const float* W1 = p + kOffW1;
-    const float* W2 = p + kOffW2;
-    const float* W3 = p + kOffW3;
-    // forward
-    for (int o = 0; o < kH; ++o) {
-        float z = p[kOffB1 + o];
+    if (tid < kTB)
         for (int k = 0; k < kIn; ++k)
-            z += W1[o * kIn + k] * xs[k * kLd + t];
-        h1[o * kLd + t] = fmaxf(z, 0.0f);
+            xs[k * kLd + s] = valid ? X[smp * kIn + k] : 0.0f;
+    __syncthreads();
+    float z[kUw];
+    // forward
+    dense_rows<kIn>(p + kOffW1, p + kOffB1, u0, xs, s, z);
+#pragma unroll
+    for (int u = 0; u < kUw; ++u)
+        h1[(u0 + u) * kLd + s] = fmaxf(z[u], 0.0f);
+    __syncthreads();
+    dense_rows<kH>(p + kOffW2, p + kOffB2, u0, h1, s, z);
+#pragma unroll
+    for (int u = 0; u < kUw; ++u)
+        h2[(u0 + u) * kLd + s] = fmaxf(z[u], 0.0f);
+    __syncthreads();
+    dense_rows<kH>(p + kOffW3, p + kOffB3, u0, h2, s, z);
+    float yp = 0.0f;  // this wave's share of the output
+#pragma unroll
+    for (int u = 0; u < kUw; ++u) {
+        const float hv = fmaxf(z[u], 0.0f);
+        h3[(u0 + u) * kLd + s] = hv;
+        yp = fmaf(p[kOffW4 + u0 + u], hv, yp);
     }
-    for (int o = 0; o < kH; ++o) {
-        float z = p[kOffB2 + o];
-        for (int k = 0; k < kH; ++k)
-            z += W2[o * kH + k] * h1[k * kLd + t];
-        h2[o * kLd + t] = fmaxf(z, 0.0f);
-    }
-    float y = p[kOffB4];
-    for (int o = 0; o < kH; ++o) {
-        float z = p[kOffB3 + o];
-        for (int k = 0; k < kH; ++k)
-            z += W3[o * kH + k] * h2[k * kLd + t];
-        const float hv = fmaxf(z, 0.0f);
-        h3[o * kLd + t] = hv;
-        y += p[kOffW4 + o] * hv;
-    }
-    // loss ((y - w)/w)^2 averaged over all n samples; dL/dy
-    const float r = use ? (y - w) / w : 0.0f;
-    const float dy = use ? 2.0f * r / (w * (float)n) : 0.0f;
-    dys[t] = dy;
-    ls[t] = r * r;
-    // backward through the hidden layers, per sample
-    for (int o = 0; o < kH; ++o)
-        d3[o * kLd + t] = h3[o * kLd + t] > 0.0f ? dy * p[kOffW4 + o] : 0.0f;
-    for (int k = 0; k < kH; ++k) {
-        float g = 0.0f;
-        for (int o = 0; o < kH; ++o)
-            g += W3[o * kH + k] * d3[o * kLd + t];
-        d2[k * kLd + t] = h2[k * kLd + t] > 0.0f ? g : 0.0f;
-    }
-    for (int k = 0; k < kH; ++k) {
-        float g = 0.0f;
-        for (int o = 0; o < kH; ++o)
-            g += W2[o * kH + k] * d2[o * kLd + t];
-        d1[k * kLd + t] = h1[k * kLd + t] > 0.0f ? g : 0.0f;
+    d1[(u0 / kUw) * kLd + s] = yp;  // d1 is free until the last layer of the backward pass
+    __syncthreads();
+    if (tid < kTB) {
+        float y = p[kOffB4];
+        for (int q = 0; q < kWaves; ++q)
+            y += d1[q * kLd + s];
+        // loss ((y - w)/w)^2 averaged over all n samples; dL/dy
+        const float w = valid ? Wt[smp] : 0.0f;
+        const bool use = valid && w > 0.0f;
+        const float r = use ? (y - w) / w : 0.0f;
+        dys[s] = use ? 2.0f * r / (w * (float)n) : 0.0f;
+        ls[s] = r * r;
     }
     __syncthreads();
-    // weight gradients: lane t owns output rows t and t + kTB of every layer
+    // backward through the hidden layers, per sample
+    const float dy = dys[s];
+#pragma unroll
+    for (int u = 0; u < kUw; ++u)
+        d3[(u0 + u) * kLd + s] = h3[(u0 + u) * kLd + s] > 0.0f ? dy * p[kOffW4 + u0 + u] : 0.0f;
+    __syncthreads();
+    dense_cols(p + kOffW3, u0, d3, s, z);
+#pragma unroll
+    for (int u = 0; u < kUw; ++u)
+        d2[(u0 + u) * kLd + s] = h2[(u0 + u) * kLd + s] > 0.0f ? z[u] : 0.0f;
+    __syncthreads();
+    dense_cols(p + kOffW2, u0, d2, s, z);
+#pragma unroll
+    for (int u = 0; u < kUw; ++u)
+        d1[(u0 + u) * kLd + s] = h1[(u0 + u) * kLd + s] > 0.0f ? z[u] : 0.0f;
+    __syncthreads();
+    // weight gradients of W2 and W3: thread -> rows 2i, 2i + 1 and columns
+    // c, c + 16, c + 32, c + 48 (conflict-free LDS rows across a half-wave)
     float* out = partial + (int64_t)blockIdx.x * (kNParam + 1);
-    for (int o = t; o < kH; o += kTB) {
-        for (int k = 0; k < kIn; ++k) {
-            float g = 0.0f;
-            for (int s = 0; s < kTB; ++s)
-                g += d1[o * kLd + s] * xs[k * kLd + s];
-            out[kOffW1 + o * kIn + k] = g;
-        }
-        float gb1 = 0.0f, gb2 = 0.0f, gb3 = 0.0f, gw4 = 0.0f;
-        for (int s = 0; s < kTB; ++s) {
-            gb1 += d1[o * kLd + s];
-            gb2 += d2[o * kLd + s];
-            gb3 += d3[o * kLd + s];
-            gw4 += dys[s] * h3[o * kLd + s];
-        }
-        out[kOffB1 + o] = gb1;
-        out[kOffB2 + o] = gb2;
-        out[kOffB3 + o] = gb3;
-        out[kOffW4 + o] = gw4;
-        for (int k = 0; k < kH; ++k) {
-            float g2 = 0.0f, g3 = 0.0f;
-            for (int s = 0; s < kTB; ++s) {
-                g2 += d2[o * kLd + s] * h1[k * kLd + s];
-                g3 += d3[o * kLd + s] * h2[k * kLd + s];
+    {
+        const int r0 = 2 * (tid / 16);
+        const int c0 = tid % 16;
+        float g2[2][4] = {}, g3[2][4] = {};
+#pragma unroll 4
+        for (int t = 0; t < kTB; ++t) {
+            const float a2[2] = {d2[r0 * kLd + t], d2[(r0 + 1) * kLd + t]};
+            const float a3[2] = {d3[r0 * kLd + t], d3[(r0 + 1) * kLd + t]};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float v1 = h1[(c0 + 16 * j) * kLd + t];
+                const float v2 = h2[(c0 + 16 * j) * kLd + t];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    g2[i][j] = fmaf(a2[i], v1, g2[i][j]);
+                    g3[i][j] = fmaf(a3[i], v2, g3[i][j]);
+                }
             }
-            out[kOffW2 + o * kH + k] = g2;
-            out[kOffW3 + o * kH + k] = g3;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                out[kOffW2 + (r0 + i) * kH + c0 + 16 * j] = g2[i][j];
+                out[kOffW3 + (r0 + i) * kH + c0 + 16 * j] = g3[i][j];
+            }
+    }
+    // W1 (threads 0..255) and b1, b2, b3, W4 (threads 256..511)
+    if (tid < kH * kIn) {
+        const int o = tid / kIn, k = tid % kIn;
+        float g = 0.0f;
+        for (int t = 0; t < kTB; ++t)
+            g = fmaf(d1[o * kLd + t], xs[k * kLd + t], g);
+        out[kOffW1 + o * kIn + k] = g;
+    } else {
+        const int which = (tid - kH * kIn) / kH, o = (tid - kH * kIn) % kH;
+        float g = 0.0f;
+        if (which == 3) {
+            for (int t = 0; t < kTB; ++t)
+                g = fmaf(dys[t], h3[o * kLd + t], g);
+            out[kOffW4 + o] = g;
+        } else {
+            const float* d = which == 0 ? d1 : which == 1 ? d2 : d3;
+            for (int t = 0; t < kTB; ++t)
+                g += d[o * kLd + t];
+            out[(which == 0 ? kOffB1 : which == 1 ? kOffB2 : kOffB3) + o] = g;
         }
     }
-    if (t == 0) {
+    if (tid == 0) {
         float gb4 = 0.0f, lsum = 0.0f;
-        for (int s = 0; s < kTB; ++s) {
-            gb4 += dys[s];
-            lsum += ls[s];
+        for (int t = 0; t < kTB; ++t) {
+            gb4 += dys[t];
+            lsum += ls[t];
         }
         out[kOffB4] = gb4;
         out[kNParam] = lsum;
     }
 }
 
-// grad[j] = sum over blocks of partial[b][j] (fixed order); loss likewise / n
-__global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ partial, int nblk, int64_t n,
+// Deterministic two-level sum of the per-block partials: group g (blockIdx.y)
+// adds blocks g, g + groups, g + 2 groups, ... in that order into
+// partial2[g][j]; k_mlp_reduce then adds the groups in order.  The summation
+// tree depends only on the number of blocks.
+constexpr int kReduceGroups = 32;
+
+__global__ void __launch_bounds__(256) k_mlp_reduce_groups(const float* __restrict__ partial, int nblk,
+                                                          float* __restrict__ partial2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (j > kNParam)
+        return;
+    float s = 0.0f;
+    for (int b = g; b < nblk; b += kReduceGroups)
+        s += partial[(int64_t)b * (kNParam + 1) + j];
+    partial2[(int64_t)g * (kNParam + 1) + j] = s;
+}
+
+// grad[j] = sum over groups of partial2[g][j] (fixed order); loss likewise / n
+__global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ partial2, int64_t n,
                                                    float* __restrict__ grad, float* __restrict__ loss)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j > kNParam)
         return;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b)
-        s += partial[(int64_t)b * (kNParam + 1) + j];
+    for (int g = 0; g < kReduceGroups; ++g)
+        s += partial2[(int64_t)g * (kNParam + 1) + j];
     if (j < kNParam)
         grad[j] = s;
     else if (loss)
