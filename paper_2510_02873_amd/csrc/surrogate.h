@@ -368,9 +368,17 @@ __host__ __device__ __forceinline__ float bf16_value(short b)
     return __builtin_bit_cast(float, (uint32_t)(uint16_t)b << 16);
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16, round to nearest even, two values per packed convert (a
+// four-wide conversion is split into one convert per value plus a permute)
 __device__ __forceinline__ bf16x4 to_bf16(f32x4 v)
 {
-    return __builtin_convertvector(v, bf16x4);
+    const bf16x2 a = __builtin_convertvector(f32x2{v[0], v[1]}, bf16x2);
+    const bf16x2 b = __builtin_convertvector(f32x2{v[2], v[3]}, bf16x2);
+    return __builtin_shufflevector(a, b, 0, 1, 2, 3);
 }
 
 __device__ __forceinline__ f32x4 relu4(f32x4 v)
@@ -397,11 +405,19 @@ __device__ __forceinline__ bf16x8 frag(const s16x8& w)
 // rounded values as a packed signed 16-bit max with 0: a negative BF16 (or
 // -0) has its sign bit set, so exactly those become +0, which is what
 // rounding after the FP32 ReLU gives.
+__device__ __forceinline__ s16x2 relu_bf16x2(float a, float b)
+{
+    const s16x2 v = __builtin_bit_cast(s16x2, __builtin_convertvector(f32x2{a, b}, bf16x2));
+    return __builtin_elementwise_max(v, s16x2{0, 0});
+}
+
 __device__ __forceinline__ bf16x8 pack_pair(f32x4 a, f32x4 b)
 {
-    typedef short s16x8v __attribute__((ext_vector_type(8)));
-    const s16x8v v = __builtin_bit_cast(s16x8v, join(to_bf16(a), to_bf16(b)));
-    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(v, s16x8v{0, 0, 0, 0, 0, 0, 0, 0}));
+    const s16x2 p0 = relu_bf16x2(a[0], a[1]), p1 = relu_bf16x2(a[2], a[3]);
+    const s16x2 p2 = relu_bf16x2(b[0], b[1]), p3 = relu_bf16x2(b[2], b[3]);
+    const s16x8 v = __builtin_shufflevector(__builtin_shufflevector(p0, p1, 0, 1, 2, 3),
+                                            __builtin_shufflevector(p2, p3, 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf16x8, v);
 }
 
 #ifndef PINO_NET_GROUPS
