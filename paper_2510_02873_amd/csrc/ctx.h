@@ -29,11 +29,16 @@ struct pino_ctx {
     std::vector<int> gok;
 
     // tabulated method: dimensionless knots [x | y | delta], the interleaved
-    // (F, M) table of the current radius, sigma-scaled delta knots
+    // (F, M) table of the current radius
     int nx = 0, ny = 0, nd = 0;
     double* d_tknots = nullptr;
+    // interval index of the table knots (x | y | delta bins), when it holds
+    int* d_tidx = nullptr;
+    int tindexed = 0;
+    int tnb[3] = {0, 0, 0};
+    double tk0[3] = {0.0, 0.0, 0.0};
+    double tbpu[3] = {0.0, 0.0, 0.0};
     double* d_tab = nullptr;
-    double* d_dscaled = nullptr;
 
     // spline-build scratch
     double* d_tmp = nullptr;

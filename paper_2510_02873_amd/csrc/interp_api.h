@@ -81,12 +81,12 @@ pino_status pino_table_build(int32_t device, int32_t nx, int32_t ny, int32_t nd,
         return interp_arg("need device >= 0, non-NULL arrays, 2 <= nx, ny <= 1024 and 2 <= nd <= 4096");
     INTERP_HIP(hipSetDevice(device));
     const hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const int64_t rows = (int64_t)nx * ny;
-    const int64_t cells = rows * nd;
-    hipLaunchKernelGGL(pino::k_table_copy_F, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, F, tab, cells);
+    const int rows = nx * ny;
+    // the shared elimination coefficients (4 nd doubles) go to work
+    hipLaunchKernelGGL(pino::k_spline_coef, dim3(1), dim3(64), 0, st, dk, nd, 1.0, work);
     INTERP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(pino::k_spline_build, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, dk, nd, F,
-                       (int64_t)nd, 1, tab + 1, (int64_t)2 * nd, 2, work, (int)rows);
+    hipLaunchKernelGGL(pino::k_table_splines, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, work, nd, F, tab,
+                       rows);
     INTERP_HIP(hipGetLastError());
     return PINO_OK;
 }
@@ -106,7 +106,7 @@ pino_status pino_table_eval(int32_t device, const double* xk, int32_t nx, const 
     const pino_status st = interp_grid(device, m, grid);
     if (st != PINO_OK)
         return st;
-    pino::TabArgs t;
+    pino::TabArgs t{};  // no interval index: binary search on the knots
     t.xk = xk;
     t.yk = yk;
     t.dk = dk;
@@ -114,8 +114,10 @@ pino_status pino_table_eval(int32_t device, const double* xk, int32_t nx, const 
     t.ny = ny;
     t.nd = nd;
     t.scale = 1.0;
+    t.inv_scale = 1.0;
     t.tab = tab;
-    hipLaunchKernelGGL(pino::k_table_eval, dim3(grid), dim3(256), (size_t)(nx + ny + nd) * sizeof(double),
+    t.indexed = 0;
+    hipLaunchKernelGGL(pino::k_table_eval, dim3(grid), dim3(256), pino::table_lds_bytes(t),
                        static_cast<hipStream_t>(hip_stream), t, qx, qy, qd, out, m);
     INTERP_HIP(hipGetLastError());
     return PINO_OK;

@@ -61,6 +61,114 @@ __global__ void __launch_bounds__(64) k_spline_build(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Table splines (the per-radius rebuild of the Tabulated method): every
+// delta row of the table shares the knots, so the elimination coefficients
+// of the system above are computed once, k_spline_coef, and each row then
+// needs only multiplies and adds, k_table_splines.  For unknown i
+// (1 <= i <= n-2), with h_i = x_{i+1} - x_i and x_k = xk[k] * scale:
+//   den_i = 2 (h_{i-1} + h_i) - h_{i-1} c_{i-1},  c_i = h_i / den_i (c_0 = 0),
+//   coef[4i .. 4i+3] = {1/h_i, h_{i-1}, 1/den_i, c_i};  coef[0] = 1/h_0.
+// One wave: the lanes scale the knots into LDS (at most kCoefKnots; the
+// host checks n) and fill the independent entries; lane 0 runs the
+// recurrence, whose knot reads come from LDS.
+// ---------------------------------------------------------------------------
+constexpr int kCoefKnots = 4096;
+
+__global__ void __launch_bounds__(64) k_spline_coef(const double* __restrict__ xk, int n, double scale,
+                                                   double* __restrict__ coef)
+{
+    __shared__ double xs[kCoefKnots];
+    if (blockIdx.x != 0)
+        return;
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        xs[k] = xk[k] * scale;
+    __syncthreads();
+    for (int i = threadIdx.x; i <= n - 2; i += blockDim.x) {
+        const double h = xs[i + 1] - xs[i];
+        coef[4 * i] = 1.0 / h;
+        if (i + 1 <= n - 2)
+            coef[4 * (i + 1) + 1] = h;
+    }
+    if (threadIdx.x != 0)
+        return;
+    coef[1] = coef[2] = coef[3] = 0.0;
+    double hl = xs[1] - xs[0];
+    double cprev = 0.0;
+    for (int i = 1; i <= n - 2; ++i) {
+        const double hr = xs[i + 1] - xs[i];
+        const double iden = 1.0 / (2.0 * (hl + hr) - hl * cprev);
+        const double c = hr * iden;
+        coef[4 * i + 2] = iden;
+        coef[4 * i + 3] = c;
+        cprev = c;
+        hl = hr;
+    }
+}
+
+// Row r of F ([rows][n]) into the interleaved table: tab[2 (r n + k)] = F,
+// tab[2 (r n + k) + 1] = M_k.  One row per lane: forward elimination
+//   d_i = (6 [(y_{i+1} - y_i)/h_i - (y_i - y_{i-1})/h_{i-1}] - h_{i-1} d_{i-1}) / den_i
+// (d_i stored in the M slot), then back substitution M_i = d_i - c_i M_{i+1}.
+// The row's values are read kSplineBatch at a time so their loads overlap;
+// the coefficients are wave-uniform loads.
+constexpr int kSplineBatch = 32;
+
+__global__ void __launch_bounds__(64) k_table_splines(const double* __restrict__ coef, int n,
+                                                     const double* __restrict__ F, double* __restrict__ tab,
+                                                     int rows)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows)
+        return;
+    const double* y = F + (int64_t)r * n;
+    double* t = tab + (int64_t)r * n * 2;
+    const double y0 = y[0];
+    double yc = y[1];
+    t[0] = y0;
+    t[1] = 0.0;
+    double sl = (yc - y0) * coef[0];  // slope of the interval left of unknown i
+    double dprev = 0.0;
+    for (int i0 = 1; i0 <= n - 2; i0 += kSplineBatch) {
+        double yn[kSplineBatch];
+#pragma unroll
+        for (int k = 0; k < kSplineBatch; ++k)
+            yn[k] = i0 + k + 1 < n ? y[i0 + k + 1] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kSplineBatch; ++k) {
+            const int i = i0 + k;
+            if (i <= n - 2) {
+                const double* cf = coef + 4 * i;
+                const double sr = (yn[k] - yc) * cf[0];
+                const double d = (6.0 * (sr - sl) - cf[1] * dprev) * cf[2];
+                t[2 * i] = yc;
+                t[2 * i + 1] = d;
+                dprev = d;
+                sl = sr;
+                yc = yn[k];
+            }
+        }
+    }
+    t[2 * (n - 1)] = yc;
+    t[2 * (n - 1) + 1] = 0.0;
+    double mnext = 0.0;
+    for (int i0 = n - 2; i0 >= 1; i0 -= kSplineBatch) {
+        double dv[kSplineBatch];
+#pragma unroll
+        for (int k = 0; k < kSplineBatch; ++k)
+            dv[k] = i0 - k >= 1 ? t[2 * (i0 - k) + 1] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kSplineBatch; ++k) {
+            const int i = i0 - k;
+            if (i >= 1) {
+                const double v = dv[k] - coef[4 * i + 3] * mnext;
+                t[2 * i + 1] = v;
+                mnext = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per-radius Classic FP64 kernel.  One particle per lane per step of a
 // grid-stride loop; the growth knots [D | a | M] of the item's cosmology are
 // staged once per workgroup in LDS.  Hessian loads are coalesced SoA reads
@@ -297,7 +405,15 @@ k_classic_f64(ItemArgs a)
 // Tabulated FP64.  The library keeps, per radius, an interleaved copy of the
 // table, tab[((ix*ny + iy)*nd + id)*2 + {0,1}] = (F, M), so the two knots of a
 // corner spline are 32 contiguous bytes.  Knots (scaled by sigma_R) live in
-// LDS after the growth knots.
+// LDS after the growth knots, followed by the per-axis interval index.
+//
+// Interval index (per axis, optional): nb uniform bins over the dimensionless
+// knot range; bin b holds the interval `locate` returns at the bin's low end
+// less a margin of 1 % of a bin, and the host has verified that at most two
+// more knots lie below the bin's high end plus the margin, so two compares
+// (whose knot reads are independent) finish the search.  The margin is far
+// above the rounding of the bin arithmetic, and the interval found is the one
+// `locate` finds.  Without the index (indexed = 0) the binary search is used.
 // ---------------------------------------------------------------------------
 struct TabArgs {
     const double* xk;  // dimensionless knots, nx, ny, nd
@@ -305,44 +421,137 @@ struct TabArgs {
     const double* dk;
     int nx, ny, nd;
     double scale;      // sigma_R
+    double inv_scale;  // 1 / sigma_R
     const double* tab; // interleaved (F, M)
+    const int* bidx;   // interval index bins, x | y | delta (nb[0] + nb[1] + nb[2])
+    int nb[3];
+    double k0[3];      // first dimensionless knot per axis
+    double bpu[3];     // bins per dimensionless unit
+    int indexed;
 };
 
-__device__ __forceinline__ double corner(const double* __restrict__ tab, int64_t row, int nd, int j, double d0,
-                                         double d1, double q)
+// Interval of the scaled knots xs (n) containing q: `locate`, through the
+// axis index when there is one.
+__host__ __device__ __forceinline__ int table_locate(const TabArgs& t, int axis, const int* idx, const double* xs, int n,
+                                            double q)
 {
-    const double2* p = reinterpret_cast<const double2*>(tab + (row * nd + j) * 2);
-    const double2 lo = p[0];
-    const double2 hi = p[1];
-    return spline_piece(d0, d1, lo.x, hi.x, lo.y, hi.y, q);
+    if (!t.indexed)
+        return locate(xs, n, q);
+    double fb = (q * t.inv_scale - t.k0[axis]) * t.bpu[axis];
+    fb = fmin(fmax(fb, 0.0), (double)(t.nb[axis] - 1));
+    const int i = idx[(int)fb];
+    const double x1 = xs[min(i + 1, n - 1)];
+    const double x2 = xs[min(i + 2, n - 1)];
+    const int c1 = (i + 1 <= n - 2 && x1 <= q) ? 1 : 0;
+    const int c2 = (c1 && i + 2 <= n - 2 && x2 <= q) ? 1 : 0;
+    return i + c1 + c2;
 }
 
-// The table at (x, y, delta): splines in delta at the four corners of the
-// (x, y) cell, then bilinear; knots xs, ys, ds (in LDS).
-__device__ __forceinline__ double table_at(const TabArgs& t, const double* xs, const double* ys, const double* ds,
-                                           double x, double y, double delta)
+// A table query resolved to its cell: the double2 offset of corner (ix, iy)
+// at knot j, the bilinear weights and the spline abscissae.  Offsets are in
+// range for any input (non-finite queries land in cell 0 or the last cell).
+struct TabQ {
+    uint32_t r;
+    double tt, uu, d0, d1, dq;
+};
+
+__device__ __forceinline__ TabQ table_query(const TabArgs& t, const double* xs, const double* ys, const double* ds,
+                                            const int* idx, double x, double y, double delta)
 {
-    const int ix = locate(xs, t.nx, x);
-    const int iy = locate(ys, t.ny, y);
-    const double tt = fmin(fmax((x - xs[ix]) * rcp2(xs[ix + 1] - xs[ix]), 0.0), 1.0);
-    const double uu = fmin(fmax((y - ys[iy]) * rcp2(ys[iy + 1] - ys[iy]), 0.0), 1.0);
-    const double dq = fmin(fmax(delta, ds[0]), ds[t.nd - 1]);
-    const int j = locate(ds, t.nd, dq);
-    const double d0 = ds[j], d1 = ds[j + 1];
-    const int64_t r00 = (int64_t)ix * t.ny + iy;
-    const double v00 = corner(t.tab, r00, t.nd, j, d0, d1, dq);
-    const double v01 = corner(t.tab, r00 + 1, t.nd, j, d0, d1, dq);
-    const double v10 = corner(t.tab, r00 + t.ny, t.nd, j, d0, d1, dq);
-    const double v11 = corner(t.tab, r00 + t.ny + 1, t.nd, j, d0, d1, dq);
+    const int ix = table_locate(t, 0, idx, xs, t.nx, x);
+    const int iy = table_locate(t, 1, idx + t.nb[0], ys, t.ny, y);
+    TabQ q;
+    q.tt = fmin(fmax((x - xs[ix]) * rcp2(xs[ix + 1] - xs[ix]), 0.0), 1.0);
+    q.uu = fmin(fmax((y - ys[iy]) * rcp2(ys[iy + 1] - ys[iy]), 0.0), 1.0);
+    q.dq = fmin(fmax(delta, ds[0]), ds[t.nd - 1]);
+    const int j = table_locate(t, 2, idx + t.nb[0] + t.nb[1], ds, t.nd, q.dq);
+    q.d0 = ds[j];
+    q.d1 = ds[j + 1];
+    q.r = (uint32_t)((ix * t.ny + iy) * t.nd + j);
+    return q;
+}
+
+// The 4 corners x 2 knots of a query's cell: c[2 * corner + {0, 1}], corners
+// (ix, iy), (ix, iy + 1), (ix + 1, iy), (ix + 1, iy + 1).
+__device__ __forceinline__ void table_load(const TabArgs& t, const TabQ& q, double2 (&c)[8])
+{
+    const double2* p = reinterpret_cast<const double2*>(t.tab) + q.r;
+    const uint32_t sy = (uint32_t)t.nd;
+    const uint32_t sx = (uint32_t)t.ny * sy;
+    c[0] = p[0];
+    c[1] = p[1];
+    c[2] = p[sy];
+    c[3] = p[sy + 1];
+    c[4] = p[sx];
+    c[5] = p[sx + 1];
+    c[6] = p[sx + sy];
+    c[7] = p[sx + sy + 1];
+}
+
+// Splines in delta at the four corners, then bilinear; clamped to >= 0.
+__device__ __forceinline__ double table_eval(const TabQ& q, const double2 (&c)[8])
+{
+    const double v00 = spline_piece(q.d0, q.d1, c[0].x, c[1].x, c[0].y, c[1].y, q.dq);
+    const double v01 = spline_piece(q.d0, q.d1, c[2].x, c[3].x, c[2].y, c[3].y, q.dq);
+    const double v10 = spline_piece(q.d0, q.d1, c[4].x, c[5].x, c[4].y, c[5].y, q.dq);
+    const double v11 = spline_piece(q.d0, q.d1, c[6].x, c[7].x, c[6].y, c[7].y, q.dq);
+    const double tt = q.tt, uu = q.uu;
     const double f = (1.0 - tt) * (1.0 - uu) * v00 + tt * (1.0 - uu) * v10 + (1.0 - tt) * uu * v01 + tt * uu * v11;
     return f > 0.0 ? f : 0.0;
 }
 
-// F from the eigenvalues: delta = l1 + l2 + l3, x = l1 - l2, y = l2 - l3.
-__device__ __forceinline__ double table_F(const TabArgs& t, const double* xs, const double* ys, const double* ds,
-                                          double l1, double l2, double l3)
+// The table at (x, y, delta): splines in delta at the four corners of the
+// (x, y) cell, then bilinear; knots xs, ys, ds and the index in LDS.
+__device__ __forceinline__ double table_at(const TabArgs& t, const double* xs, const double* ys, const double* ds,
+                                           const int* idx, double x, double y, double delta)
 {
-    return table_at(t, xs, ys, ds, l1 - l2, l2 - l3, l1 + l2 + l3);
+    const TabQ q = table_query(t, xs, ys, ds, idx, x, y, delta);
+    double2 c[8];
+    table_load(t, q, c);
+    return table_eval(q, c);
+}
+
+// Stage the scaled knots and the interval index at `base` (LDS); returns the
+// index's LDS address.
+__device__ __forceinline__ const int* stage_table(double* base, const TabArgs& t)
+{
+    double* xs = base;
+    double* ys = xs + t.nx;
+    double* ds = ys + t.ny;
+    int* idx = reinterpret_cast<int*>(ds + t.nd);
+    for (int k = threadIdx.x; k < t.nx; k += blockDim.x)
+        xs[k] = t.xk[k] * t.scale;
+    for (int k = threadIdx.x; k < t.ny; k += blockDim.x)
+        ys[k] = t.yk[k] * t.scale;
+    for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
+        ds[k] = t.dk[k] * t.scale;
+    if (t.indexed)
+        for (int k = threadIdx.x; k < t.nb[0] + t.nb[1] + t.nb[2]; k += blockDim.x)
+            idx[k] = t.bidx[k];
+    return idx;
+}
+
+// Eigenvalues of one particle and its table query (delta = l1 + l2 + l3,
+// x = l1 - l2, y = l2 - l3); `finite` is false for non-finite eigenvalues,
+// whose F is 0.
+__device__ __forceinline__ TabQ tabulated_query(const TabArgs& t, const double* xs, const double* ys,
+                                                const double* ds, const int* idx, const Hess64& h, bool& finite)
+{
+    double l1, l2, l3;
+    eig_all(h, l1, l2, l3);
+    finite = isfinite(l1) && isfinite(l2) && isfinite(l3);
+    return table_query(t, xs, ys, ds, idx, l1 - l2, l2 - l3, l1 + l2 + l3);
+}
+
+__device__ __forceinline__ double tabulated_of(const TabArgs& t, const double* xs, const double* ys,
+                                              const double* ds, const int* idx, const Hess64& h)
+{
+    bool finite;
+    const TabQ q = tabulated_query(t, xs, ys, ds, idx, h, finite);
+    double2 c[8];
+    table_load(t, q, c);
+    const double F = table_eval(q, c);
+    return finite ? F : 0.0;
 }
 
 __global__ void __launch_bounds__(256) k_tabulated_f64_1(ItemArgs a, TabArgs t)
@@ -353,12 +562,7 @@ __global__ void __launch_bounds__(256) k_tabulated_f64_1(ItemArgs a, TabArgs t)
     double* xs = lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
     double* ys = xs + t.nx;
     double* ds = ys + t.ny;
-    for (int k = threadIdx.x; k < t.nx; k += blockDim.x)
-        xs[k] = t.xk[k] * t.scale;
-    for (int k = threadIdx.x; k < t.ny; k += blockDim.x)
-        ys[k] = t.yk[k] * t.scale;
-    for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
-        ds[k] = t.dk[k] * t.scale;
+    const int* idx = stage_table(xs, t);
     __syncthreads();
     // One particle per lane (arrays not 16-byte aligned); the next element's
     // loads issued ahead of the current arithmetic.
@@ -379,26 +583,13 @@ __global__ void __launch_bounds__(256) k_tabulated_f64_1(ItemArgs a, TabArgs t)
             hn = load_h64(a, next);
             fn = a.reset ? 0.0 : *elem(a.Fmax, next);
         }
-        double l1, l2, l3;
-        eig_all(h, l1, l2, l3);
-        const bool finite = isfinite(l1) && isfinite(l2) && isfinite(l3);
-        const double F = finite ? table_F(t, xs, ys, ds, l1, l2, l3) : 0.0;
-        update_max(a, g, gi, i, F, fm);
+        update_max(a, g, gi, i, tabulated_of(t, xs, ys, ds, idx, h), fm);
     }
 }
 
-// Table value of one particle: all three eigenvalues, then table_F
-__device__ __forceinline__ double tabulated_of(const TabArgs& t, const double* xs, const double* ys,
-                                              const double* ds, const Hess64& h)
-{
-    double l1, l2, l3;
-    eig_all(h, l1, l2, l3);
-    const bool finite = isfinite(l1) && isfinite(l2) && isfinite(l3);
-    return finite ? table_F(t, xs, ys, ds, l1, l2, l3) : 0.0;
-}
-
-// Two adjacent particles per lane, as k_classic_f64 (eight corner gathers
-// in flight per lane instead of four).
+// Two adjacent particles per lane, as k_classic_f64.  Both particles' cells
+// are located before either's corners are read, so all 16 corner gathers of
+// the lane are in flight together.
 __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
 {
     extern __shared__ double lds[];
@@ -407,12 +598,7 @@ __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
     double* xs = lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
     double* ys = xs + t.nx;
     double* ds = ys + t.ny;
-    for (int k = threadIdx.x; k < t.nx; k += blockDim.x)
-        xs[k] = t.xk[k] * t.scale;
-    for (int k = threadIdx.x; k < t.ny; k += blockDim.x)
-        ys[k] = t.yk[k] * t.scale;
-    for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
-        ds[k] = t.dk[k] * t.scale;
+    const int* idx = stage_table(xs, t);
     __syncthreads();
     const uint32_t n = (uint32_t)a.n;
     const uint32_t np = n / 2;
@@ -434,15 +620,28 @@ __global__ void __launch_bounds__(256) k_tabulated_f64(ItemArgs a, TabArgs t)
             if (!a.reset)
                 fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * next));
         }
-        const double F0 = tabulated_of(t, xs, ys, ds, Hess64{h.xx.x, h.yy.x, h.zz.x, h.xy.x, h.xz.x, h.yz.x});
-        const double F1 = tabulated_of(t, xs, ys, ds, Hess64{h.xx.y, h.yy.y, h.zz.y, h.xy.y, h.xz.y, h.yz.y});
-        update_pair(a, g, gi, p, F0, F1, fm);
+        bool f0, f1;
+        const TabQ q0 = tabulated_query(t, xs, ys, ds, idx, Hess64{h.xx.x, h.yy.x, h.zz.x, h.xy.x, h.xz.x, h.yz.x}, f0);
+        const TabQ q1 = tabulated_query(t, xs, ys, ds, idx, Hess64{h.xx.y, h.yy.y, h.zz.y, h.xy.y, h.xz.y, h.yz.y}, f1);
+        double2 c0[8], c1[8];
+        table_load(t, q0, c0);
+        table_load(t, q1, c1);
+        const double F0 = table_eval(q0, c0);
+        const double F1 = table_eval(q1, c1);
+        update_pair(a, g, gi, p, f0 ? F0 : 0.0, f1 ? F1 : 0.0, fm);
     }
     if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t i = n - 1;
         const double fm = a.reset ? 0.0 : *elem(a.Fmax, i);
-        update_max(a, g, gi, i, tabulated_of(t, xs, ys, ds, load_h64(a, i)), fm);
+        update_max(a, g, gi, i, tabulated_of(t, xs, ys, ds, idx, load_h64(a, i)), fm);
     }
+}
+
+// LDS bytes of stage_table
+__host__ __device__ inline size_t table_lds_bytes(const TabArgs& t)
+{
+    return sizeof(double) * ((size_t)t.nx + t.ny + t.nd) +
+           (t.indexed ? sizeof(int) * ((size_t)t.nb[0] + t.nb[1] + t.nb[2]) : 0);
 }
 
 // Interval index of a growth table (see GrowthIndex): bin b covers
@@ -462,24 +661,6 @@ __global__ void __launch_bounds__(256) k_growth_index(const double* __restrict__
     const int i1 = locate(D, n, hi);
     idx[b] = i0;
     need[b] = i1 - i0;
-}
-
-// dst[k] = src[k] * scale
-__global__ void __launch_bounds__(256) k_scale_copy(const double* __restrict__ src, int n, double scale,
-                                                   double* __restrict__ dst)
-{
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-        dst[k] = src[k] * scale;
-}
-
-// copy the caller's F values into the even slots of the interleaved table
-// (the spline build writes M into the odd slots)
-__global__ void __launch_bounds__(256) k_table_copy_F(const double* __restrict__ F, double* __restrict__ tab,
-                                                     int64_t count)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count)
-        tab[2 * i] = F[i];
 }
 
 }  // namespace pino

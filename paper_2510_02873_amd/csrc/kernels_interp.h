@@ -41,16 +41,11 @@ __global__ void __launch_bounds__(256) k_table_eval(TabArgs t, const double* __r
     double* xs = lds;
     double* ys = xs + t.nx;
     double* ds = ys + t.ny;
-    for (int k = threadIdx.x; k < t.nx; k += blockDim.x)
-        xs[k] = t.xk[k];
-    for (int k = threadIdx.x; k < t.ny; k += blockDim.x)
-        ys[k] = t.yk[k];
-    for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
-        ds[k] = t.dk[k];
+    const int* idx = stage_table(xs, t);
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
-        out[i] = table_at(t, xs, ys, ds, qx[i], qy[i], qd[i]);
+        out[i] = table_at(t, xs, ys, ds, idx, qx[i], qy[i], qd[i]);
 }
 
 }  // namespace pino

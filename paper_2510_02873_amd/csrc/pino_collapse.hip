@@ -91,6 +91,10 @@ bool validate_config(const pino_config* cfg, std::string& why)
             why = "tabulated method needs table knots with nx, ny >= 2 and nd >= 4";
             return false;
         }
+        if (t->nd > kCoefKnots) {
+            why = "table with more than " + std::to_string(kCoefKnots) + " delta knots";
+            return false;
+        }
         if ((int64_t)t->nx * t->ny * t->nd > kMaxTableCells) {
             why = "table larger than 2^24 cells";
             return false;
@@ -206,6 +210,31 @@ bool lds_fits(const pino_config* cfg, std::string& why)
     return true;
 }
 
+// Interval index of one axis of dimensionless table knots k[n] (TabArgs):
+// 4 (n - 1) uniform bins, each holding the interval at its low end less a
+// margin of 1 % of a bin; false if more than two knots can follow inside a
+// bin (the kernels then use the binary search) or if the margin is not far
+// above the rounding of the bin arithmetic.
+bool table_axis_index(const double* k, int n, std::vector<int>& idx, int& nb, double& k0, double& bpu)
+{
+    nb = 4 * (n - 1);
+    const double lo = k[0], hi = k[n - 1];
+    const double w = (hi - lo) / nb;
+    const double margin = 0.01 * w;
+    k0 = lo;
+    bpu = 1.0 / w;
+    if (!(w > 0.0) || !std::isfinite(bpu) || margin < 1e-12 * std::max(std::fabs(lo), std::fabs(hi)))
+        return false;
+    for (int b = 0; b < nb; ++b) {
+        const int i0 = locate(k, n, lo + b * w - margin);
+        const int i1 = locate(k, n, lo + (b + 1) * w + margin);
+        if (i1 - i0 > 2)
+            return false;
+        idx.push_back(i0);
+    }
+    return true;
+}
+
 bool aligned(const void* p, uintptr_t bytes)
 {
     return (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
@@ -222,13 +251,14 @@ void free_all(pino_ctx* c)
 {
     if (!c)
         return;
-    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tab,
-                    c->d_dscaled, c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_qcount};
+    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tidx, c->d_tab,
+                    c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_qcount};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
-    c->d_growth = c->d_tknots = c->d_tab = c->d_dscaled = c->d_tmp = nullptr;
+    c->d_growth = c->d_tknots = c->d_tab = c->d_tmp = nullptr;
     c->d_gidx = nullptr;
+    c->d_tidx = nullptr;
     c->d_growth32 = nullptr;
     c->d_mlp = nullptr;
     c->d_counters = nullptr;
@@ -280,10 +310,24 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
         kn.insert(kn.end(), t->delta, t->delta + t->nd);
         PINO_HIP(c, hipMalloc((void**)&c->d_tknots, kn.size() * sizeof(double)));
         PINO_HIP(c, hipMemcpy(c->d_tknots, kn.data(), kn.size() * sizeof(double), hipMemcpyHostToDevice));
+        // the interval index, used when all three axes admit it and it fits
+        // the LDS budget beside the growth and table knots
+        std::vector<int> bins;
+        const double* axes[3] = {t->x, t->y, t->delta};
+        const int ns[3] = {t->nx, t->ny, t->nd};
+        bool ok = true;
+        for (int ax = 0; ax < 3 && ok; ++ax)
+            ok = table_axis_index(axes[ax], ns[ax], bins, c->tnb[ax], c->tk0[ax], c->tbpu[ax]);
+        const size_t lds_need = growth_lds_bytes(nk_max, index_bins(nk_max)) +
+                                sizeof(double) * kn.size() + sizeof(int) * bins.size();
+        if (ok && lds_need <= kLdsBudget) {
+            PINO_HIP(c, hipMalloc((void**)&c->d_tidx, bins.size() * sizeof(int)));
+            PINO_HIP(c, hipMemcpy(c->d_tidx, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice));
+            c->tindexed = 1;
+        }
         const int64_t cells = (int64_t)t->nx * t->ny * t->nd;
         PINO_HIP(c, hipMalloc((void**)&c->d_tab, 2 * cells * sizeof(double)));
-        PINO_HIP(c, hipMalloc((void**)&c->d_dscaled, t->nd * sizeof(double)));
-        tmp_doubles = std::max(tmp_doubles, cells);
+        tmp_doubles = std::max<int64_t>(tmp_doubles, 4 * (int64_t)t->nd);  // spline coefficients
     }
     PINO_HIP(c, hipMalloc((void**)&c->d_tmp, tmp_doubles * sizeof(double)));
 
@@ -374,19 +418,14 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
     const size_t lds = growth_lds_bytes(a.nk, a.gi.nb);
 
     if (c->method == PINO_TABULATED) {
-        // per-radius table: copy F into the interleaved table and rebuild the
-        // delta splines on the device
-        const int64_t rows = (int64_t)c->nx * c->ny;
-        const int64_t cells = rows * c->nd;
-        hipLaunchKernelGGL(k_table_copy_F, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, it.table_F,
-                           c->d_tab, cells);
-        PINO_HIP(c, hipGetLastError());
+        // per-radius table: F into the interleaved table and the delta
+        // splines over the sigma-scaled knots, rebuilt on the device
+        const int rows = c->nx * c->ny;
         const double* dks = c->d_tknots + c->nx + c->ny;
-        hipLaunchKernelGGL(k_scale_copy, dim3(1), dim3(256), 0, st, dks, c->nd, it.sigma_R, c->d_dscaled);
+        hipLaunchKernelGGL(k_spline_coef, dim3(1), dim3(64), 0, st, dks, c->nd, it.sigma_R, c->d_tmp);
         PINO_HIP(c, hipGetLastError());
-        hipLaunchKernelGGL(k_spline_build, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, c->d_dscaled,
-                           c->nd, it.table_F, (int64_t)c->nd, 1, c->d_tab + 1, (int64_t)2 * c->nd, 2,
-                           c->d_tmp, (int)rows);
+        hipLaunchKernelGGL(k_table_splines, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, c->d_tmp, c->nd,
+                           it.table_F, c->d_tab, rows);
         PINO_HIP(c, hipGetLastError());
     }
 
@@ -423,8 +462,16 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
                 t.ny = c->ny;
                 t.nd = c->nd;
                 t.scale = it.sigma_R;
+                t.inv_scale = 1.0 / it.sigma_R;
                 t.tab = c->d_tab;
-                const size_t lds_t = lds + (size_t)(c->nx + c->ny + c->nd) * sizeof(double);
+                t.bidx = c->d_tidx;
+                t.indexed = c->tindexed;
+                for (int ax = 0; ax < 3; ++ax) {
+                    t.nb[ax] = c->tnb[ax];
+                    t.k0[ax] = c->tk0[ax];
+                    t.bpu[ax] = c->tbpu[ax];
+                }
+                const size_t lds_t = lds + table_lds_bytes(t);
                 if (al)
                     hipLaunchKernelGGL(k_tabulated_f64, dim3(gp), dim3(block), lds_t, st, a, t);
                 else

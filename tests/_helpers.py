@@ -58,7 +58,9 @@ def compare(ref, got, rel=REL_TOL, tie_mask=None, label=""):
     small = ~big
     if small.any():
         assert np.max(np.abs(Fr[small] - Fg[small])) <= 1e-15, f"{label}: small-F mismatch"
-    mism = Rr != Rg
+    # a particle whose collapse decision flips within the 1e-15 allowance on F
+    # (checked above) has no unique radius index
+    mism = (Rr != Rg) & ((Fr > 0) == (Fg > 0))
     if tie_mask is not None:
         mism &= ~tie_mask
     assert not mism.any(), f"{label}: {int(mism.sum())} radius-index mismatches"

@@ -134,3 +134,39 @@ def test_tabulated_unaligned_arrays_match_aligned(pkg, orc, n):
                       table_F=tF)
         torch.cuda.synchronize()
         assert torch.equal(F1, F2) and torch.equal(R1, R2) and torch.equal(A1, A2)
+
+
+@pytest.mark.parametrize("spacing", ["uniform", "clustered"])
+def test_tabulated_interval_search_modes(pkg, orc, spacing):
+    """Uniform knots take the kernels' binned interval search, knots
+    clustered at one end (a cubic spacing) the binary search; both match the
+    oracle, with queries on and next to the knots, at the bin edges and far
+    outside the table.  The table holds a smooth function bounded away from
+    zero, so every particle collapses and a wrong interval shows in F."""
+    rng = np.random.default_rng(17)
+    t = np.linspace(0.0, 1.0, 33)
+    if spacing == "uniform":
+        xk, yk, dk = 6.0 * t[:25], 6.0 * t[:21], -4.0 + 12.0 * t
+    else:
+        xk, yk, dk = 6.0 * t[:25] ** 3, 6.0 * t[:21] ** 3, -4.0 + 12.0 * t ** 3
+    xk, yk = xk / xk[-1] * 6.0, yk / yk[-1] * 6.0
+    sigma = 0.7
+    X, Y, Dl = np.meshgrid(xk * sigma, yk * sigma, dk * sigma, indexing="ij")
+    tab = orc.Table(xk * sigma, yk * sigma, dk * sigma,
+                    1.5 + np.sin(1.3 * X + 0.4) * np.cos(0.7 * Y) + 0.05 * (Dl - 1.0) ** 2)
+    pts = [rng.uniform(-1, 7, 3000), rng.uniform(-1, 7, 3000), rng.uniform(-6, 10, 3000)]
+    for ax, k in enumerate((xk, yk, dk)):
+        edges = k[0] + (k[-1] - k[0]) * np.arange(4 * (len(k) - 1) + 1) / (4 * (len(k) - 1))
+        on = np.concatenate([k, edges, np.nextafter(k, -np.inf), np.nextafter(k, np.inf)])
+        pts[ax] = np.concatenate([pts[ax], rng.permutation(np.resize(on, 3000))])
+    pts = [np.concatenate([p, [-50.0, 50.0, 1e6]]) for p in pts]
+    m = min(len(p) for p in pts)
+    x, y, d = (p[:m] * sigma for p in pts)
+    x, y = np.abs(x), np.abs(y)
+    l2 = (d - x + y) / 3.0
+    h6 = np.zeros((6, m))
+    h6[0], h6[1], h6[2] = l2 + x, l2, l2 - y
+    a, D = synth.growth_table(0.3)
+    ref, got, _ = _run(pkg, orc, (xk, yk, dk), [h6], [sigma], a, D, tables=[tab])
+    assert np.all(ref[0] > 0.4)
+    compare(ref, got, label=f"interval search {spacing}")
