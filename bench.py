@@ -71,7 +71,7 @@ def _time_steps(step, steps, stream):
 
 
 def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, steps, dk=None,
-                   updates=None):
+                   updates=None, train_steps=TRAIN_STEPS):
     """Secondary rates on the same resident fields: mixed precision (FP32
     copies of the Hessians) and the Tabulated method (64 x 64 x 128 tables
     filled per radius by the library's Classic kernel on the table's sample
@@ -113,7 +113,8 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                     "roofline": step_roofline(step_bytes(24), ms)}
     mcol.close()
 
-    out["surrogate"] = measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps)
+    out["surrogate"] = measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps,
+                                         train_steps)
     # stream floor: FP32 Hessians once per particle (the deferred particles'
     # second read by the fallback kernel is not counted)
     out["surrogate"]["roofline"] = step_roofline(step_bytes(24), out["surrogate"]["ms_per_step"])
@@ -294,7 +295,8 @@ def measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps, co
     return res
 
 
-def measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps):
+def measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps,
+                      train_steps=TRAIN_STEPS):
     """Learned surrogate + certify on the same fields (FP32 inputs): train the
     network with the library's kernels on 20M (inputs, target) pairs from the
     benchmark fields and four perturbed cosmologies (untimed), then time the
@@ -332,7 +334,7 @@ def measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F
     n_pairs = x.shape[0]
     log(f"surrogate: {n_pairs} training pairs in {time.time() - t0:.1f}s")
     t1 = time.time()
-    blob, _, hist = surrogate.train(x, w, steps=TRAIN_STEPS, batch=16384, lr_max=3e-3, seed=7, log_every=10000,
+    blob, _, hist = surrogate.train(x, w, steps=train_steps, batch=16384, lr_max=3e-3, seed=7, log_every=10000,
                                     log=lambda m: log(m))
     train_s = time.time() - t1
     del x, w
@@ -361,7 +363,7 @@ def measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F
            "rel_Dc_vs_fp64_field": {"max": float(rel.max()), "p99.9": float(np.percentile(rel, 99.9)),
                                     "mean": float(rel.mean())},
            "index_mismatch_frac": float((Rs != R64).double().mean().item()),
-           "training": {"pairs": int(n_pairs), "steps": TRAIN_STEPS, "batch": 16384, "seconds": round(train_s, 1),
+           "training": {"pairs": int(n_pairs), "steps": train_steps, "batch": 16384, "seconds": round(train_s, 1),
                         "final_loss": hist[-1][1] if hist else None}}
     scol.close()
     log(f"surrogate+certify {res['value']:.3e} evals/s, fallback {res['fallback_fraction_of_consulted']:.3f}")
@@ -450,6 +452,9 @@ def main():
                     help="skip the secondary measurements (mixed precision, Tabulated) on the same fields")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched 64-realisation workload (182 GB of resident Hessians)")
+    ap.add_argument("--train-steps", type=int, default=TRAIN_STEPS,
+                    help="optimiser steps of the surrogate's (untimed) training; counter-collection runs, which "
+                         "serialise every dispatch, shorten it")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB device-to-device once, so HBM "
                          "counters can be scaled against a transfer of known size")
@@ -586,7 +591,7 @@ def main():
     extras = {}
     if not args.no_extras:
         extras = measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, args.steps, dk,
-                                updates)
+                                updates, args.train_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
