@@ -118,7 +118,6 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
     # stream floor: FP32 Hessians once per particle (the deferred particles'
     # second read by the fallback kernel is not counted)
     out["surrogate"]["roofline"] = step_roofline(step_bytes(24), out["surrogate"]["ms_per_step"])
-    del s32
 
     # Tabulated: fill each radius' table with the Classic kernel on the
     # table's sample points (diagonal Hessians), then interpolate
@@ -148,6 +147,32 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                         "roofline_note": "HBM streams only; the corner gathers (128 B per evaluation) are served "
                                          "from L2/MALL (8.4 MB table)"}
     tcol.close()
+
+    # Tabulated in mixed precision: FP32 Hessians, FP32 knot-pair table (four
+    # 16-byte corner reads per evaluation), FP64 interpolation arithmetic
+    mtcol = P.Collapse([(a, D)], method=P.PINO_TABULATED, precision=P.PINO_MIXED, table_knots=knots)
+    Fq, Rq, Aq = mtcol.outputs(n)
+    qitems = [mtcol.item(s32[r], Fq, Rq, Aq if r == last else None, radius_index=r, sigma_R=sig[r],
+                         table_F=tabs[r]) for r in range(len(radii))]
+
+    def qstep():
+        for r, it in enumerate(qitems):
+            mtcol.eval([it], reset=(r == 0), finalize=(r == last), stream=stream)
+
+    ms = _time_steps(qstep, steps, stream)
+    relq = ((Fq[both] - Ft[both]).abs() / Ft[both]).cpu().numpy()
+    out["tabulated_mixed"] = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s",
+                              "ms_per_step": round(ms, 4),
+                              "dtype": "f32 inputs and table, f64 eigen/search/interpolation",
+                              "rel_F_vs_fp64_tabulated": {"max": float(relq.max()),
+                                                          "p99.9": float(np.percentile(relq, 99.9)),
+                                                          "mean": float(relq.mean())},
+                              "index_mismatch_frac": float((Rq != Rt).double().mean().item()),
+                              "roofline": step_roofline(step_bytes(24), ms),
+                              "roofline_note": "HBM streams only; the corner gathers (64 B per evaluation) are "
+                                               "served from L2/MALL"}
+    mtcol.close()
+    del s32
 
     if dk is not None:
         out["field_fused"] = measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps, [(a, D)])

@@ -65,9 +65,14 @@ typedef enum { PINO_CLASSIC = 0, PINO_TABULATED = 1 } pino_method;
 
 /* Arithmetic of the evaluation.
  *   PINO_FP64      : FP64 Hessians, FP64 throughout.
- *   PINO_MIXED     : FP32 Hessians; eigenvalues and interpolation in FP32,
- *                    FP64 for nearly degenerate eigenvalues and for the final
- *                    polish of the collapse root (Classic).
+ *   PINO_MIXED     : FP32 Hessians.  Classic: eigenvalues and interpolation
+ *                    in FP32, FP64 for nearly degenerate eigenvalues and for
+ *                    the final polish of the collapse root.  Tabulated: the
+ *                    Hessians widened to FP64 for the eigenvalues and the
+ *                    cell search, the table read from an FP32 copy built on
+ *                    the device each radius (F and the spline second
+ *                    derivatives rounded to FP32), the interpolation in FP64.
+ *                    a(D) in FP32 for both.
  *   PINO_SURROGATE : FP32 Hessians; a small network predicts the collapse
  *                    growth factor and one FP64 Newton step refines it; the
  *                    result is accepted only if the first root of the

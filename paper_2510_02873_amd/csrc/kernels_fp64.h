@@ -451,7 +451,8 @@ __host__ __device__ __forceinline__ int table_locate(const TabArgs& t, int axis,
 // at knot j, the bilinear weights and the spline abscissae.  Offsets are in
 // range for any input (non-finite queries land in cell 0 or the last cell).
 struct TabQ {
-    uint32_t r;
+    uint32_t r;   // (row nd + j), row = ix ny + iy: the (F, M) table
+    uint32_t rp;  // (row (nd - 1) + j): the FP32 knot-pair table (mixed precision)
     double tt, uu, d0, d1, dq;
 };
 
@@ -467,7 +468,9 @@ __device__ __forceinline__ TabQ table_query(const TabArgs& t, const double* xs, 
     const int j = table_locate(t, 2, idx + t.nb[0] + t.nb[1], ds, t.nd, q.dq);
     q.d0 = ds[j];
     q.d1 = ds[j + 1];
-    q.r = (uint32_t)((ix * t.ny + iy) * t.nd + j);
+    const int row = ix * t.ny + iy;
+    q.r = (uint32_t)(row * t.nd + j);
+    q.rp = (uint32_t)(row * (t.nd - 1) + j);
     return q;
 }
 

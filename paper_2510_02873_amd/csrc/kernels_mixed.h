@@ -111,6 +111,33 @@ __device__ __forceinline__ double mixed_F(const Hess32& h)
 
 typedef float f2v __attribute__((ext_vector_type(2)));
 
+// update_max_f32 for the pair (2p, 2p + 1): 16-byte Fmax and a_coll, 8-byte
+// Rmax accesses
+__device__ __forceinline__ void update_pair_f32(const ItemArgs& a, const float* g, const GrowthIndex& gi, uint32_t p,
+                                                double F0, double F1, d2v fm)
+{
+    const bool u0 = F0 > fm.x, u1 = F1 > fm.y;
+    const d2v fnew{u0 ? F0 : fm.x, u1 ? F1 : fm.y};
+    int2 rm{-1, -1};
+    if (!a.reset)
+        rm = *reinterpret_cast<const int2*>(elem(a.Rmax, 2 * p));
+    *reinterpret_cast<d2v*>(elem(a.Fmax, 2 * p)) = fnew;
+    *reinterpret_cast<int2*>(elem(a.Rmax, 2 * p)) = int2{u0 ? a.radius : rm.x, u1 ? a.radius : rm.y};
+    if (a.acoll) {
+        d2v* ac = reinterpret_cast<d2v*>(elem(a.acoll, 2 * p));
+        d2v v;
+        if (a.finalize) {
+            v.x = fnew.x > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew.x), gi) : kInf;
+            v.y = fnew.y > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew.y), gi) : kInf;
+        } else {
+            const d2v am = a.reset ? d2v{kInf, kInf} : *ac;
+            v.x = u0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F0), gi) : am.x;
+            v.y = u1 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F1), gi) : am.y;
+        }
+        *ac = v;
+    }
+}
+
 // Two adjacent particles per lane (8-byte component loads, 16-byte Fmax and
 // a_coll, 8-byte Rmax; alignment checked by the host), as k_classic_f64.
 __global__ void __launch_bounds__(256) k_classic_mixed(ItemArgs a, const float* __restrict__ growth32)
@@ -143,26 +170,7 @@ __global__ void __launch_bounds__(256) k_classic_mixed(ItemArgs a, const float* 
             load(p + stride);
         const double F0 = mixed_F(Hess32{h[0].x, h[1].x, h[2].x, h[3].x, h[4].x, h[5].x});
         const double F1 = mixed_F(Hess32{h[0].y, h[1].y, h[2].y, h[3].y, h[4].y, h[5].y});
-        const bool u0 = F0 > fm.x, u1 = F1 > fm.y;
-        const d2v fnew{u0 ? F0 : fm.x, u1 ? F1 : fm.y};
-        int2 rm{-1, -1};
-        if (!a.reset)
-            rm = *reinterpret_cast<const int2*>(elem(a.Rmax, 2 * p));
-        *reinterpret_cast<d2v*>(elem(a.Fmax, 2 * p)) = fnew;
-        *reinterpret_cast<int2*>(elem(a.Rmax, 2 * p)) = int2{u0 ? a.radius : rm.x, u1 ? a.radius : rm.y};
-        if (a.acoll) {
-            d2v* ac = reinterpret_cast<d2v*>(elem(a.acoll, 2 * p));
-            d2v v;
-            if (a.finalize) {
-                v.x = fnew.x > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew.x), gi) : kInf;
-                v.y = fnew.y > 0.0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(fnew.y), gi) : kInf;
-            } else {
-                const d2v am = a.reset ? d2v{kInf, kInf} : *ac;
-                v.x = u0 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F0), gi) : am.x;
-                v.y = u1 ? (double)growth_invert_f32(g, a.nk, (float)rcp2(F1), gi) : am.y;
-            }
-            *ac = v;
-        }
+        update_pair_f32(a, g, gi, p, F0, F1, fm);
     }
     if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t i = n - 1;
@@ -184,5 +192,154 @@ __host__ __device__ inline size_t growth32_lds_bytes(int nk, int nb)
 {
     return (((size_t)3 * nk * sizeof(float) + 7) / 8) * 8 + (((size_t)nb * sizeof(int) + 7) / 8) * 8;
 }
+
+// ---------------------------------------------------------------------------
+// Mixed-precision Tabulated kernels: FP32 Hessians (24 B per particle),
+// widened to FP64 for the eigenvalues and the cell search, and an FP32 copy
+// of the table in which each (row, knot interval j) holds the 16-byte tuple
+// (F_j, M_j, F_{j+1}, M_{j+1}), so one corner spline is one 16-byte read
+// (four per particle instead of eight).  The interpolation arithmetic is
+// FP64 on the FP32 table values; a(D) from the FP32 growth knots, as in the
+// mixed Classic kernel.
+// ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// tab32[r (nd - 1) + j] = (F_j, M_j, F_{j+1}, M_{j+1}) of row r, from the
+// interleaved FP64 (F, M) table of the same radius
+__global__ void __launch_bounds__(256) k_table_pairs_f32(const double* __restrict__ tab, f4v* __restrict__ tab32,
+                                                        int rows, int nd)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)rows * (nd - 1))
+        return;
+    const int64_t r = k / (nd - 1);
+    const int64_t j = k - r * (nd - 1);
+    const double* s = tab + (r * nd + j) * 2;
+    tab32[k] = f4v{(float)s[0], (float)s[1], (float)s[2], (float)s[3]};
+}
+
+// corners (ix, iy), (ix, iy + 1), (ix + 1, iy), (ix + 1, iy + 1)
+__device__ __forceinline__ void table_load32(const TabArgs& t, const f4v* __restrict__ tab32, const TabQ& q,
+                                             f4v (&c)[4])
+{
+    const f4v* p = tab32 + q.rp;
+    const uint32_t sy = (uint32_t)t.nd - 1;
+    const uint32_t sx = (uint32_t)t.ny * sy;
+    c[0] = p[0];
+    c[1] = p[sy];
+    c[2] = p[sx];
+    c[3] = p[sx + sy];
+}
+
+__device__ __forceinline__ double table_eval32(const TabQ& q, const f4v (&c)[4])
+{
+    const double v00 = spline_piece(q.d0, q.d1, c[0].x, c[0].z, c[0].y, c[0].w, q.dq);
+    const double v01 = spline_piece(q.d0, q.d1, c[1].x, c[1].z, c[1].y, c[1].w, q.dq);
+    const double v10 = spline_piece(q.d0, q.d1, c[2].x, c[2].z, c[2].y, c[2].w, q.dq);
+    const double v11 = spline_piece(q.d0, q.d1, c[3].x, c[3].z, c[3].y, c[3].w, q.dq);
+    const double tt = q.tt, uu = q.uu;
+    const double f = (1.0 - tt) * (1.0 - uu) * v00 + tt * (1.0 - uu) * v10 + (1.0 - tt) * uu * v01 + tt * uu * v11;
+    return f > 0.0 ? f : 0.0;
+}
+
+__device__ __forceinline__ double tabulated_mixed_of(const TabArgs& t, const f4v* __restrict__ tab32,
+                                                    const double* xs, const double* ys, const double* ds,
+                                                    const int* idx, const Hess32& h)
+{
+    bool finite;
+    const TabQ q = tabulated_query(t, xs, ys, ds, idx, widen(h), finite);
+    f4v c[4];
+    table_load32(t, tab32, q, c);
+    const double F = table_eval32(q, c);
+    return finite ? F : 0.0;
+}
+
+// One particle per lane (FP32 components not 8-byte aligned).
+__global__ void __launch_bounds__(256) k_tabulated_mixed_1(ItemArgs a, TabArgs t, const f4v* __restrict__ tab32,
+                                                          const float* __restrict__ growth32)
+{
+    extern __shared__ double lds[];
+    float* g = reinterpret_cast<float*>(lds);
+    const GrowthIndex gi = stage_growth32(g, growth32, a);
+    double* xs = lds + growth32_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
+    double* ys = xs + t.nx;
+    double* ds = ys + t.ny;
+    const int* idx = stage_table(xs, t);
+    __syncthreads();
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    Hess32 hn{};
+    double fn = 0.0;
+    if (i < n) {
+        hn = load_h32(a, i);
+        fn = a.reset ? 0.0 : *elem(a.Fmax, i);
+    }
+    for (; i < n; i += stride) {
+        const Hess32 h = hn;
+        const double fm = fn;
+        const uint32_t next = i + stride;
+        if (next < n) {
+            hn = load_h32(a, next);
+            fn = a.reset ? 0.0 : *elem(a.Fmax, next);
+        }
+        update_max_f32(a, g, gi, i, tabulated_mixed_of(t, tab32, xs, ys, ds, idx, h), fm);
+    }
+}
+
+// Two adjacent particles per lane (alignment as k_classic_mixed); both cells
+// are located before the eight corner reads are issued.
+__global__ void __launch_bounds__(256) k_tabulated_mixed(ItemArgs a, TabArgs t, const f4v* __restrict__ tab32,
+                                                        const float* __restrict__ growth32)
+{
+    extern __shared__ double lds[];
+    float* g = reinterpret_cast<float*>(lds);
+    const GrowthIndex gi = stage_growth32(g, growth32, a);
+    double* xs = lds + growth32_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
+    double* ys = xs + t.nx;
+    double* ds = ys + t.ny;
+    const int* idx = stage_table(xs, t);
+    __syncthreads();
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t np = n / 2;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    f2v hn[6];
+    d2v fn{0.0, 0.0};
+    auto load = [&](uint32_t q) {
+        for (int c = 0; c < 6; ++c)
+            hn[c] = __builtin_nontemporal_load(
+                reinterpret_cast<const f2v*>(elem(reinterpret_cast<const float*>(a.h[c]), 2 * q)));
+        if (!a.reset)
+            fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * q));
+    };
+    if (p < np)
+        load(p);
+    for (; p < np; p += stride) {
+        f2v h[6];
+        for (int c = 0; c < 6; ++c)
+            h[c] = hn[c];
+        const d2v fm = fn;
+        if (p + stride < np)
+            load(p + stride);
+        bool f0, f1;
+        const TabQ q0 =
+            tabulated_query(t, xs, ys, ds, idx, widen(Hess32{h[0].x, h[1].x, h[2].x, h[3].x, h[4].x, h[5].x}), f0);
+        const TabQ q1 =
+            tabulated_query(t, xs, ys, ds, idx, widen(Hess32{h[0].y, h[1].y, h[2].y, h[3].y, h[4].y, h[5].y}), f1);
+        f4v c0[4], c1[4];
+        table_load32(t, tab32, q0, c0);
+        table_load32(t, tab32, q1, c1);
+        const double F0 = table_eval32(q0, c0);
+        const double F1 = table_eval32(q1, c1);
+        update_pair_f32(a, g, gi, p, f0 ? F0 : 0.0, f1 ? F1 : 0.0, fm);
+    }
+    if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t i = n - 1;
+        const double fm = a.reset ? 0.0 : *elem(a.Fmax, i);
+        update_max_f32(a, g, gi, i, tabulated_mixed_of(t, tab32, xs, ys, ds, idx, load_h32(a, i)), fm);
+    }
+}
+
 
 }  // namespace pino

@@ -9,13 +9,10 @@ namespace {
 
 
 
-inline pino_status launch_mixed(pino_ctx* c, const pino_item& it, const pino::ItemArgs& a, uint32_t, hipStream_t st,
-                                int grid, int block)
+// tab: the Tabulated kernels' view of this radius' table (NULL for Classic)
+inline pino_status launch_mixed(pino_ctx* c, const pino_item& it, const pino::ItemArgs& a, const pino::TabArgs* tab,
+                                hipStream_t st, int grid, int block)
 {
-    if (c->method != PINO_CLASSIC) {
-        c->err = "mixed precision is implemented for the Classic method";
-        return PINO_ERR_UNSUPPORTED;
-    }
     const float* g32 = c->d_growth32 + (size_t)it.cosmo * 3 * c->nk_max;
     const size_t lds = pino::growth32_lds_bytes(a.nk, a.gi.nb);
     // pairs of particles per lane need 8-byte aligned FP32 components,
@@ -24,9 +21,16 @@ inline pino_status launch_mixed(pino_ctx* c, const pino_item& it, const pino::It
     bool paired = al(a.Fmax, 16) && al(a.Rmax, 8) && (!a.acoll || al(a.acoll, 16));
     for (int k = 0; k < 6; ++k)
         paired = paired && al(a.h[k], 8);
-    if (paired) {
-        const int64_t need = (a.n / 2 + block - 1) / block;
-        const int gp = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)c->cu_count * c->blocks_per_cu));
+    const int64_t need = (a.n / 2 + block - 1) / block;
+    const int gp = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)c->cu_count * c->blocks_per_cu));
+    if (tab) {
+        const auto* t32 = static_cast<const pino::f4v*>(c->d_tab32);
+        const size_t lds_t = lds + pino::table_lds_bytes(*tab);
+        if (paired)
+            hipLaunchKernelGGL(pino::k_tabulated_mixed, dim3(gp), dim3(block), lds_t, st, a, *tab, t32, g32);
+        else
+            hipLaunchKernelGGL(pino::k_tabulated_mixed_1, dim3(grid), dim3(block), lds_t, st, a, *tab, t32, g32);
+    } else if (paired) {
         hipLaunchKernelGGL(pino::k_classic_mixed, dim3(gp), dim3(block), lds, st, a, g32);
     } else {
         hipLaunchKernelGGL(pino::k_classic_mixed_1, dim3(grid), dim3(block), lds, st, a, g32);
@@ -34,7 +38,7 @@ inline pino_status launch_mixed(pino_ctx* c, const pino_item& it, const pino::It
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         c->broken = true;
-        c->err = std::string("k_classic_mixed launch: ") + hipGetErrorString(e);
+        c->err = std::string(tab ? "k_tabulated_mixed" : "k_classic_mixed") + " launch: " + hipGetErrorString(e);
         return PINO_ERR_HIP;
     }
     return PINO_OK;

@@ -81,10 +81,6 @@ bool validate_config(const pino_config* cfg, std::string& why)
         why = "certify_rtol must be in [0, 1e-2)";
         return false;
     }
-    if (cfg->precision == PINO_MIXED && cfg->method != PINO_CLASSIC) {
-        why = "mixed precision is implemented for the Classic method";
-        return false;
-    }
     if (cfg->method == PINO_TABULATED) {
         const pino_table_knots* t = cfg->table;
         if (!t || !t->x || !t->y || !t->delta || t->nx < 2 || t->ny < 2 || t->nd < 4) {
@@ -251,7 +247,7 @@ void free_all(pino_ctx* c)
 {
     if (!c)
         return;
-    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tidx, c->d_tab,
+    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tidx, c->d_tab, c->d_tab32,
                     c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_qcount};
     for (void* p : ptrs)
         if (p)
@@ -259,6 +255,7 @@ void free_all(pino_ctx* c)
     c->d_growth = c->d_tknots = c->d_tab = c->d_tmp = nullptr;
     c->d_gidx = nullptr;
     c->d_tidx = nullptr;
+    c->d_tab32 = nullptr;
     c->d_growth32 = nullptr;
     c->d_mlp = nullptr;
     c->d_counters = nullptr;
@@ -327,6 +324,8 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
         }
         const int64_t cells = (int64_t)t->nx * t->ny * t->nd;
         PINO_HIP(c, hipMalloc((void**)&c->d_tab, 2 * cells * sizeof(double)));
+        if (cfg->precision == PINO_MIXED)
+            PINO_HIP(c, hipMalloc(&c->d_tab32, (size_t)t->nx * t->ny * (t->nd - 1) * 4 * sizeof(float)));
         tmp_doubles = std::max<int64_t>(tmp_doubles, 4 * (int64_t)t->nd);  // spline coefficients
     }
     PINO_HIP(c, hipMalloc((void**)&c->d_tmp, tmp_doubles * sizeof(double)));
@@ -427,6 +426,33 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
         hipLaunchKernelGGL(k_table_splines, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, c->d_tmp, c->nd,
                            it.table_F, c->d_tab, rows);
         PINO_HIP(c, hipGetLastError());
+        if (c->precision == PINO_MIXED) {
+            const int64_t pairs = (int64_t)rows * (c->nd - 1);
+            hipLaunchKernelGGL(k_table_pairs_f32, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, c->d_tab,
+                               static_cast<f4v*>(c->d_tab32), rows, c->nd);
+            PINO_HIP(c, hipGetLastError());
+        }
+    }
+
+    // the Tabulated kernels' view of the table of this radius
+    TabArgs t{};
+    if (c->method == PINO_TABULATED) {
+        t.xk = c->d_tknots;
+        t.yk = c->d_tknots + c->nx;
+        t.dk = c->d_tknots + c->nx + c->ny;
+        t.nx = c->nx;
+        t.ny = c->ny;
+        t.nd = c->nd;
+        t.scale = it.sigma_R;
+        t.inv_scale = 1.0 / it.sigma_R;
+        t.tab = c->d_tab;
+        t.bidx = c->d_tidx;
+        t.indexed = c->tindexed;
+        for (int ax = 0; ax < 3; ++ax) {
+            t.nb[ax] = c->tnb[ax];
+            t.k0[ax] = c->tk0[ax];
+            t.bpu[ax] = c->tbpu[ax];
+        }
     }
 
     // the kernels index with 32-bit byte offsets: chunks of at most kChunk
@@ -454,23 +480,6 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
                     hipLaunchKernelGGL(k_classic_f64_1, dim3(g), dim3(block), lds, st, a);
                 }
             } else {
-                TabArgs t;
-                t.xk = c->d_tknots;
-                t.yk = c->d_tknots + c->nx;
-                t.dk = c->d_tknots + c->nx + c->ny;
-                t.nx = c->nx;
-                t.ny = c->ny;
-                t.nd = c->nd;
-                t.scale = it.sigma_R;
-                t.inv_scale = 1.0 / it.sigma_R;
-                t.tab = c->d_tab;
-                t.bidx = c->d_tidx;
-                t.indexed = c->tindexed;
-                for (int ax = 0; ax < 3; ++ax) {
-                    t.nb[ax] = c->tnb[ax];
-                    t.k0[ax] = c->tk0[ax];
-                    t.bpu[ax] = c->tbpu[ax];
-                }
                 const size_t lds_t = lds + table_lds_bytes(t);
                 if (al)
                     hipLaunchKernelGGL(k_tabulated_f64, dim3(gp), dim3(block), lds_t, st, a, t);
@@ -479,7 +488,7 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
             }
             PINO_HIP(c, hipGetLastError());
         } else if (c->precision == PINO_MIXED) {
-            ps = launch_mixed(c, it, a, flags, st, g, block);
+            ps = launch_mixed(c, it, a, c->method == PINO_TABULATED ? &t : nullptr, st, g, block);
         } else {
             ps = launch_surrogate(c, it, a, flags, st, g, block);
         }

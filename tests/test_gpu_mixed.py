@@ -1,6 +1,7 @@
-"""Mixed-precision Classic path (FP32 Hessians and eigenvalues, FP64 root
-polish and nearly-repeated branch, FP32 growth interpolation) against the
-FP64 oracle.
+"""Mixed-precision paths against the FP64 oracle.  Classic: FP32 Hessians
+and eigenvalues, FP64 root polish and nearly-repeated branch, FP32 growth
+interpolation.  Tabulated: FP32 Hessians, FP32 copy of the table (gated by
+the bound its rounding sets), FP64 interpolation arithmetic.
 
 The oracle runs on the same inputs the kernel reads (the FP32 Hessians
 widened to FP64), which isolates the arithmetic error, and on the original
@@ -97,12 +98,114 @@ def test_mixed_special_and_ragged(pkg, orc):
         assert np.array_equal(R, R0)
 
 
-def test_mixed_rejects_tabulated(pkg):
+def _tab32_bound(orc, tables):
+    """Bound on |F_mixed - F_oracle| from rounding the table to FP32: the
+    interpolant is linear in the table values, with weights (1 - t), t and
+    h^2/6 ((1-t)^3 - (1-t)) etc. (|.| <= 0.385 h^2/6) inside convex bilinear
+    weights, so |dF| <= 2^-24 (max|F| + 0.1284 h^2 max|M|) over the cell; the
+    maximum over radii is 1-Lipschitz."""
+    b = 0.0
+    for t in tables:
+        h = np.max(np.diff(t.dk))
+        b = max(b, EPS32 * (np.max(np.abs(t.F)) + 0.1284 * h * h * np.max(np.abs(t.M))))
+    return 1.01 * b
+
+
+def _mixed_tab_run(pkg, orc, knots, slabs32, sigmas, a, D, col_kw=None):
+    """Oracle Tabulated on the FP32 Hessians widened to FP64 (FP64 tables)
+    and the mixed-precision GPU path on the FP32 Hessians."""
+    from tests.test_gpu_tabulated import _filled_table
+    tabs = [_filled_table(orc, knots, s) for s in sigmas]
+    widened = [h.to(torch.float64).numpy() for h in slabs32]
+    g = orc.Growth(a, D)
+    ref = orc.collapse(widened, g, method=orc.TABULATED, tables=tabs)
+    per_r = []
+    for h, t in zip(widened, tabs):
+        n = h.shape[1]
+        F, R, A = np.zeros(n), np.full(n, -1, np.int32), np.full(n, np.inf)
+        orc.update_radius(h, 0, g, F, R, A, reset=True, method=orc.TABULATED, table=t)
+        per_r.append(F)
+    with pkg.Collapse([(a, D)], method=pkg.PINO_TABULATED, precision=pkg.PINO_MIXED, table_knots=knots,
+                      **(col_kw or {})) as col:
+        n = slabs32[0].shape[1]
+        Fm, Rm, ac = col.outputs(n)
+        last = len(slabs32) - 1
+        for r, (h, t, s) in enumerate(zip(slabs32, tabs, sigmas)):
+            tF = torch.from_numpy(np.ascontiguousarray(t.F)).cuda()
+            col.apply(h.cuda().contiguous(), r, Fm, Rm, ac if r == last else None, reset=(r == 0),
+                      finalize=(r == last), sigma_R=s, table_F=tF)
+        torch.cuda.synchronize()
+        got = (Fm.cpu().numpy(), Rm.cpu().numpy(), ac.cpu().numpy())
+    return ref, got, np.stack(per_r), _tab32_bound(orc, tabs)
+
+
+def _check_mixed_tab(ref, got, per_r, b, label):
+    Fr, Rr, Ar = ref
+    F, R, A = got
+    dF = np.abs(F - Fr)
+    print(f"{label}: |dF| max {dF.max():.2e} (bound {b:.2e}), index mismatches {int(np.sum(R != Rr))}", flush=True)
+    assert np.all(dF <= b + 1e-12 * np.abs(Fr)), f"{label}: worst excess {np.max(dF - b):.3e}"
+    # radius index: exact unless the top two radii are within the bound (or F ~ 0)
+    srt = np.sort(per_r, axis=0)
+    second = srt[-2] if srt.shape[0] > 1 else np.zeros_like(srt[-1])
+    close = (np.abs(srt[-1] - second) <= 2 * b) | (np.abs(Fr) <= b)
+    assert np.all((R == Rr) | close)
+    fin = np.isfinite(Ar) & np.isfinite(A)
+    assert np.array_equal(np.isfinite(Ar), np.isfinite(A)) or np.all(np.abs(Fr[np.isfinite(Ar) != np.isfinite(A)]) <= b)
+    big = fin & (Fr > 1e3 * b)
+    ra = np.abs(A[big] - Ar[big]) / Ar[big]
+    tol = b / Fr[big] + 16 * EPS32
+    assert np.all(ra <= tol), f"{label}: a_coll worst excess {np.max(ra - tol):.3e}"
+
+
+def test_mixed_tabulated_c1(pkg, orc):
+    """Mixed-precision Tabulated at C1 (32^3 x 25 radii, 64 x 64 x 128 tables):
+    against the oracle on the same (FP32) inputs, F within the bound set by
+    the FP32 table, radius index exact outside near-ties, a_coll within that
+    bound plus the FP32 spline."""
+    cfg, slabs, a, D = c1_inputs()
+    slabs32 = [h.to(torch.float32) for h in slabs]
+    sigmas = [synth.grid_sigma_gauss(cfg["n_side"], cfg["box"], R) for R in cfg["radii"]]
+    knots = synth.table_knots(1.0, 64, 64, 128)
+    ref, got, per_r, b = _mixed_tab_run(pkg, orc, knots, slabs32, sigmas, a, D)
+    _check_mixed_tab(ref, got, per_r, b, "mixed tabulated C1")
+
+
+def test_mixed_tabulated_special_and_ragged(pkg, orc):
+    from tests.test_gpu_classic import _special_hessians
     a, D = synth.growth_table(0.3)
-    with pytest.raises(pkg.PinoError) as e:
-        pkg.Collapse([(a, D)], precision=pkg.PINO_MIXED, method=pkg.PINO_TABULATED,
-                     table_knots=synth.table_knots())
-    assert e.value.status == pkg.PINO_ERR_ARG
+    rng = np.random.default_rng(4)
+    knots = synth.table_knots(1.0, 16, 12, 40)
+    for h6 in (_special_hessians(), rng.normal(size=(6, 4097)) * 0.7, rng.normal(size=(6, 1)) * 0.7):
+        h32 = torch.from_numpy(h6).to(torch.float32)
+        ref, got, per_r, b = _mixed_tab_run(pkg, orc, knots, [h32], [0.9], a, D)
+        _check_mixed_tab(ref, got, per_r, b, f"mixed tabulated n={h6.shape[1]}")
+
+
+@pytest.mark.parametrize("n", [1, 3, 1001])
+def test_mixed_tabulated_unaligned_matches_aligned(pkg, orc, n):
+    """FP32 components 4- but not 8-byte aligned take the one-particle-per-
+    lane kernel; it equals the paired kernel bit for bit."""
+    from tests.test_gpu_tabulated import _filled_table
+    rng = np.random.default_rng(n + 11)
+    knots = synth.table_knots(1.0, 16, 12, 40)
+    a, D = synth.growth_table(0.3)
+    tF = torch.from_numpy(np.ascontiguousarray(_filled_table(orc, knots, 0.8).F)).cuda()
+    slabs = [torch.from_numpy(rng.normal(size=(6, n)) * 0.8).to(torch.float32).cuda() for _ in range(2)]
+    with pkg.Collapse([(a, D)], method=pkg.PINO_TABULATED, precision=pkg.PINO_MIXED, table_knots=knots) as col:
+        F1, R1, A1 = col.outputs(n)
+        F2, R2, A2 = col.outputs(n)
+        for r, hd in enumerate(slabs):
+            buf = torch.empty((6, n + 1), dtype=torch.float32, device="cuda")
+            buf[:, 1:] = hd
+            hu = [buf[c, 1:] for c in range(6)]
+            assert hu[0].data_ptr() % 8 == 4
+            col.apply(hd, r, F1, R1, A1 if r == 1 else None, reset=(r == 0), finalize=(r == 1), sigma_R=0.8,
+                      table_F=tF)
+            col.apply(hu, r, F2, R2, A2 if r == 1 else None, reset=(r == 0), finalize=(r == 1), sigma_R=0.8,
+                      table_F=tF)
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F2) and torch.equal(R1, R2) and torch.equal(A1, A2)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 64, 1001])
