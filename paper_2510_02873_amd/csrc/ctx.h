@@ -39,6 +39,8 @@ struct pino_ctx {
     double tk0[3] = {0.0, 0.0, 0.0};
     double tbpu[3] = {0.0, 0.0, 0.0};
     double* d_tab = nullptr;
+    // natural-spline elimination coefficients of the dimensionless delta knots
+    double* d_tcoef = nullptr;
     // mixed precision: FP32 knot-pair table (F_j, M_j, F_j+1, M_j+1) per row
     void* d_tab32 = nullptr;
 

@@ -85,8 +85,7 @@ pino_status pino_table_build(int32_t device, int32_t nx, int32_t ny, int32_t nd,
     // the shared elimination coefficients (4 nd doubles) go to work
     hipLaunchKernelGGL(pino::k_spline_coef, dim3(1), dim3(64), 0, st, dk, nd, 1.0, work);
     INTERP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(pino::k_table_splines, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, work, nd, F, tab,
-                       rows);
+    pino::launch_table_splines(work, 1.0, nd, F, tab, rows, st);
     INTERP_HIP(hipGetLastError());
     return PINO_OK;
 }

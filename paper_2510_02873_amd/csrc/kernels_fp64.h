@@ -63,15 +63,39 @@ __global__ void __launch_bounds__(64) k_spline_build(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Table splines (the per-radius rebuild of the Tabulated method): every
 // delta row of the table shares the knots, so the elimination coefficients
-// of the system above are computed once, k_spline_coef, and each row then
-// needs only multiplies and adds, k_table_splines.  For unknown i
-// (1 <= i <= n-2), with h_i = x_{i+1} - x_i and x_k = xk[k] * scale:
+// of the system above are computed once and each row then needs only
+// multiplies and adds.  For unknown i (1 <= i <= n-2), with
+// h_i = x_{i+1} - x_i:
 //   den_i = 2 (h_{i-1} + h_i) - h_{i-1} c_{i-1},  c_i = h_i / den_i (c_0 = 0),
 //   coef[4i .. 4i+3] = {1/h_i, h_{i-1}, 1/den_i, c_i};  coef[0] = 1/h_0.
-// One wave: the lanes scale the knots into LDS (at most kCoefKnots; the
-// host checks n) and fill the independent entries; lane 0 runs the
-// recurrence, whose knot reads come from LDS.
+// Under x -> s x, 1/h and 1/den scale by 1/s, h by s, and c is unchanged, so
+// a context keeps the coefficients of its dimensionless knots and the row
+// kernels apply sigma_R.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline void spline_coef_serial(const double* x, int n, double* coef)
+{
+    double xc = x[1];
+    double hl = xc - x[0];
+    coef[0] = 1.0 / hl;
+    coef[1] = coef[2] = coef[3] = 0.0;
+    double cprev = 0.0;
+    for (int i = 1; i <= n - 2; ++i) {
+        const double xn = x[i + 1];
+        const double hr = xn - xc;
+        const double iden = 1.0 / (2.0 * (hl + hr) - hl * cprev);
+        const double c = hr * iden;
+        coef[4 * i + 0] = 1.0 / hr;
+        coef[4 * i + 1] = hl;
+        coef[4 * i + 2] = iden;
+        coef[4 * i + 3] = c;
+        cprev = c;
+        hl = hr;
+        xc = xn;
+    }
+}
+
+// The coefficients of the knots xk[k] * scale on the device (one wave: the
+// knots are staged in LDS, at most kCoefKnots; lane 0 runs the recurrence).
 constexpr int kCoefKnots = 4096;
 
 __global__ void __launch_bounds__(64) k_spline_coef(const double* __restrict__ xk, int n, double scale,
@@ -83,38 +107,22 @@ __global__ void __launch_bounds__(64) k_spline_coef(const double* __restrict__ x
     for (int k = threadIdx.x; k < n; k += blockDim.x)
         xs[k] = xk[k] * scale;
     __syncthreads();
-    for (int i = threadIdx.x; i <= n - 2; i += blockDim.x) {
-        const double h = xs[i + 1] - xs[i];
-        coef[4 * i] = 1.0 / h;
-        if (i + 1 <= n - 2)
-            coef[4 * (i + 1) + 1] = h;
-    }
-    if (threadIdx.x != 0)
-        return;
-    coef[1] = coef[2] = coef[3] = 0.0;
-    double hl = xs[1] - xs[0];
-    double cprev = 0.0;
-    for (int i = 1; i <= n - 2; ++i) {
-        const double hr = xs[i + 1] - xs[i];
-        const double iden = 1.0 / (2.0 * (hl + hr) - hl * cprev);
-        const double c = hr * iden;
-        coef[4 * i + 2] = iden;
-        coef[4 * i + 3] = c;
-        cprev = c;
-        hl = hr;
-    }
+    if (threadIdx.x == 0)
+        spline_coef_serial(xs, n, coef);
 }
 
 // Row r of F ([rows][n]) into the interleaved table: tab[2 (r n + k)] = F,
-// tab[2 (r n + k) + 1] = M_k.  One row per lane: forward elimination
+// tab[2 (r n + k) + 1] = M_k, knots scaled by s (inv_s = 1/s) from the
+// coefficients above.  One row per lane: forward elimination
 //   d_i = (6 [(y_{i+1} - y_i)/h_i - (y_i - y_{i-1})/h_{i-1}] - h_{i-1} d_{i-1}) / den_i
 // (d_i stored in the M slot), then back substitution M_i = d_i - c_i M_{i+1}.
 // The row's values are read kSplineBatch at a time so their loads overlap;
-// the coefficients are wave-uniform loads.
+// the coefficients are wave-uniform loads.  Used for rows longer than
+// k_table_splines_scan takes.
 constexpr int kSplineBatch = 32;
 
-__global__ void __launch_bounds__(64) k_table_splines(const double* __restrict__ coef, int n,
-                                                     const double* __restrict__ F, double* __restrict__ tab,
+__global__ void __launch_bounds__(64) k_table_splines(const double* __restrict__ coef, double s, double inv_s,
+                                                     int n, const double* __restrict__ F, double* __restrict__ tab,
                                                      int rows)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -126,7 +134,7 @@ __global__ void __launch_bounds__(64) k_table_splines(const double* __restrict__
     double yc = y[1];
     t[0] = y0;
     t[1] = 0.0;
-    double sl = (yc - y0) * coef[0];  // slope of the interval left of unknown i
+    double sl = (yc - y0) * (coef[0] * inv_s);  // slope of the interval left of unknown i
     double dprev = 0.0;
     for (int i0 = 1; i0 <= n - 2; i0 += kSplineBatch) {
         double yn[kSplineBatch];
@@ -138,8 +146,8 @@ __global__ void __launch_bounds__(64) k_table_splines(const double* __restrict__
             const int i = i0 + k;
             if (i <= n - 2) {
                 const double* cf = coef + 4 * i;
-                const double sr = (yn[k] - yc) * cf[0];
-                const double d = (6.0 * (sr - sl) - cf[1] * dprev) * cf[2];
+                const double sr = (yn[k] - yc) * (cf[0] * inv_s);
+                const double d = (6.0 * (sr - sl) - (cf[1] * s) * dprev) * (cf[2] * inv_s);
                 t[2 * i] = yc;
                 t[2 * i + 1] = d;
                 dprev = d;
@@ -166,6 +174,139 @@ __global__ void __launch_bounds__(64) k_table_splines(const double* __restrict__
             }
         }
     }
+}
+
+// The same system with one wave per row (n <= 64 kScanPer): lane L holds the
+// m = ceil(n / 64) consecutive knots i = L m .. L m + m - 1.  Both
+// recurrences are affine, d_i = A_i d_{i-1} + B_i with A_i = -h_{i-1}/den_i,
+// B_i = 6 (slope_i - slope_{i-1})/den_i, and M_i = -c_i M_{i+1} + d_i, so
+// each lane composes its own maps, a wave scan (6 shuffle steps) composes
+// the lanes' maps, and each lane then applies its maps from the value the
+// scan hands it.  |A_i| and |c_i| are below 1 (diagonal dominance), so the
+// composed maps stay bounded; the result differs from the sequential
+// elimination by rounding only.
+constexpr int kScanPer = 8;
+
+// inclusive scan of x -> A x + B over lanes 0..L (up) or L..63 (down);
+// the map of the nearer lanes is applied last
+__device__ __forceinline__ void affine_scan(double& A, double& B, int lane, bool up)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double Ao = up ? __shfl_up(A, off, 64) : __shfl_down(A, off, 64);
+        const double Bo = up ? __shfl_up(B, off, 64) : __shfl_down(B, off, 64);
+        if (up ? lane >= off : lane + off < 64) {
+            B = fma(A, Bo, B);
+            A = A * Ao;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_table_splines_scan(const double* __restrict__ coef, double s, double inv_s,
+                                                           int n, const double* __restrict__ F,
+                                                           double* __restrict__ tab, int rows)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= rows)
+        return;  // the whole wave
+    const int m = (n + 63) >> 6;
+    const int i0 = lane * m;
+    const double* y = F + (int64_t)r * n;
+    double* t = tab + (int64_t)r * n * 2;
+    double yv[kScanPer], A[kScanPer], B[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        yv[k] = (k < m && i0 + k < n) ? y[i0 + k] : 0.0;
+    // slopes of intervals i0 + k, and the slope left of i0 from lane - 1
+    const double ynl = __shfl_down(yv[0], 1, 64);  // first knot of the next lane
+    double sv[kScanPer];
+    double slast = 0.0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int i = i0 + k;
+        double yn = ynl;
+#pragma unroll
+        for (int q = k + 1; q < kScanPer; ++q)
+            yn = q == k + 1 && q < m ? yv[q] : yn;
+        sv[k] = (k < m && i <= n - 2) ? (yn - yv[k]) * (coef[4 * i] * inv_s) : 0.0;
+        slast = k < m ? sv[k] : slast;
+    }
+    const double sprev_lane = __shfl_up(slast, 1, 64);
+    // forward maps, composed over the lane's knots
+    double Al = 1.0, Bl = 0.0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int i = i0 + k;
+        double a = 1.0, b = 0.0;
+        if (k < m && i == 0) {
+            a = 0.0;
+        } else if (k < m && i <= n - 2) {
+            const double iden = coef[4 * i + 2] * inv_s;
+            const double sl = k == 0 ? sprev_lane : sv[k > 0 ? k - 1 : 0];
+            a = -(coef[4 * i + 1] * s) * iden;
+            b = 6.0 * (sv[k] - sl) * iden;
+        }
+        A[k] = a;
+        B[k] = b;
+        Bl = fma(a, Bl, b);
+        Al = a * Al;
+    }
+    affine_scan(Al, Bl, lane, true);
+    double d = __shfl_up(Bl, 1, 64);  // d just before the lane's first knot
+    if (lane == 0)
+        d = 0.0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        d = fma(A[k], d, B[k]);
+        B[k] = d;  // d_i
+    }
+    // backward maps M_i = -c_i M_{i+1} + d_i (0 at i = 0 and i >= n - 1)
+    Al = 1.0;
+    Bl = 0.0;
+#pragma unroll
+    for (int k = kScanPer - 1; k >= 0; --k) {
+        const int i = i0 + k;
+        double a = 1.0, b = 0.0;
+        if (k < m) {
+            if (i >= 1 && i <= n - 2) {
+                a = -coef[4 * i + 3];
+                b = B[k];
+            } else {
+                a = 0.0;
+            }
+        }
+        A[k] = a;
+        B[k] = b;
+        Bl = fma(a, Bl, b);
+        Al = a * Al;
+    }
+    affine_scan(Al, Bl, lane, false);
+    double M = __shfl_down(Bl, 1, 64);  // M just after the lane's last knot
+    if (lane == 63)
+        M = 0.0;
+#pragma unroll
+    for (int k = kScanPer - 1; k >= 0; --k) {
+        M = fma(A[k], M, B[k]);
+        const int i = i0 + k;
+        if (k < m && i < n) {
+            t[2 * i] = yv[k];
+            t[2 * i + 1] = M;
+        }
+    }
+}
+
+// The table splines of `rows` rows of n knots scaled by s (coef as above):
+// one wave per row when the row fits the scan kernel, else one row per lane.
+inline void launch_table_splines(const double* coef, double s, int n, const double* F, double* tab, int rows,
+                                 hipStream_t st)
+{
+    if (n <= 64 * kScanPer)
+        hipLaunchKernelGGL(k_table_splines_scan, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, coef, s,
+                           1.0 / s, n, F, tab, rows);
+    else
+        hipLaunchKernelGGL(k_table_splines, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, coef, s, 1.0 / s,
+                           n, F, tab, rows);
 }
 
 // ---------------------------------------------------------------------------

@@ -87,10 +87,6 @@ bool validate_config(const pino_config* cfg, std::string& why)
             why = "tabulated method needs table knots with nx, ny >= 2 and nd >= 4";
             return false;
         }
-        if (t->nd > kCoefKnots) {
-            why = "table with more than " + std::to_string(kCoefKnots) + " delta knots";
-            return false;
-        }
         if ((int64_t)t->nx * t->ny * t->nd > kMaxTableCells) {
             why = "table larger than 2^24 cells";
             return false;
@@ -247,7 +243,7 @@ void free_all(pino_ctx* c)
 {
     if (!c)
         return;
-    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tidx, c->d_tab, c->d_tab32,
+    void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tidx, c->d_tcoef, c->d_tab, c->d_tab32,
                     c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_qcount};
     for (void* p : ptrs)
         if (p)
@@ -255,6 +251,7 @@ void free_all(pino_ctx* c)
     c->d_growth = c->d_tknots = c->d_tab = c->d_tmp = nullptr;
     c->d_gidx = nullptr;
     c->d_tidx = nullptr;
+    c->d_tcoef = nullptr;
     c->d_tab32 = nullptr;
     c->d_growth32 = nullptr;
     c->d_mlp = nullptr;
@@ -322,11 +319,16 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
             PINO_HIP(c, hipMemcpy(c->d_tidx, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice));
             c->tindexed = 1;
         }
+        // elimination coefficients of the dimensionless delta knots (the row
+        // kernels scale them by sigma_R)
+        std::vector<double> coef(4 * (size_t)t->nd);
+        spline_coef_serial(t->delta, t->nd, coef.data());
+        PINO_HIP(c, hipMalloc((void**)&c->d_tcoef, coef.size() * sizeof(double)));
+        PINO_HIP(c, hipMemcpy(c->d_tcoef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
         const int64_t cells = (int64_t)t->nx * t->ny * t->nd;
         PINO_HIP(c, hipMalloc((void**)&c->d_tab, 2 * cells * sizeof(double)));
         if (cfg->precision == PINO_MIXED)
             PINO_HIP(c, hipMalloc(&c->d_tab32, (size_t)t->nx * t->ny * (t->nd - 1) * 4 * sizeof(float)));
-        tmp_doubles = std::max<int64_t>(tmp_doubles, 4 * (int64_t)t->nd);  // spline coefficients
     }
     PINO_HIP(c, hipMalloc((void**)&c->d_tmp, tmp_doubles * sizeof(double)));
 
@@ -420,11 +422,7 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
         // per-radius table: F into the interleaved table and the delta
         // splines over the sigma-scaled knots, rebuilt on the device
         const int rows = c->nx * c->ny;
-        const double* dks = c->d_tknots + c->nx + c->ny;
-        hipLaunchKernelGGL(k_spline_coef, dim3(1), dim3(64), 0, st, dks, c->nd, it.sigma_R, c->d_tmp);
-        PINO_HIP(c, hipGetLastError());
-        hipLaunchKernelGGL(k_table_splines, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, c->d_tmp, c->nd,
-                           it.table_F, c->d_tab, rows);
+        launch_table_splines(c->d_tcoef, it.sigma_R, c->nd, it.table_F, c->d_tab, rows, st);
         PINO_HIP(c, hipGetLastError());
         if (c->precision == PINO_MIXED) {
             const int64_t pairs = (int64_t)rows * (c->nd - 1);

@@ -138,3 +138,26 @@ def test_ragged_query_counts(A, orc, m):
     pick = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, min(m, 2000))]))
     ref = orc.spline_eval(x, y, orc.spline_natural(x, y), q[pick])
     assert np.max(np.abs(got[pick] - ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("nd", [2, 3, 64, 65, 130, 512, 513, 700])
+def test_table_build_row_lengths(A, orc, nd):
+    """The table's delta splines for row lengths on both sides of the
+    one-wave-per-row scan solver's limit (512 knots; longer rows take the
+    one-row-per-lane solver) and of a lane's share of knots, against the
+    oracle's Thomas solve."""
+    rng = np.random.default_rng(nd)
+    step = 3.0 / (nd - 1)
+    dk = np.linspace(-1.0, 2.0, nd) + np.concatenate([[0.0], rng.uniform(-0.2, 0.2, nd - 2) * step, [0.0]])
+    nx, ny = 3, 5
+    F = rng.normal(size=(nx, ny, nd)) + np.sin(2.0 * dk)
+    Fd = _cuda(F)
+    tab = torch.empty(2 * F.size, dtype=torch.float64, device="cuda")
+    work = torch.empty(F.size, dtype=torch.float64, device="cuda")
+    A.pino_table_build(_cuda(dk), Fd, tab, work)
+    torch.cuda.synchronize()
+    got = tab.cpu().numpy().reshape(nx, ny, nd, 2)
+    assert np.array_equal(got[..., 0], F)
+    M = orc.table_build(dk, F)
+    scale = max(np.max(np.abs(M)), 1e-300)
+    assert np.max(np.abs(got[..., 1] - M)) <= 1e-12 * scale
