@@ -1,11 +1,13 @@
-"""The 512^3 x 40-radius configuration at full size (134M particles, one
+"""Full-size configurations.  The 512^3 x 40-radius configuration (134M particles, one
 GPU's share of a 2048^3 run), FP32 Hessians streamed one radius at a time,
 through the mixed-precision path and through the surrogate + certify path
 on the same fields.  The oracle recomputes a seeded sample of particles over
 all 40 radii, both from the FP64 field (the error the mixed path is quoted
 with) and from the FP32 inputs widened to FP64 (what the kernels read; the
 gates).  Gates: mixed, the per-particle FP32 bound of the mixed tests;
-surrogate, 1e-6 relative on D_c and a_coll after certification."""
+surrogate, 1e-6 relative on D_c and a_coll after certification.  The
+Tabulated workload (256^3 x 25 radii) and the batched 64-realisation one are
+checked the same way, on seeded samples of particles."""
 
 import numpy as np
 import pytest
@@ -95,6 +97,75 @@ def test_512cube_40radii_mixed_and_surrogate(orc, trained_net):
     assert rD.max() <= 1e-6 and ra.max() <= 1e-6
     assert np.array_equal(np.isfinite(gs[2]), fin)
     assert np.all((gs[1] == Rr) | tie)
+
+
+def test_256cube_25radii_tabulated_sampled(orc):
+    """The Tabulated workload at full size (C2T: 256^3 x 25 radii, 64 x 64 x 128
+    tables rebuilt each radius), FP64 and mixed precision on the same fields.
+    The tables are filled by the oracle's Classic solve at their sample
+    points; the oracle then interpolates them for a seeded sample of
+    particles.  Gates: FP64, the plain-path gate (1e-9 relative, index exact
+    outside near-ties); mixed, the FP32-table bound against the oracle on the
+    FP32 inputs widened to FP64."""
+    import paper_2510_02873_amd as P
+    from tests._helpers import compare, near_tie_mask
+    from tests.test_gpu_mixed import _check_mixed_tab, _tab32_bound
+    cfg = synth.config("C2T")
+    n_side, box, radii, cosmo = cfg["n_side"], cfg["box"], cfg["radii"], cfg["cosmo"]
+    n = n_side ** 3
+    a, D = synth.growth_table(cosmo.omega_m, cfg["n_growth"])
+    sig = synth.grid_sigma_gauss(n_side, box, radii, cosmo)
+    knots = synth.table_knots(1.0, *cfg["table"])
+    tabs = []
+    for sR in sig:
+        xk, yk, dk = (np.asarray(k) * sR for k in knots)
+        _, Ft = orc.points(synth.table_grid_hessians(xk, yk, dk))
+        tabs.append(orc.Table(xk, yk, dk, Ft.reshape(len(xk), len(yk), len(dk))))
+    fld = synth.fields.field(n_side, box, cfg["seed"], cosmo, device="cuda")
+    rng = np.random.default_rng(4321)
+    idx = np.concatenate([np.sort(rng.choice(n, size=20000, replace=False)), [0, n - 1]])
+    tidx = torch.from_numpy(idx).cuda()
+    s64, s32 = [], []
+    print(f"256^3 x {len(radii)} Tabulated: n={n}", flush=True)
+    with P.Collapse([(a, D)], method=P.PINO_TABULATED, table_knots=knots) as c64, \
+            P.Collapse([(a, D)], method=P.PINO_TABULATED, precision=P.PINO_MIXED, table_knots=knots) as c32:
+        F1, R1, A1 = c64.outputs(n)
+        F2, R2, A2 = c32.outputs(n)
+        last = len(radii) - 1
+        for r, R in enumerate(radii):
+            tF = torch.from_numpy(np.ascontiguousarray(tabs[r].F)).cuda()
+            h64 = fld.hessian(R)
+            s64.append(h64[:, tidx].cpu().numpy())
+            c64.apply(h64, r, F1, R1, A1 if r == last else None, reset=(r == 0), finalize=(r == last),
+                      sigma_R=sig[r], table_F=tF)
+            h32 = h64.float()
+            del h64
+            s32.append(h32[:, tidx].double().cpu().numpy())
+            c32.apply(h32, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last),
+                      sigma_R=sig[r], table_F=tF)
+            del h32
+            if r % 10 == 9:
+                torch.cuda.synchronize()
+                print(f"  radius {r + 1}/{len(radii)} done", flush=True)
+        torch.cuda.synchronize()
+        g64 = tuple(t[tidx].cpu().numpy() for t in (F1, R1, A1))
+        g32 = tuple(t[tidx].cpu().numpy() for t in (F2, R2, A2))
+    g = orc.Growth(a, D)
+    ref64 = orc.collapse(s64, g, method=orc.TABULATED, tables=tabs)
+    ref32 = orc.collapse(s32, g, method=orc.TABULATED, tables=tabs)
+
+    def per_radius(slabs):
+        out = []
+        for h, t in zip(slabs, tabs):
+            m = h.shape[1]
+            F, R, A = np.zeros(m), np.full(m, -1, np.int32), np.full(m, np.inf)
+            orc.update_radius(h, 0, g, F, R, A, reset=True, method=orc.TABULATED, table=t)
+            out.append(F)
+        return np.stack(out)
+
+    st = compare(ref64, g64, tie_mask=near_tie_mask(per_radius(s64)), label="tabulated 256^3 sample")
+    print("tabulated 256^3 x 25 sample (FP64)", st, flush=True)
+    _check_mixed_tab(ref32, g32, per_radius(s32), _tab32_bound(orc, tabs), "tabulated 256^3 sample (mixed)")
 
 
 def test_c4_batched_full_size_sampled(orc):
