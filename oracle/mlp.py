@@ -4,6 +4,13 @@
 order W1[64][4], b1, W2[64][64], b2, W3[64][64], b3, W4[64], b4; loss the mean
 relative squared error over samples with target w > 0.  Written out layer by
 layer in numpy float64, forward and backward by the chain rule.
+
+bf16=True evaluates the network the way the BF16 matrix-core inference
+does: the weights of the two 64 x 64 layers and their inputs (the ReLU
+outputs of layers 1 and 2) rounded to BF16 (8 significant bits, ties to
+even), everything else unrounded.  Its gradient treats each rounding as the
+identity (straight-through): it is the exact gradient of the same network
+with the rounding offsets frozen at their current values.
 """
 
 from __future__ import annotations
@@ -26,31 +33,43 @@ def unpack(theta):
     return out
 
 
-def forward(theta, x):
+def round_bf16(v):
+    """Nearest value with 8 significant bits (ties to even), from the
+    definition: v = m 2^e with 0.5 <= |m| < 1, round m 2^8 to an integer."""
+    v = np.asarray(v, dtype=np.float64)
+    m, e = np.frexp(v)
+    return np.ldexp(np.rint(m * 256.0) / 256.0, e)
+
+
+def forward(theta, x, bf16=False):
     p = unpack(theta)
+    rnd = round_bf16 if bf16 else (lambda v: v)
     x = np.asarray(x, dtype=np.float64)
     z1 = x @ p["W1"].T + p["b1"]
-    h1 = np.maximum(z1, 0.0)
-    z2 = h1 @ p["W2"].T + p["b2"]
-    h2 = np.maximum(z2, 0.0)
-    z3 = h2 @ p["W3"].T + p["b3"]
+    h1 = rnd(np.maximum(z1, 0.0))
+    z2 = h1 @ rnd(p["W2"]).T + p["b2"]
+    h2 = rnd(np.maximum(z2, 0.0))
+    z3 = h2 @ rnd(p["W3"]).T + p["b3"]
     h3 = np.maximum(z3, 0.0)
     y = h3 @ p["W4"] + p["b4"][0]
     return y, (x, z1, h1, z2, h2, z3, h3)
 
 
-def loss(theta, x, w):
-    y, _ = forward(theta, x)
+def loss(theta, x, w, bf16=False):
+    y, _ = forward(theta, x, bf16)
     w = np.asarray(w, dtype=np.float64)
     use = w > 0
     r = np.where(use, (y - w) / np.where(use, w, 1.0), 0.0)
     return float(np.sum(r * r) / len(w))
 
 
-def grad(theta, x, w):
-    """Gradient of loss() with respect to theta (same layout)."""
+def grad(theta, x, w, bf16=False):
+    """Gradient of loss() with respect to theta (same layout); with bf16, the
+    straight-through gradient described above."""
     p = unpack(theta)
-    y, (x, z1, h1, z2, h2, z3, h3) = forward(theta, x)
+    y, (x, z1, h1, z2, h2, z3, h3) = forward(theta, x, bf16)
+    W2 = round_bf16(p["W2"]) if bf16 else p["W2"]
+    W3 = round_bf16(p["W3"]) if bf16 else p["W3"]
     w = np.asarray(w, dtype=np.float64)
     n = len(w)
     use = w > 0
@@ -60,10 +79,10 @@ def grad(theta, x, w):
     dz3 = np.outer(dy, p["W4"]) * (z3 > 0)
     g["W3"] = dz3.T @ h2
     g["b3"] = dz3.sum(0)
-    dz2 = (dz3 @ p["W3"]) * (z2 > 0)
+    dz2 = (dz3 @ W3) * (z2 > 0)
     g["W2"] = dz2.T @ h1
     g["b2"] = dz2.sum(0)
-    dz1 = (dz2 @ p["W2"]) * (z1 > 0)
+    dz1 = (dz2 @ W2) * (z1 > 0)
     g["W1"] = dz1.T @ x
     g["b1"] = dz1.sum(0)
     return np.concatenate([g[name].ravel() for name, _ in SIZES])
