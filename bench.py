@@ -360,6 +360,7 @@ def measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F
     log(f"surrogate: {n_pairs} training pairs in {time.time() - t0:.1f}s")
     t1 = time.time()
     blob, _, hist = surrogate.train(x, w, steps=train_steps, batch=16384, lr_max=3e-3, seed=7, log_every=10000,
+                                    bf16_forward=True,
                                     log=lambda m: log(m))
     train_s = time.time() - t1
     del x, w
@@ -388,7 +389,7 @@ def measure_surrogate(P, slabs, s32, radii, sig, n, a, D, cfg, n_side, stream, F
            "rel_Dc_vs_fp64_field": {"max": float(rel.max()), "p99.9": float(np.percentile(rel, 99.9)),
                                     "mean": float(rel.mean())},
            "index_mismatch_frac": float((Rs != R64).double().mean().item()),
-           "training": {"pairs": int(n_pairs), "steps": train_steps, "batch": 16384, "seconds": round(train_s, 1),
+           "training": {"pairs": int(n_pairs), "steps": train_steps, "batch": 16384, "bf16_forward": True, "seconds": round(train_s, 1),
                         "final_loss": hist[-1][1] if hist else None}}
     scol.close()
     log(f"surrogate+certify {res['value']:.3e} evals/s, fallback {res['fallback_fraction_of_consulted']:.3f}")

@@ -45,9 +45,18 @@ pino_status pino_mlp_forward(pino_mlp *m, const float *x, float *y, int64_t n, v
  * with w_i > 0 (others ignored, n counts all), its gradient with respect to
  * the parameters (device, PINO_MLP_PARAMS floats, overwritten) and L (device,
  * one float).  Deterministic: per-block partial sums reduced in fixed order.
- * n <= 2^24. */
+ * 0 < n <= 65536. */
 pino_status pino_mlp_grad(pino_mlp *m, const float *x, const float *w, int64_t n, float *grad, float *loss,
                           void *hip_stream);
+
+/* BF16 forward for training (on = 1; off = 0, the default): pino_mlp_grad
+ * then evaluates the network as the collapse kernel's matrix-core inference
+ * does -- the weights of the two 64 x 64 layers and their inputs (the ReLU
+ * outputs of layers 1 and 2) rounded to BF16 (nearest even), FP32
+ * accumulation, layer 1 and the output layer in FP32 -- and back-propagates
+ * through the rounding as if it were the identity (straight-through), into
+ * the FP32 master parameters.  PINO_ERR_ARG for other values of on. */
+pino_status pino_mlp_set_bf16_forward(pino_mlp *m, int32_t on);
 
 /* One Adam step (bias-corrected; step counter kept in the handle) with the
  * given gradient (device). */

@@ -193,6 +193,7 @@ def _bind_mlp():
     L.pino_mlp_forward.argtypes = [c_p, c_p, c_p, c_i64, c_p]
     L.pino_mlp_grad.argtypes = [c_p, c_p, c_p, c_i64, c_p, c_p, c_p]
     L.pino_mlp_adam.argtypes = [c_p, c_p, c_f, c_f, c_f, c_f, c_p]
+    L.pino_mlp_set_bf16_forward.argtypes = [c_p, ctypes.c_int32]
     L.pino_mlp_train_step.argtypes = [c_p, c_p, c_p, c_i64, c_f, c_p, c_p]
     L.pino_mlp_export.argtypes = [c_p, c_p, c_i64, ctypes.POINTER(c_i64)]
     L.pino_mlp_free.argtypes = [c_p]
@@ -201,7 +202,8 @@ def _bind_mlp():
     L.pino_collapse_surrogate_stats.argtypes = [c_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
                                                 ctypes.POINTER(c_i64), ctypes.c_int32]
     for name in ("pino_mlp_create", "pino_mlp_set_params", "pino_mlp_get_params", "pino_mlp_forward",
-                 "pino_mlp_grad", "pino_mlp_adam", "pino_mlp_train_step", "pino_mlp_export", "pino_mlp_free",
+                 "pino_mlp_grad", "pino_mlp_adam", "pino_mlp_set_bf16_forward", "pino_mlp_train_step",
+                 "pino_mlp_export", "pino_mlp_free",
                  "pino_collapse_features", "pino_collapse_predict", "pino_collapse_surrogate_stats"):
         getattr(L, name).restype = ctypes.c_int
     _mlp_bound = True
@@ -246,6 +248,10 @@ def pino_mlp_grad(m, x, w, grad, loss=None, stream=None):
 
 def pino_mlp_adam(m, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(_bind_mlp().pino_mlp_adam(m, _ptr(grad), lr, beta1, beta2, eps, _stream(stream)))
+
+
+def pino_mlp_set_bf16_forward(m, on):
+    _check(_bind_mlp().pino_mlp_set_bf16_forward(m, int(on)))
 
 
 def pino_mlp_train_step(m, x, w, lr, loss=None, stream=None):

@@ -22,6 +22,8 @@ struct pino_mlp {
     float* d_grad = nullptr;
     float* d_partial = nullptr;
     float* d_partial2 = nullptr;  // per-group sums of the partials
+    float* d_pq = nullptr;        // BF16-rounded parameters (BF16 forward)
+    int bf16_fwd = 0;
     int64_t step = 0;
     bool broken = false;
     std::string err = "no error";
@@ -254,6 +256,7 @@ pino_status pino_mlp_create(int32_t device, uint64_t seed, pino_mlp** out)
     if (st == PINO_OK &&
         (e = hipMalloc(&m->d_partial2, (size_t)kReduceGroups * (kNParam + 1) * sizeof(float))) != hipSuccess)
         fail(e, "hipMalloc");
+    if (st == PINO_OK && (e = hipMalloc(&m->d_pq, kNParam * sizeof(float))) != hipSuccess) fail(e, "hipMalloc");
     if (st == PINO_OK && (e = hipMemcpy(m->d_params, P.data(), kNParam * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
         fail(e, "hipMemcpy");
     if (st == PINO_OK && (e = hipMemset(m->d_m1, 0, kNParam * sizeof(float))) != hipSuccess) fail(e, "hipMemset");
@@ -322,8 +325,13 @@ pino_status pino_mlp_grad(pino_mlp* m, const float* x, const float* w, int64_t n
     MLP_HIP(m, hipSetDevice(m->device));
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const int nblk = (int)((n + pino::kTB - 1) / pino::kTB);
+    if (m->bf16_fwd) {
+        hipLaunchKernelGGL(pino::k_mlp_round_bf16, dim3((pino::kNParam + 255) / 256), dim3(256), 0, st, m->d_params,
+                           m->d_pq);
+        MLP_HIP(m, hipGetLastError());
+    }
     hipLaunchKernelGGL(pino::k_mlp_grad_block, dim3(nblk), dim3(pino::kGradThreads), pino::mlp_grad_lds_bytes(), st,
-                       m->d_params, x, w, n, m->d_partial);
+                       m->d_params, m->bf16_fwd ? m->d_pq : m->d_params, m->bf16_fwd, x, w, n, m->d_partial);
     MLP_HIP(m, hipGetLastError());
     const unsigned cols = (unsigned)((pino::kNParam + 1 + 255) / 256);
     hipLaunchKernelGGL(pino::k_mlp_reduce_groups, dim3(cols, pino::kReduceGroups), dim3(256), 0, st, m->d_partial,
@@ -331,6 +339,14 @@ pino_status pino_mlp_grad(pino_mlp* m, const float* x, const float* w, int64_t n
     MLP_HIP(m, hipGetLastError());
     hipLaunchKernelGGL(pino::k_mlp_reduce, dim3(cols), dim3(256), 0, st, m->d_partial2, n, grad, loss);
     MLP_HIP(m, hipGetLastError());
+    return PINO_OK;
+}
+
+pino_status pino_mlp_set_bf16_forward(pino_mlp* m, int32_t on)
+{
+    if (!m || (on != 0 && on != 1))
+        return PINO_ERR_ARG;
+    m->bf16_fwd = on;
     return PINO_OK;
 }
 
@@ -391,7 +407,7 @@ pino_status pino_mlp_free(pino_mlp* m)
         return PINO_OK;
     (void)hipSetDevice(m->device);
     (void)hipDeviceSynchronize();
-    float* ptrs[] = {m->d_params, m->d_m1, m->d_m2, m->d_grad, m->d_partial, m->d_partial2};
+    float* ptrs[] = {m->d_params, m->d_m1, m->d_m2, m->d_grad, m->d_partial, m->d_partial2, m->d_pq};
     for (float* p : ptrs)
         if (p)
             (void)hipFree(p);

@@ -23,6 +23,19 @@ constexpr int kOffW4 = kOffB3 + kH;
 constexpr int kOffB4 = kOffW4 + kH;
 constexpr int kNParam = kOffB4 + 1;  // 8705
 
+// FP32 -> BF16 bits, round to nearest even (finite inputs)
+__host__ __device__ __forceinline__ short bf16_bits(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__host__ __device__ __forceinline__ float bf16_value(short b)
+{
+    return __builtin_bit_cast(float, (uint32_t)(uint16_t)b << 16);
+}
+
 // the network is consulted only where l1 >= kGate * max|l| (and l1 > 0)
 constexpr double kGate = 0.1;
 
@@ -99,7 +112,13 @@ __device__ __forceinline__ void dense_cols(const float* __restrict__ W, int u0, 
     }
 }
 
+// pq: the parameters whose W2 and W3 the hidden layers use (the BF16-rounded
+// copy when bf16, else p itself); bf16 also rounds those layers' inputs (the
+// ReLU outputs of layers 1 and 2) to BF16, as the matrix-core inference
+// does.  The backward pass uses the same weights and stored activations and
+// treats the rounding as the identity (straight-through).
 __global__ void __launch_bounds__(kGradThreads) k_mlp_grad_block(const float* __restrict__ p,
+                                                                const float* __restrict__ pq, int bf16,
                                                                 const float* __restrict__ X,
                                                                 const float* __restrict__ Wt, int64_t n,
                                                                 float* __restrict__ partial)
@@ -127,15 +146,19 @@ __global__ void __launch_bounds__(kGradThreads) k_mlp_grad_block(const float* __
     // forward
     dense_rows<kIn>(p + kOffW1, p + kOffB1, u0, xs, s, z);
 #pragma unroll
-    for (int u = 0; u < kUw; ++u)
-        h1[(u0 + u) * kLd + s] = fmaxf(z[u], 0.0f);
+    for (int u = 0; u < kUw; ++u) {
+        const float hv = fmaxf(z[u], 0.0f);
+        h1[(u0 + u) * kLd + s] = bf16 ? bf16_value(bf16_bits(hv)) : hv;
+    }
     __syncthreads();
-    dense_rows<kH>(p + kOffW2, p + kOffB2, u0, h1, s, z);
+    dense_rows<kH>(pq + kOffW2, p + kOffB2, u0, h1, s, z);
 #pragma unroll
-    for (int u = 0; u < kUw; ++u)
-        h2[(u0 + u) * kLd + s] = fmaxf(z[u], 0.0f);
+    for (int u = 0; u < kUw; ++u) {
+        const float hv = fmaxf(z[u], 0.0f);
+        h2[(u0 + u) * kLd + s] = bf16 ? bf16_value(bf16_bits(hv)) : hv;
+    }
     __syncthreads();
-    dense_rows<kH>(p + kOffW3, p + kOffB3, u0, h2, s, z);
+    dense_rows<kH>(pq + kOffW3, p + kOffB3, u0, h2, s, z);
     float yp = 0.0f;  // this wave's share of the output
 #pragma unroll
     for (int u = 0; u < kUw; ++u) {
@@ -163,12 +186,12 @@ __global__ void __launch_bounds__(kGradThreads) k_mlp_grad_block(const float* __
     for (int u = 0; u < kUw; ++u)
         d3[(u0 + u) * kLd + s] = h3[(u0 + u) * kLd + s] > 0.0f ? dy * p[kOffW4 + u0 + u] : 0.0f;
     __syncthreads();
-    dense_cols(p + kOffW3, u0, d3, s, z);
+    dense_cols(pq + kOffW3, u0, d3, s, z);
 #pragma unroll
     for (int u = 0; u < kUw; ++u)
         d2[(u0 + u) * kLd + s] = h2[(u0 + u) * kLd + s] > 0.0f ? z[u] : 0.0f;
     __syncthreads();
-    dense_cols(p + kOffW2, u0, d2, s, z);
+    dense_cols(pq + kOffW2, u0, d2, s, z);
 #pragma unroll
     for (int u = 0; u < kUw; ++u)
         d1[(u0 + u) * kLd + s] = h1[(u0 + u) * kLd + s] > 0.0f ? z[u] : 0.0f;
@@ -270,6 +293,14 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ pa
         *loss = s / (float)n;
 }
 
+// q[j] = P[j] rounded to BF16 (nearest even), as FP32
+__global__ void __launch_bounds__(256) k_mlp_round_bf16(const float* __restrict__ P, float* __restrict__ q)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < kNParam)
+        q[j] = bf16_value(bf16_bits(P[j]));
+}
+
 __global__ void __launch_bounds__(256) k_mlp_adam(float* __restrict__ P, float* __restrict__ m1,
                                                  float* __restrict__ m2, const float* __restrict__ g, float lr,
                                                  float b1, float b2, float eps, float c1, float c2)
@@ -355,18 +386,6 @@ __host__ __device__ __forceinline__ int k32_neuron(int kt, int g, int j)
     return 32 * kt + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
 }
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs; host side)
-__host__ __device__ __forceinline__ short bf16_bits(float f)
-{
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
-__host__ __device__ __forceinline__ float bf16_value(short b)
-{
-    return __builtin_bit_cast(float, (uint32_t)(uint16_t)b << 16);
-}
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));

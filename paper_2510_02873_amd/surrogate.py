@@ -51,9 +51,14 @@ def training_pairs(fields, growth_tables, device=0, per_slab=None, stream=None):
     return torch.cat(xs), torch.cat(ws)
 
 
-def train(x, w, steps=8000, batch=8192, lr_max=3e-3, seed=0, device=0, log_every=0, log=print):
-    """One-cycle Adam training; returns (blob, params, history)."""
+def train(x, w, steps=8000, batch=8192, lr_max=3e-3, seed=0, device=0, log_every=0, log=print,
+          bf16_forward=False):
+    """One-cycle Adam training; returns (blob, params, history).  With
+    bf16_forward the forward pass rounds as the BF16 inference does
+    (pino_mlp_set_bf16_forward)."""
     m = _abi.pino_mlp_create(device, seed)
+    if bf16_forward:
+        _abi.pino_mlp_set_bf16_forward(m, True)
     loss = torch.zeros(1, dtype=torch.float32, device=x.device)
     gen = torch.Generator(device=x.device).manual_seed(seed)
     hist = []

@@ -61,6 +61,47 @@ def test_mlp_grad_and_forward_vs_fp64(P):
     assert abs(float(loss.item()) - omlp.loss(th.astype(np.float64), x, w)) < 1e-4 * omlp.loss(th.astype(np.float64), x, w)
 
 
+def test_mlp_grad_bf16_forward_vs_oracle(P):
+    """BF16 forward for training: the gradient matches the oracle's
+    straight-through gradient of the BF16-rounded network (the GPU rounds its
+    FP32 activations, the oracle its FP64 ones, so a value at a rounding tie
+    can land one BF16 step apart: 2-norm gate 2e-3); switching it off gives
+    the FP32 gradient again, bit for bit; other switch values are rejected."""
+    _, A = P
+    rng = np.random.default_rng(13)
+    n = 3000
+    x = rng.normal(size=(n, 4)).astype(np.float32)
+    w = rng.uniform(0.5, 2.0, size=n).astype(np.float32)
+    w[::13] = 0.0
+    th = _theta(17)
+    m = A.pino_mlp_create(0, 0)
+    try:
+        A.pino_mlp_set_params(m, th)
+        xd, wd = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+        g32 = torch.empty(A.PINO_MLP_PARAMS, dtype=torch.float32, device="cuda")
+        g16 = torch.empty_like(g32)
+        g32b = torch.empty_like(g32)
+        A.pino_mlp_grad(m, xd, wd, g32)
+        A.pino_mlp_set_bf16_forward(m, True)
+        A.pino_mlp_grad(m, xd, wd, g16)
+        A.pino_mlp_set_bf16_forward(m, False)
+        A.pino_mlp_grad(m, xd, wd, g32b)
+        torch.cuda.synchronize()
+        with pytest.raises(A.PinoError):
+            A.pino_mlp_set_bf16_forward(m, 2)
+    finally:
+        A.pino_mlp_free(m)
+    assert torch.equal(g32, g32b)
+    th64 = th.astype(np.float32).astype(np.float64)
+    ref = omlp.grad(th64, x, w, bf16=True)
+    gg = g16.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(gg - ref) / np.linalg.norm(ref)
+    rel_fp32 = np.linalg.norm(g32.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"bf16-forward grad rel err (2-norm) {rel:.2e}; the FP32 gradient is {rel_fp32:.2e} away", flush=True)
+    assert rel < 2e-3
+    assert rel_fp32 > 10 * rel
+
+
 def test_adam_step_matches_formula(P):
     _, A = P
     th = _theta(3)
