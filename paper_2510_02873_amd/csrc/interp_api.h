@@ -30,6 +30,11 @@ pino_status interp_hip(hipError_t e, const char* what)
     } while (0)
 
 // enough workgroups to fill the device, no more than the queries need
+// bins per knot interval of the spline's per-block interval index: random
+// knots (the Sec. 4.3 benchmark) cluster, and at 8 bins per interval more
+// than three knots rarely follow inside one bin
+constexpr int kInterpBins = 8;
+
 pino_status interp_grid(int32_t device, int64_t m, unsigned& grid)
 {
     int cus = 0;
@@ -67,8 +72,13 @@ pino_status pino_spline_eval(int32_t device, const double* x, const double* y, c
     const pino_status st = interp_grid(device, m, grid);
     if (st != PINO_OK)
         return st;
-    hipLaunchKernelGGL(pino::k_spline_eval, dim3(grid), dim3(256), (size_t)3 * n * sizeof(double),
-                       static_cast<hipStream_t>(hip_stream), x, y, M, n, q, out, m);
+    // an interval index when each thread has at least 32 queries to amortise
+    // the block's build and its bins fit beside the knots in 64 KiB of LDS
+    const int64_t bins_fit = (65536 - 24 * (int64_t)n) / (int64_t)sizeof(int);
+    const int nb = m >= (int64_t)grid * 256 * 32 ? (int)std::min<int64_t>(kInterpBins * (int64_t)(n - 1), bins_fit) : 0;
+    hipLaunchKernelGGL(pino::k_spline_eval, dim3(grid), dim3(256),
+                       (size_t)3 * n * sizeof(double) + (size_t)std::max(nb, 0) * sizeof(int),
+                       static_cast<hipStream_t>(hip_stream), x, y, M, n, std::max(nb, 0), q, out, m);
     INTERP_HIP(hipGetLastError());
     return PINO_OK;
 }
@@ -116,7 +126,8 @@ pino_status pino_table_eval(int32_t device, const double* xk, int32_t nx, const 
     t.inv_scale = 1.0;
     t.tab = tab;
     t.indexed = 0;
-    hipLaunchKernelGGL(pino::k_table_eval, dim3(grid), dim3(256), pino::table_lds_bytes(t),
+    const size_t lds = pino::table_lds_bytes(t);
+    hipLaunchKernelGGL(pino::k_table_eval, dim3(grid), dim3(256), lds,
                        static_cast<hipStream_t>(hip_stream), t, qx, qy, qd, out, m);
     INTERP_HIP(hipGetLastError());
     return PINO_OK;

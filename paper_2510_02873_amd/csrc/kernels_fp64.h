@@ -550,9 +550,9 @@ k_classic_f64(ItemArgs a)
 //
 // Interval index (per axis, optional): nb uniform bins over the dimensionless
 // knot range; bin b holds the interval `locate` returns at the bin's low end
-// less a margin of 1 % of a bin, and the host has verified that at most two
-// more knots lie below the bin's high end plus the margin, so two compares
-// (whose knot reads are independent) finish the search.  The margin is far
+// less a margin of 1 % of a bin, and the host has verified that at most
+// kIndexCompares more knots lie below the bin's high end plus the margin, so
+// that many compares (whose knot reads are independent) finish the search.  The margin is far
 // above the rounding of the bin arithmetic, and the interval found is the one
 // `locate` finds.  Without the index (indexed = 0) the binary search is used.
 // ---------------------------------------------------------------------------
@@ -573,6 +573,28 @@ struct TabArgs {
 
 // Interval of the scaled knots xs (n) containing q: `locate`, through the
 // axis index when there is one.
+// Finish an interval search from interval i: up to K more knots, read
+// independently of each other.  The Tabulated kernels' table index allows
+// kIndexCompares (smooth knots, checked by the host); the stand-alone
+// spline's per-block index allows one more (random knots cluster).
+constexpr int kIndexCompares = 2;
+
+template <int K = kIndexCompares>
+__host__ __device__ __forceinline__ int locate_after(const double* xs, int n, double q, int i)
+{
+    double xv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        xv[k] = xs[min(i + 1 + k, n - 1)];
+    int r = i, c = 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        c = c & ((i + 1 + k <= n - 2 && xv[k] <= q) ? 1 : 0);
+        r += c;
+    }
+    return r;
+}
+
 __host__ __device__ __forceinline__ int table_locate(const TabArgs& t, int axis, const int* idx, const double* xs, int n,
                                             double q)
 {
@@ -580,12 +602,29 @@ __host__ __device__ __forceinline__ int table_locate(const TabArgs& t, int axis,
         return locate(xs, n, q);
     double fb = (q * t.inv_scale - t.k0[axis]) * t.bpu[axis];
     fb = fmin(fmax(fb, 0.0), (double)(t.nb[axis] - 1));
-    const int i = idx[(int)fb];
-    const double x1 = xs[min(i + 1, n - 1)];
-    const double x2 = xs[min(i + 2, n - 1)];
-    const int c1 = (i + 1 <= n - 2 && x1 <= q) ? 1 : 0;
-    const int c2 = (c1 && i + 2 <= n - 2 && x2 <= q) ? 1 : 0;
-    return i + c1 + c2;
+    return locate_after(xs, n, q, idx[(int)fb]);
+}
+
+// The interval index of knots xs[0..n-1] (LDS), built by the whole block:
+// nb uniform bins over [xs[0], xs[n-1]], bin b holding the interval at its
+// low end less a margin of 1 % of a bin.  Returns, the same on every thread,
+// whether at most K more knots follow inside any bin (margins included) and
+// the margin is far above the rounding of the bin arithmetic; bpu receives
+// the bins per unit.  All threads of the block must call it.
+template <int K>
+__device__ __forceinline__ bool build_axis_index(const double* xs, int n, int nb, int* idx, double& bpu)
+{
+    const double lo = xs[0], hi = xs[n - 1];
+    const double w = (hi - lo) / nb;
+    bpu = 1.0 / w;
+    bool ok = w > 0.0 && isfinite(bpu) && 0.01 * w >= 1e-12 * fmax(fabs(lo), fabs(hi));
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int i0 = locate(xs, n, lo + (b - 0.01) * w);
+        const int i1 = locate(xs, n, lo + (b + 1.01) * w);
+        idx[b] = i0;
+        ok = ok && i1 - i0 <= K;
+    }
+    return __syncthreads_and(ok) != 0;
 }
 
 // A table query resolved to its cell: the double2 offset of corner (ix, iy)
@@ -616,10 +655,13 @@ __device__ __forceinline__ TabQ table_query(const TabArgs& t, const double* xs, 
 }
 
 // The 4 corners x 2 knots of a query's cell: c[2 * corner + {0, 1}], corners
-// (ix, iy), (ix, iy + 1), (ix + 1, iy), (ix + 1, iy + 1).
-__device__ __forceinline__ void table_load(const TabArgs& t, const TabQ& q, double2 (&c)[8])
+// (ix, iy), (ix, iy + 1), (ix + 1, iy), (ix + 1, iy + 1).  (The table is
+// passed as its own restrict-qualified pointer so that its reads are known
+// not to alias the kernels' stores.)
+__device__ __forceinline__ void table_load_from(const double* __restrict__ tab, const TabArgs& t, const TabQ& q,
+                                               double2 (&c)[8])
 {
-    const double2* p = reinterpret_cast<const double2*>(t.tab) + q.r;
+    const double2* p = reinterpret_cast<const double2*>(tab) + q.r;
     const uint32_t sy = (uint32_t)t.nd;
     const uint32_t sx = (uint32_t)t.ny * sy;
     c[0] = p[0];
@@ -630,6 +672,11 @@ __device__ __forceinline__ void table_load(const TabArgs& t, const TabQ& q, doub
     c[5] = p[sx + 1];
     c[6] = p[sx + sy];
     c[7] = p[sx + sy + 1];
+}
+
+__device__ __forceinline__ void table_load(const TabArgs& t, const TabQ& q, double2 (&c)[8])
+{
+    table_load_from(t.tab, t, q, c);
 }
 
 // Splines in delta at the four corners, then bilinear; clamped to >= 0.
@@ -645,14 +692,31 @@ __device__ __forceinline__ double table_eval(const TabQ& q, const double2 (&c)[8
 }
 
 // The table at (x, y, delta): splines in delta at the four corners of the
-// (x, y) cell, then bilinear; knots xs, ys, ds and the index in LDS.
+// (x, y) cell, then bilinear; knots xs, ys, ds and the index in LDS.  The
+// same arithmetic as table_load + table_eval, but each corner is read and
+// evaluated in turn: a kernel with one query per lane keeps half the
+// registers live (42 against 84 VGPRs) and runs at higher occupancy.
+__device__ __forceinline__ double table_corner(const double* __restrict__ tab, uint32_t o, const TabQ& q)
+{
+    const double2* p = reinterpret_cast<const double2*>(tab) + o;
+    const double2 lo = p[0];
+    const double2 hi = p[1];
+    return spline_piece(q.d0, q.d1, lo.x, hi.x, lo.y, hi.y, q.dq);
+}
+
 __device__ __forceinline__ double table_at(const TabArgs& t, const double* xs, const double* ys, const double* ds,
                                            const int* idx, double x, double y, double delta)
 {
     const TabQ q = table_query(t, xs, ys, ds, idx, x, y, delta);
-    double2 c[8];
-    table_load(t, q, c);
-    return table_eval(q, c);
+    const uint32_t sy = (uint32_t)t.nd;
+    const uint32_t sx = (uint32_t)t.ny * sy;
+    const double v00 = table_corner(t.tab, q.r, q);
+    const double v01 = table_corner(t.tab, q.r + sy, q);
+    const double v10 = table_corner(t.tab, q.r + sx, q);
+    const double v11 = table_corner(t.tab, q.r + sx + sy, q);
+    const double tt = q.tt, uu = q.uu;
+    const double f = (1.0 - tt) * (1.0 - uu) * v00 + tt * (1.0 - uu) * v10 + (1.0 - tt) * uu * v01 + tt * uu * v11;
+    return f > 0.0 ? f : 0.0;
 }
 
 // Stage the scaled knots and the interval index at `base` (LDS); returns the

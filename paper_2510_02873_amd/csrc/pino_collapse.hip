@@ -204,9 +204,9 @@ bool lds_fits(const pino_config* cfg, std::string& why)
 
 // Interval index of one axis of dimensionless table knots k[n] (TabArgs):
 // 4 (n - 1) uniform bins, each holding the interval at its low end less a
-// margin of 1 % of a bin; false if more than two knots can follow inside a
-// bin (the kernels then use the binary search) or if the margin is not far
-// above the rounding of the bin arithmetic.
+// margin of 1 % of a bin; false if more than kIndexCompares knots can follow
+// inside a bin (the kernels then use the binary search) or if the margin is
+// not far above the rounding of the bin arithmetic.
 bool table_axis_index(const double* k, int n, std::vector<int>& idx, int& nb, double& k0, double& bpu)
 {
     nb = 4 * (n - 1);
@@ -220,7 +220,7 @@ bool table_axis_index(const double* k, int n, std::vector<int>& idx, int& nb, do
     for (int b = 0; b < nb; ++b) {
         const int i0 = locate(k, n, lo + b * w - margin);
         const int i1 = locate(k, n, lo + (b + 1) * w + margin);
-        if (i1 - i0 > 2)
+        if (i1 - i0 > kIndexCompares)
             return false;
         idx.push_back(i0);
     }

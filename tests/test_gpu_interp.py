@@ -161,3 +161,48 @@ def test_table_build_row_lengths(A, orc, nd):
     M = orc.table_build(dk, F)
     scale = max(np.max(np.abs(M)), 1e-300)
     assert np.max(np.abs(got[..., 1] - M)) <= 1e-12 * scale
+
+
+def _index_holds(k, compares=3, per_interval=8):
+    """The kernels' test for their interval index over knots k: 8 (n - 1)
+    uniform bins, 1 % margins, at most `compares` knots beyond a bin's
+    first interval."""
+    nb = per_interval * (len(k) - 1)
+    w = (k[-1] - k[0]) / nb
+    b = np.arange(nb)
+    lo = np.clip(np.searchsorted(k, k[0] + (b - 0.01) * w, side="right") - 1, 0, len(k) - 2)
+    hi = np.clip(np.searchsorted(k, k[0] + (b + 1.01) * w, side="right") - 1, 0, len(k) - 2)
+    return bool(np.max(hi - lo) <= compares)
+
+
+def test_indexed_search_at_large_query_counts(A, orc):
+    """At 2^24 + 3 queries each block of the spline evaluator builds an
+    interval index (8 bins per knot interval over 512 random knots) and takes
+    each query's interval from its bin; sampled outputs, including queries on
+    the knots, next to them, at bin edges and outside the range, match the
+    oracle.  The table evaluator (binary search) is checked at the same
+    count."""
+    rng = np.random.default_rng(31)
+    m = (1 << 24) + 3
+    x = _knots(rng, 512)
+    y = np.cos(5 * x) + x * x
+    q = rng.uniform(-0.1, 1.1, m)
+    q[:512] = x
+    q[512:1024] = np.nextafter(x, -np.inf)
+    q[1024:3072] = x[0] + (x[-1] - x[0]) * np.arange(2048) / 2044.0
+    _, got = _spline_gpu(A, x, y, q)
+    pick = np.unique(np.concatenate([np.arange(3072), rng.integers(0, m, 20000), [m - 1]]))
+    ref = orc.spline_eval(x, y, orc.spline_natural(x, y), q[pick])
+    assert np.max(np.abs(got[pick] - ref)) <= 1e-12 * np.max(np.abs(ref))
+    xk, yk, dk = _knots(rng, 64), _knots(rng, 64), _knots(rng, 128, -1.0, 2.0)
+    X, Y, Dd = np.meshgrid(xk, yk, dk, indexing="ij")
+    F = X ** 2 + Y ** 2 + 0.3 * Dd ** 2 + 0.1 * np.sin(3 * Dd)
+    qx, qy, qd = rng.uniform(-0.1, 1.1, m), rng.uniform(-0.1, 1.1, m), rng.uniform(-1.2, 2.2, m)
+    qx[:64], qy[64:128], qd[128:256] = xk, yk, dk
+    tab, gt = _table_gpu(A, xk, yk, dk, F, qx, qy, qd)
+    pick = np.unique(np.concatenate([np.arange(256), rng.integers(0, m, 5000), [m - 1]]))
+    ref = _oracle_table(orc, xk, yk, dk, F, orc.table_build(dk, F), qx[pick], qy[pick], qd[pick])
+    assert np.max(np.abs(gt[pick] - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # precondition: the spline's knots admit the index (at most 3 knots
+    # beyond a bin's first interval), so the binned path is the one exercised
+    assert _index_holds(x)
