@@ -53,9 +53,8 @@ struct pino_ctx {
     double certify_rtol = 5e-7;
     int64_t* d_counters = nullptr;
     // surrogate: queue of deferred particle indices (chunk-relative), one
-    // segment per block, and the segments' lengths
+    // segment per block
     int32_t* d_queue = nullptr;
-    int32_t* d_qcount = nullptr;
     int64_t queue_cap = 0;
     std::vector<double> omega;
 

@@ -15,20 +15,22 @@ __device__ __forceinline__ Hess64 load_h(const ItemArgs& a, uint32_t i, bool f32
 
 // Per particle: FP64 eigenvalues of the FP32 Hessian, the BF16 network's
 // prediction and the FP64 certificate.  Certified and gated particles (F from
-// the certificate, or 0) update the maxima here.  The others are deferred:
-// each block appends their indices to its own segment of `queue`
+// the certificate, or 0) update the maxima in the main loop.  The others are
+// deferred: each block appends their indices to its own segment of `queue`
 // (queue + blockIdx.x * seg, seg >= the particles a block visits) through an
-// LDS counter, one LDS atomic per wave, and stores the segment's length in
-// qcount[blockIdx.x]; their maxima are carried over unchanged, for
-// k_surrogate_fallback to finish with the full solve.  The loop is
+// LDS counter, one LDS atomic per wave, and carries their maxima over
+// unchanged.  After its loop the block finishes its own deferred particles
+// with the full FP64 Classic solve on the same widened FP32 Hessian and
+// updates their maxima against what the loop stored (at FINALIZE their
+// a(D_c) is rewritten where F wins), so the full solve costs only the
+// particles that need it, with no second launch.  The main loop is
 // wave-uniform (all 64 lanes run the network together); lanes past the end
 // compute on zeros and store nothing.  counters: certified, consulted but not
 // certified, not consulted (wave totals added once per wave at the end).
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_surrogate(ItemArgs a, const NetFrags* __restrict__ net, double sigma,
                                                   double omega_m, double rtol,
                                                   unsigned long long* __restrict__ counters,
-                                                  int32_t* __restrict__ queue, int32_t* __restrict__ qcount,
-                                                  int64_t seg)
+                                                  int32_t* __restrict__ queue, int64_t seg)
 {
     extern __shared__ double lds[];
     __shared__ int fill;
@@ -96,26 +98,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         atomicAdd(counters + 1, nfall);
         atomicAdd(counters + 2, ngate);
     }
+    // the block's queue entries and the maxima its loop stored are visible
+    // to the whole block after the barrier
     __syncthreads();
-    if (threadIdx.x == 0)
-        qcount[blockIdx.x] = fill;
-}
-
-// The deferred particles of one k_surrogate pass (same grid: block b takes
-// the segment block b filled): FP64 eigenvalues of the same widened FP32
-// Hessian, the full Classic solve, and the max update against what
-// k_surrogate stored (the maxima carried over from the earlier radii, and at
-// FINALIZE their a(D_c), rewritten here when F wins).
-__global__ void __launch_bounds__(256) k_surrogate_fallback(ItemArgs a, const int32_t* __restrict__ queue,
-                                                           const int32_t* __restrict__ qcount, int64_t seg)
-{
-    extern __shared__ double lds[];
-    const GrowthIndex gi = stage_growth(lds, a);
-    __syncthreads();
-    const int count = qcount[blockIdx.x];
-    const int32_t* myq = queue + (int64_t)blockIdx.x * seg;
-    for (int q = threadIdx.x; q < count; q += blockDim.x) {
-        const uint32_t i = (uint32_t)myq[q];
+    const int count = fill;
+    for (int qi = threadIdx.x; qi < count; qi += blockDim.x) {
+        const uint32_t i = (uint32_t)myq[qi];
         double l1, s, pp;
         eig_top(widen(load_h32(a, i)), l1, s, pp);
         const double F = classic_F(l1, s, pp);

@@ -124,8 +124,6 @@ pino_status mlp_upload(pino_ctx* c, const void* blob, int64_t)
         c->queue_cap = kQueueCap;
         e = hipMalloc((void**)&c->d_queue, (size_t)c->queue_cap * sizeof(int32_t));
     }
-    if (e == hipSuccess)
-        e = hipMalloc((void**)&c->d_qcount, (size_t)kQueueBlocks * sizeof(int32_t));
     if (e != hipSuccess) {
         c->broken = true;
         c->err = std::string("surrogate upload: ") + hipGetErrorString(e);
@@ -152,8 +150,7 @@ inline pino_status launch_fail(pino_ctx* c, const char* what)
 pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemArgs& a0, uint32_t, hipStream_t st,
                              int, int block)
 {
-    const size_t lds_fb = pino::growth_lds_bytes(a0.nk, a0.gi.nb);
-    const size_t lds = lds_fb + sizeof(pino::NetFrags);
+    const size_t lds = pino::growth_lds_bytes(a0.nk, a0.gi.nb) + sizeof(pino::NetFrags);
     auto* cnt = reinterpret_cast<unsigned long long*>(c->d_counters);
     const auto* net = static_cast<const pino::NetFrags*>(c->d_mlp);
     const int64_t cap_blocks = std::min<int64_t>((int64_t)c->cu_count * c->blocks_per_cu, kQueueBlocks);
@@ -170,9 +167,7 @@ pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemA
         const int64_t stride = grid * block;
         const int64_t seg = (a.n + stride - 1) / stride * block;
         hipLaunchKernelGGL(pino::k_surrogate, dim3((unsigned)grid), dim3(block), lds, st, a, net, it.sigma_R,
-                           c->omega[it.cosmo], c->certify_rtol, cnt, c->d_queue, c->d_qcount, seg);
-        hipLaunchKernelGGL(pino::k_surrogate_fallback, dim3((unsigned)grid), dim3(block), lds_fb, st, a,
-                           static_cast<const int32_t*>(c->d_queue), static_cast<const int32_t*>(c->d_qcount), seg);
+                           c->omega[it.cosmo], c->certify_rtol, cnt, c->d_queue, seg);
         const pino_status ps = launch_fail(c, "surrogate launch");
         if (ps != PINO_OK)
             return ps;

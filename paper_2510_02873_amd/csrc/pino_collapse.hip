@@ -244,7 +244,7 @@ void free_all(pino_ctx* c)
     if (!c)
         return;
     void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tidx, c->d_tcoef, c->d_tab, c->d_tab32,
-                    c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_qcount};
+                    c->d_tmp, c->d_mlp, c->d_counters, c->d_queue};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -257,7 +257,6 @@ void free_all(pino_ctx* c)
     c->d_mlp = nullptr;
     c->d_counters = nullptr;
     c->d_queue = nullptr;
-    c->d_qcount = nullptr;
 }
 
 pino_status init_impl(const pino_config* cfg, pino_ctx* c)
