@@ -6,9 +6,9 @@ relative squared error over samples with target w > 0.  Written out layer by
 layer in numpy float64, forward and backward by the chain rule.
 
 bf16=True evaluates the network the way the BF16 matrix-core inference
-does: the weights of the two 64 x 64 layers and their inputs (the ReLU
-outputs of layers 1 and 2) rounded to BF16 (8 significant bits, ties to
-even), everything else unrounded.  Its gradient treats each rounding as the
+does: the weights of the two 64 x 64 layers and the inputs of those layers
+and of the output layer (the ReLU outputs of layers 1, 2 and 3) rounded to
+BF16 (8 significant bits, ties to even), everything else unrounded.  Its gradient treats each rounding as the
 identity (straight-through): it is the exact gradient of the same network
 with the rounding offsets frozen at their current values.
 """
@@ -50,7 +50,7 @@ def forward(theta, x, bf16=False):
     z2 = h1 @ rnd(p["W2"]).T + p["b2"]
     h2 = rnd(np.maximum(z2, 0.0))
     z3 = h2 @ rnd(p["W3"]).T + p["b3"]
-    h3 = np.maximum(z3, 0.0)
+    h3 = rnd(np.maximum(z3, 0.0))
     y = h3 @ p["W4"] + p["b4"][0]
     return y, (x, z1, h1, z2, h2, z3, h3)
 

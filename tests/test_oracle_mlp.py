@@ -70,7 +70,8 @@ def test_round_bf16_matches_library_conversion():
 
 def _frozen_loss(th, x, w, th0):
     """The network with the BF16 rounding offsets frozen at their values for
-    th0: W -> W + (round(W0) - W0), h -> h + (round(h0) - h0)."""
+    th0: W -> W + (round(W0) - W0), h -> h + (round(h0) - h0) for W2, W3 and
+    the three hidden layers' outputs."""
     p, p0 = mlp.unpack(th), mlp.unpack(th0)
     dW2 = mlp.round_bf16(p0["W2"]) - p0["W2"]
     dW3 = mlp.round_bf16(p0["W3"]) - p0["W3"]
@@ -78,9 +79,11 @@ def _frozen_loss(th, x, w, th0):
     dh1 = mlp.round_bf16(h1_0) - h1_0
     h2_0 = np.maximum((h1_0 + dh1) @ (p0["W2"] + dW2).T + p0["b2"], 0.0)
     dh2 = mlp.round_bf16(h2_0) - h2_0
+    h3_0 = np.maximum((h2_0 + dh2) @ (p0["W3"] + dW3).T + p0["b3"], 0.0)
+    dh3 = mlp.round_bf16(h3_0) - h3_0
     h1 = np.maximum(x @ p["W1"].T + p["b1"], 0.0) + dh1
     h2 = np.maximum(h1 @ (p["W2"] + dW2).T + p["b2"], 0.0) + dh2
-    h3 = np.maximum(h2 @ (p["W3"] + dW3).T + p["b3"], 0.0)
+    h3 = np.maximum(h2 @ (p["W3"] + dW3).T + p["b3"], 0.0) + dh3
     y = h3 @ p["W4"] + p["b4"][0]
     r = np.where(w > 0, (y - w) / np.where(w > 0, w, 1.0), 0.0)
     return float(np.sum(r * r) / len(w))
