@@ -87,6 +87,10 @@ pino::NetFrags build_frags(const float* P)
                     const int kk = k32_neuron(kt, g, j);
                     f.w2[mt][kt][l][j] = bf16_bits(P[kOffW2 + o * kH + kk]);
                     f.w3[mt][kt][l][j] = bf16_bits(P[kOffW3 + o * kH + kk]);
+                    // output weights in the same neuron order, every row alike
+                    const float w4 = P[kOffW4 + kk];
+                    f.w4h[kt][l][j] = bf16_bits(w4);
+                    f.w4l[kt][l][j] = bf16_bits(w4 - bf16_value(bf16_bits(w4)));
                 }
             }
         }
@@ -94,7 +98,6 @@ pino::NetFrags build_frags(const float* P)
         f.b1[o] = P[kOffB1 + o];
         f.b2[o] = P[kOffB2 + o];
         f.b3[o] = P[kOffB3 + o];
-        f.w4[o] = P[kOffW4 + o];
     }
     f.b4 = P[kOffB4];
     return f;

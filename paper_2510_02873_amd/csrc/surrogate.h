@@ -113,9 +113,9 @@ __device__ __forceinline__ void dense_cols(const float* __restrict__ W, int u0, 
 }
 
 // pq: the parameters whose W2 and W3 the hidden layers use (the BF16-rounded
-// copy when bf16, else p itself); bf16 also rounds those layers' inputs (the
-// ReLU outputs of layers 1 and 2) to BF16, as the matrix-core inference
-// does.  The backward pass uses the same weights and stored activations and
+// copy when bf16, else p itself); bf16 also rounds the inputs of those layers
+// and of the output layer (the ReLU outputs of layers 1, 2 and 3) to BF16, as
+// the matrix-core inference does.  The backward pass uses the same weights and stored activations and
 // treats the rounding as the identity (straight-through).
 __global__ void __launch_bounds__(kGradThreads) k_mlp_grad_block(const float* __restrict__ p,
                                                                 const float* __restrict__ pq, int bf16,
@@ -162,7 +162,8 @@ __global__ void __launch_bounds__(kGradThreads) k_mlp_grad_block(const float* __
     float yp = 0.0f;  // this wave's share of the output
 #pragma unroll
     for (int u = 0; u < kUw; ++u) {
-        const float hv = fmaxf(z[u], 0.0f);
+        const float hr = fmaxf(z[u], 0.0f);
+        const float hv = bf16 ? bf16_value(bf16_bits(hr)) : hr;
         h3[(u0 + u) * kLd + s] = hv;
         yp = fmaf(p[kOffW4 + u0 + u], hv, yp);
     }
@@ -375,10 +376,14 @@ struct NetFrags {
     s16x8 w1[4][64];     // [mt][lane], BF16 bits
     s16x8 w2[4][2][64];  // [mt][kt][lane]
     s16x8 w3[4][2][64];
-    float b1[kH], b2[kH], b3[kH], w4[kH];
+    s16x8 w4h[2][64];    // [kt][lane]: W4 (BF16 high part) as an MFMA A operand, every row the same
+    s16x8 w4l[2][64];    // the low part (W4 - high), so the output weights are ~FP32-accurate
+    float b1[kH], b2[kH], b3[kH];
     float b4;
     float pad[3];
 };
+
+static_assert(sizeof(NetFrags) % 16 == 0, "NetFrags is staged into LDS in 16-byte pieces");
 
 // Input neuron of K tile kt carried at slot j of lane group g (see above).
 __host__ __device__ __forceinline__ int k32_neuron(int kt, int g, int j)
@@ -500,19 +505,21 @@ __device__ __forceinline__ float net_bf16(const NetFrags& N, const float x[4])
                 acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, hb[e][1], t, 0, 0, 0);
             }
         }
-        // output layer in FP32: this lane's 16 neurons of column q, then the
-        // sum over the four lanes that share the column
+        // output layer on the matrix cores: layer 3's ReLU outputs packed to
+        // BF16 as the B operand, and an A operand holding W4 (BF16 high and
+        // low parts) in every row, so every row of D is the particle's
+        // output and the lanes of group p + e take it from their own column
+        for (int e = 0; e < G; ++e)
+            for (int kt = 0; kt < 2; ++kt)
+                hb[e][kt] = pack_pair(acc[e][2 * kt], acc[e][2 * kt + 1]);
         for (int e = 0; e < G; ++e) {
-            float part = 0.0f;
-            for (int mt = 0; mt < 4; ++mt) {
-                const f32x4 w = bias4(N.w4, mt, g);
-                for (int j = 0; j < 4; ++j)
-                    part += w[j] * fmaxf(acc[e][mt][j], 0.0f);
+            f32x4 o{N.b4, N.b4, N.b4, N.b4};
+            for (int kt = 0; kt < 2; ++kt) {
+                o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(N.w4h[kt][l]), hb[e][kt], o, 0, 0, 0);
+                o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(N.w4l[kt][l]), hb[e][kt], o, 0, 0, 0);
             }
-            part += __shfl_xor(part, 16, 64);
-            part += __shfl_xor(part, 32, 64);
             if (g == p + e)
-                out = part + N.b4;
+                out = o[0];
         }
     }
     return out;
