@@ -129,3 +129,15 @@ def test_interp_calls_reject_bad_sizes():
     with pytest.raises(P.PinoError) as e:
         _abi.pino_table_build(many, torch.zeros((1, 4, 8), dtype=torch.float64), many, many)   # nx = 1
     assert e.value.status == P.PINO_ERR_ARG
+
+
+def test_mlp_calls_reject_null_handle():
+    """The network entry points validate their handle before any HIP call."""
+    import paper_2510_02873_amd as P
+    from paper_2510_02873_amd import _abi
+    L = _abi._bind_mlp()
+    assert L.pino_mlp_set_bf16_forward(None, 1) == P.PINO_ERR_ARG
+    assert L.pino_mlp_grad(None, None, None, 16, None, None, None) == P.PINO_ERR_ARG
+    assert L.pino_mlp_adam(None, None, 1e-3, 0.9, 0.999, 1e-8, None) == P.PINO_ERR_ARG
+    assert L.pino_mlp_forward(None, None, None, 4, None) == P.PINO_ERR_ARG
+    assert L.pino_mlp_free(None) == P.PINO_OK
