@@ -187,6 +187,8 @@ __global__ void __launch_bounds__(64) k_table_splines(const double* __restrict__
 // elimination by rounding only.
 constexpr int kScanPer = 8;
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 // inclusive scan of x -> A x + B over lanes 0..L (up) or L..63 (down);
 // the map of the nearer lanes is applied last
 __device__ __forceinline__ void affine_scan(double& A, double& B, int lane, bool up)
@@ -202,9 +204,13 @@ __device__ __forceinline__ void affine_scan(double& A, double& B, int lane, bool
     }
 }
 
+// pairs (may be NULL): also write the FP32 knot-pair copy of the row,
+// pairs[r (n - 1) + i] = (F_i, M_i, F_{i+1}, M_{i+1}), i < n - 1, the values
+// rounded from the FP64 ones written to tab.
 __global__ void __launch_bounds__(256) k_table_splines_scan(const double* __restrict__ coef, double s, double inv_s,
                                                            int n, const double* __restrict__ F,
-                                                           double* __restrict__ tab, int rows)
+                                                           double* __restrict__ tab, int rows,
+                                                           f4v* __restrict__ pairs)
 {
     const int lane = threadIdx.x & 63;
     const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -285,28 +291,41 @@ __global__ void __launch_bounds__(256) k_table_splines_scan(const double* __rest
     double M = __shfl_down(Bl, 1, 64);  // M just after the lane's last knot
     if (lane == 63)
         M = 0.0;
+    f4v* pr = pairs ? pairs + (int64_t)r * (n - 1) : nullptr;
 #pragma unroll
     for (int k = kScanPer - 1; k >= 0; --k) {
+        const double Mn = M;  // M of the next knot (steps k >= m are identities)
         M = fma(A[k], M, B[k]);
         const int i = i0 + k;
         if (k < m && i < n) {
             t[2 * i] = yv[k];
             t[2 * i + 1] = M;
+            if (pr && i <= n - 2) {
+                double yn = ynl;
+#pragma unroll
+                for (int q = k + 1; q < kScanPer; ++q)
+                    yn = q == k + 1 && q < m ? yv[q] : yn;
+                pr[i] = f4v{(float)yv[k], (float)M, (float)yn, (float)Mn};
+            }
         }
     }
 }
 
 // The table splines of `rows` rows of n knots scaled by s (coef as above):
 // one wave per row when the row fits the scan kernel, else one row per lane.
-inline void launch_table_splines(const double* coef, double s, int n, const double* F, double* tab, int rows,
-                                 hipStream_t st)
+// Returns whether the FP32 knot-pair copy (pairs, may be NULL) was written
+// too (the scan kernel writes it in the same pass).
+inline bool launch_table_splines(const double* coef, double s, int n, const double* F, double* tab, int rows,
+                                 hipStream_t st, f4v* pairs = nullptr)
 {
-    if (n <= 64 * kScanPer)
+    if (n <= 64 * kScanPer) {
         hipLaunchKernelGGL(k_table_splines_scan, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, coef, s,
-                           1.0 / s, n, F, tab, rows);
-    else
-        hipLaunchKernelGGL(k_table_splines, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, coef, s, 1.0 / s,
-                           n, F, tab, rows);
+                           1.0 / s, n, F, tab, rows, pairs);
+        return pairs != nullptr;
+    }
+    hipLaunchKernelGGL(k_table_splines, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, coef, s, 1.0 / s, n,
+                       F, tab, rows);
+    return false;
 }
 
 // ---------------------------------------------------------------------------

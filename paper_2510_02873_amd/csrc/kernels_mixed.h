@@ -202,7 +202,6 @@ __host__ __device__ inline size_t growth32_lds_bytes(int nk, int nb)
 // FP64 on the FP32 table values; a(D) from the FP32 growth knots, as in the
 // mixed Classic kernel.
 // ---------------------------------------------------------------------------
-typedef float f4v __attribute__((ext_vector_type(4)));
 
 // tab32[r (nd - 1) + j] = (F_j, M_j, F_{j+1}, M_{j+1}) of row r, from the
 // interleaved FP64 (F, M) table of the same radius

@@ -421,12 +421,14 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
         // per-radius table: F into the interleaved table and the delta
         // splines over the sigma-scaled knots, rebuilt on the device
         const int rows = c->nx * c->ny;
-        launch_table_splines(c->d_tcoef, it.sigma_R, c->nd, it.table_F, c->d_tab, rows, st);
+        f4v* pairs = c->precision == PINO_MIXED ? static_cast<f4v*>(c->d_tab32) : nullptr;
+        const bool paired_done = launch_table_splines(c->d_tcoef, it.sigma_R, c->nd, it.table_F, c->d_tab, rows, st,
+                                                      pairs);
         PINO_HIP(c, hipGetLastError());
-        if (c->precision == PINO_MIXED) {
-            const int64_t pairs = (int64_t)rows * (c->nd - 1);
-            hipLaunchKernelGGL(k_table_pairs_f32, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, c->d_tab,
-                               static_cast<f4v*>(c->d_tab32), rows, c->nd);
+        if (pairs && !paired_done) {
+            const int64_t count = (int64_t)rows * (c->nd - 1);
+            hipLaunchKernelGGL(k_table_pairs_f32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, c->d_tab,
+                               pairs, rows, c->nd);
             PINO_HIP(c, hipGetLastError());
         }
     }
