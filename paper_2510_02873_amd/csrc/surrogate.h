@@ -328,22 +328,33 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ P
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    // activations in registers: every array index is a compile-time constant
     float a[kH], b[kH];
+    float x[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k)
+        x[k] = X[i * kIn + k];
+#pragma unroll
     for (int o = 0; o < kH; ++o) {
         float z = p[kOffB1 + o];
+#pragma unroll
         for (int k = 0; k < kIn; ++k)
-            z += p[kOffW1 + o * kIn + k] * X[i * kIn + k];
+            z += p[kOffW1 + o * kIn + k] * x[k];
         a[o] = fmaxf(z, 0.0f);
     }
+#pragma unroll
     for (int o = 0; o < kH; ++o) {
         float z = p[kOffB2 + o];
+#pragma unroll
         for (int k = 0; k < kH; ++k)
             z += p[kOffW2 + o * kH + k] * a[k];
         b[o] = fmaxf(z, 0.0f);
     }
     float y = p[kOffB4];
+#pragma unroll
     for (int o = 0; o < kH; ++o) {
         float z = p[kOffB3 + o];
+#pragma unroll
         for (int k = 0; k < kH; ++k)
             z += p[kOffW3 + o * kH + k] * b[k];
         y += p[kOffW4 + o] * fmaxf(z, 0.0f);
