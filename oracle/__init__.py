@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liborc_collapse.so")
 
 CLASSIC = 0
 TABULATED = 1
+CLASSIC_LCDM = 2
 
 
 def build(force: bool = True) -> str:
@@ -71,6 +72,14 @@ def lib():
         L.orc_growth_unnorm.restype = ctypes.c_double
         L.orc_growth_D.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_growth_D.restype = ctypes.c_double
+        L.orc_lpt_growth.argtypes = [ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]
+        L.orc_lpt_growth.restype = ctypes.c_int
+        L.orc_collapse_D_lcdm.argtypes = [_D, ctypes.c_int] + [_D] * 7 + [ctypes.POINTER(ctypes.c_int)]
+        L.orc_collapse_D_lcdm.restype = ctypes.c_double
+        L.orc_update_radius_lcdm.argtypes = ([ctypes.c_int64] + [_D] * 6 + [ctypes.c_int32, ctypes.c_int]
+                                             + [_D] * 9 + [ctypes.c_int, _D, _I32, _D])
+        L.orc_g_lcdm.argtypes = [_D, ctypes.c_int] + [_D] * 7 + [ctypes.c_double, _D]
+        L.orc_g_lcdm.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -168,13 +177,51 @@ def points(h6):
     return lam, F
 
 
-class Growth:
-    """Inverse growth spline a(D) built from a growth table (a_k, D_k)."""
+def lpt_growth(omega_m, a):
+    """Ratios (k2, k3a, k3b) of the second- and third-order LPT growth of flat
+    LCDM to their Einstein-de Sitter values at the scale factors a."""
+    a = _f64(a)
+    k = [np.empty_like(a) for _ in range(3)]
+    if lib().orc_lpt_growth(float(omega_m), len(a), _p(a), *[_p(x) for x in k]) != 0:
+        raise ValueError("need omega_m > 0 and a strictly increasing, > 0")
+    return tuple(k)
 
-    def __init__(self, a, D):
+
+class Growth:
+    """Inverse growth spline a(D) built from a growth table (a_k, D_k).  With
+    omega_m, also the LCDM time coefficients of the LPT collapse at the knots
+    and their natural splines in D (the Classic method with LCDM
+    coefficients)."""
+
+    def __init__(self, a, D, omega_m=None):
         self.a = _f64(a)
         self.D = _f64(D)
         self.M = spline_natural(self.D, self.a)
+        self.omega_m = omega_m
+        if omega_m is not None:
+            self.k2, self.k3a, self.k3b = lpt_growth(omega_m, self.a)
+            self.m2, self.m3a, self.m3b = (spline_natural(self.D, k) for k in (self.k2, self.k3a, self.k3b))
+
+    def _kappa_args(self):
+        if self.omega_m is None:
+            raise ValueError("this growth table has no LCDM coefficients (pass omega_m)")
+        return [_p(x) for x in (self.D, self.k2, self.m2, self.k3a, self.m3a, self.k3b, self.m3b)]
+
+
+def collapse_D_lcdm(lam, growth: Growth):
+    """Growth factor at collapse with the LCDM time coefficients, or None."""
+    lam = _f64(lam)
+    found = ctypes.c_int()
+    D = lib().orc_collapse_D_lcdm(_p(lam), len(growth.D), *growth._kappa_args(), ctypes.byref(found))
+    return D if found.value else None
+
+
+def g_lcdm(lam, growth: Growth, D):
+    """(G(D), dG/dD) of the LCDM collapse condition."""
+    lam = _f64(lam)
+    d = ctypes.c_double()
+    g = lib().orc_g_lcdm(_p(lam), len(growth.D), *growth._kappa_args(), float(D), ctypes.byref(d))
+    return g, d.value
 
 
 class Table:
@@ -197,6 +244,12 @@ def update_radius(h6, radius_index, growth: Growth, Fmax, Rmax, acoll, reset, me
     if acoll is not None:
         assert acoll.dtype == np.float64 and acoll.flags.c_contiguous and acoll.shape == (n,)
     null = ctypes.cast(None, _D)
+    if method == CLASSIC_LCDM:
+        lib().orc_update_radius_lcdm(n, *[_p(h6[c]) for c in range(6)], int(radius_index), len(growth.D),
+                                     _p(growth.D), _p(growth.a), _p(growth.M),
+                                     *growth._kappa_args()[1:], int(bool(reset)), _p(Fmax),
+                                     Rmax.ctypes.data_as(_I32), _p(acoll) if acoll is not None else null)
+        return
     if method == TABULATED:
         t = table
         nx, ny, nd = t.F.shape

@@ -475,3 +475,290 @@ double orc_growth_D(double om, double a)
 {
     return orc_growth_unnorm(om, a) / orc_growth_unnorm(om, 1.0);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Higher-order LPT growth in flat LCDM (cosmology-dependent time           */
+/* coefficients of the LPT collapse condition, Sec. 3).                      */
+/*                                                                          */
+/* With x = ln a, E^2 = Om a^-3 + 1 - Om and Om(a) = Om a^-3 / E^2, the     */
+/* growing modes of the second and third LPT orders solve                    */
+/*   L[D] = D'' + (2 - 1.5 Om(a)) D' - 1.5 Om(a) D                          */
+/*   L[D1] = 0,  L[D2] = -1.5 Om(a) D1^2,  L[D3a] = -3 Om(a) D1^3,          */
+/*   L[D3b] = -3 Om(a) D1 (D2 - D1^2),                                       */
+/* which in Einstein-de Sitter give D2 = -(3/7) D1^2, D3a = -(1/3) D1^3 and  */
+/* D3b = (10/21) D1^3.  Here they are NOT integrated as ODEs: the oracle     */
+/* writes the solution by variation of parameters with the two homogeneous   */
+/* solutions D+ = E I (the growing mode, I = (5 Om / 2) int_0^a da'/(a'E)^3) */
+/* and D- = E (the decaying mode).  Their Wronskian is -(5 Om/2)/(a^2 E),    */
+/* so a source f gives the growing-mode particular solution                  */
+/*   D(a) = (2/(5 Om)) E(a) int_0^a [I(a) - I(a')] E(a')^2 a'^2 f(a') da'/a'. */
+/* With the sources above this becomes                                       */
+/*   D2  = -(3/5) E [I A2 - B2],  A2 = int D1^2 a^-2 da,  B2 = int I D1^2 a^-2 da, */
+/*   D3a = -(6/5) E [I A3 - B3],  A3 = int D1^3 a^-2 da,  B3 = int I D1^3 a^-2 da, */
+/*   D3b = -(6/5) E [I A4 - B4],  A4 = int D1 (D2 - D1^2) a^-2 da,  B4 likewise    */
+/*   with a factor I,                                                           */
+/* all integrals from 0.  Below a_s = 1e-7 a_0 (a_0 the first knot) the      */
+/* Lambda term changes them by less than 1e-20 relative, so their values at  */
+/* a_s are the Einstein-de Sitter power laws; from a_s on they are           */
+/* accumulated by composite Simpson on a grid uniform in ln a, with every    */
+/* knot a grid node and steps of at most 1e-3.  The outputs are the ratios   */
+/* to the Einstein-de Sitter coefficients at each knot,                      */
+/*   k2 = D2 / (-(3/7) D1^2),  k3a = D3a / (-(1/3) D1^3),                     */
+/*   k3b = D3b / ((10/21) D1^3),                                              */
+/* which do not depend on how D1 is normalised.                               */
+/* ------------------------------------------------------------------------ */
+
+/* cumulative integral over the nodes of one segment of uniform step h (m
+ * steps, m even): S[0] = s0, then Simpson over node pairs for the even
+ * nodes and, for the odd ones, the integral over one step of the quadratic
+ * through that step's two nodes and the next, h/12 (5 f0 + 8 f1 - f2). */
+static void cum_simpson(int m, double h, const double *f, double s0, double *S)
+{
+    S[0] = s0;
+    for (int j = 0; j + 2 <= m; j += 2) {
+        S[j + 1] = S[j] + h / 12.0 * (5.0 * f[j] + 8.0 * f[j + 1] - f[j + 2]);
+        S[j + 2] = S[j] + h / 3.0 * (f[j] + 4.0 * f[j + 1] + f[j + 2]);
+    }
+}
+
+int orc_lpt_growth(double om, int nk, const double *ak, double *k2, double *k3a, double *k3b)
+{
+    if (nk < 1 || !(om > 0.0) || !(ak[0] > 0.0))
+        return -1;
+    for (int k = 0; k + 1 < nk; ++k)
+        if (!(ak[k + 1] > ak[k]))
+            return -1;
+    const double ol = 1.0 - om;
+    /* segments: 0 over [a_s, a_0], k >= 1 over [a_{k-1}, a_k], each uniform
+     * in ln a with an even number of steps of at most 1e-3 */
+    const double as = 1e-7 * ak[0];
+    int *ms = (int *)malloc(sizeof(int) * nk);
+    double *hs = (double *)malloc(sizeof(double) * nk);
+    int *st = (int *)malloc(sizeof(int) * nk);
+    int total = 0, mmax = 0;
+    for (int k = 0; k < nk; ++k) {
+        double lo = (k == 0) ? as : ak[k - 1];
+        double dx = log(ak[k] / lo);
+        int m = (int)ceil(dx / 1e-3);
+        if (m < 16)
+            m = 16;
+        m += m & 1;
+        ms[k] = m;
+        hs[k] = dx / m;
+        st[k] = total;
+        total += m;
+        if (m > mmax)
+            mmax = m;
+    }
+    const int nn = total + 1;
+    double *a = (double *)malloc(sizeof(double) * nn);
+    for (int k = 0; k < nk; ++k) {
+        double x0 = log((k == 0) ? as : ak[k - 1]);
+        if (k == 0)
+            a[0] = as;
+        for (int j = 1; j <= ms[k]; ++j)
+            a[st[k] + j] = (j == ms[k]) ? ak[k] : exp(x0 + hs[k] * j);
+    }
+    double *E = (double *)malloc(sizeof(double) * nn);
+    double *I = (double *)malloc(sizeof(double) * nn);
+    double *r1 = (double *)malloc(sizeof(double) * nn); /* D1 / a */
+    double *r2 = (double *)malloc(sizeof(double) * nn); /* D2 / a^2 */
+    double *A = (double *)malloc(sizeof(double) * nn);
+    double *B = (double *)malloc(sizeof(double) * nn);
+    double *A3 = (double *)malloc(sizeof(double) * nn);
+    double *B3 = (double *)malloc(sizeof(double) * nn);
+    double *A4 = (double *)malloc(sizeof(double) * nn);
+    double *B4 = (double *)malloc(sizeof(double) * nn);
+    double *f = (double *)malloc(sizeof(double) * (mmax + 1));
+    for (int j = 0; j < nn; ++j)
+        E[j] = sqrt(om / (a[j] * a[j] * a[j]) + ol);
+
+    /* OUT = s0 at a_s plus the cumulative integral of g da = g a dx, g the
+     * expression gv of node q */
+#define ACCUMULATE(gv, s0, OUT)                                                          \
+    do {                                                                                 \
+        double s = (s0);                                                                 \
+        for (int k = 0; k < nk; ++k) {                                                   \
+            for (int j = 0; j <= ms[k]; ++j) {                                           \
+                int q = st[k] + j;                                                       \
+                f[j] = (gv) * a[q];                                                      \
+            }                                                                            \
+            cum_simpson(ms[k], hs[k], f, s, OUT + st[k]);                                \
+            s = OUT[st[k] + ms[k]];                                                      \
+        }                                                                                \
+    } while (0)
+
+    /* Einstein-de Sitter values at a_s: I = a^(5/2)/sqrt(Om), D1 = a,
+     * D2 = -(3/7) a^2 */
+    const double sq = sqrt(om);
+    const double i_s = as * as * sqrt(as) / sq;
+    ACCUMULATE(2.5 * om / (a[q] * E[q] * a[q] * E[q] * a[q] * E[q]), i_s, I);
+    for (int j = 0; j < nn; ++j)
+        r1[j] = E[j] * I[j] / a[j];
+    ACCUMULATE(r1[q] * r1[q], as, A);
+    ACCUMULATE(I[q] * r1[q] * r1[q], (2.0 / 7.0) * i_s * as, B);
+    for (int j = 0; j < nn; ++j)
+        r2[j] = -0.6 * E[j] * (I[j] * A[j] - B[j]) / (a[j] * a[j]);
+    ACCUMULATE(r1[q] * r1[q] * r1[q] * a[q], 0.5 * as * as, A3);
+    ACCUMULATE(I[q] * r1[q] * r1[q] * r1[q] * a[q], (2.0 / 9.0) * i_s * as * as, B3);
+    ACCUMULATE(r1[q] * (r2[q] - r1[q] * r1[q]) * a[q], -(5.0 / 7.0) * as * as, A4);
+    ACCUMULATE(I[q] * r1[q] * (r2[q] - r1[q] * r1[q]) * a[q], -(10.0 / 7.0) * (2.0 / 9.0) * i_s * as * as, B4);
+#undef ACCUMULATE
+    for (int k = 0; k < nk; ++k) {
+        int q = st[k] + ms[k];
+        double d1 = r1[q] * a[q];
+        double d2 = r2[q] * a[q] * a[q];
+        double d3a = -1.2 * E[q] * (I[q] * A3[q] - B3[q]);
+        double d3b = -1.2 * E[q] * (I[q] * A4[q] - B4[q]);
+        k2[k] = d2 / (-(3.0 / 7.0) * d1 * d1);
+        k3a[k] = d3a / (-(1.0 / 3.0) * d1 * d1 * d1);
+        k3b[k] = d3b / ((10.0 / 21.0) * d1 * d1 * d1);
+    }
+    free(ms); free(hs); free(st); free(a); free(E); free(I); free(r1); free(r2);
+    free(A); free(B); free(A3); free(B3); free(A4); free(B4); free(f);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Classic collapse with the LCDM time coefficients.  The EdS coefficients  */
+/* of the axis-1 condition split as beta (second order), gamma_a (the        */
+/* -(1/9) a1 a2 a3 part of c_1, a third-order term of determinant type) and  */
+/* gamma_b = c_1 - gamma_a (the mixed first-times-second-order terms).  In   */
+/* LCDM each is scaled by its growth ratio at the epoch where the growth     */
+/* factor is D:                                                              */
+/*   G(D) = 1 - l1 D + k2(D) beta D^2 + (k3a(D) gamma_a + k3b(D) gamma_b) D^3, */
+/* with k2, k3a, k3b the natural cubic splines in D of their values at the   */
+/* growth-table knots (D_k, from orc_lpt_growth at a_k), held at the end     */
+/* values outside [D_0, D_{n-1}].  The collapse is the smallest positive     */
+/* root of G: a sign scan on a geometric grid of 4001 points from 1e-4/L to  */
+/* 1e4/L (L = max(|l1|, |l3|), ratio 1.0046), bisection of the first step    */
+/* that reaches G <= 0, and past the grid the doubling search of the         */
+/* constant-coefficient cubic.                                              */
+/* ------------------------------------------------------------------------ */
+static double kappa_at(int nk, const double *D, const double *k, const double *M, double Dq)
+{
+    if (Dq <= D[0])
+        return k[0];
+    if (Dq >= D[nk - 1])
+        return k[nk - 1];
+    return orc_spline_eval(nk, D, k, M, Dq);
+}
+
+typedef struct {
+    int nk;
+    const double *D, *k2, *m2, *k3a, *m3a, *k3b, *m3b;
+} orc_kappa;
+
+static double g_lcdm(const orc_kappa *K, double l1, double beta, double ga, double gb, double D)
+{
+    double k2 = kappa_at(K->nk, K->D, K->k2, K->m2, D);
+    double k3a = kappa_at(K->nk, K->D, K->k3a, K->m3a, D);
+    double k3b = kappa_at(K->nk, K->D, K->k3b, K->m3b, D);
+    return 1.0 - l1 * D + k2 * beta * D * D + (k3a * ga + k3b * gb) * D * D * D;
+}
+
+static double bisect_lcdm(const orc_kappa *K, double l1, double beta, double ga, double gb, double lo, double hi)
+{
+    for (int it = 0; it < 5000; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi))
+            break;
+        if (g_lcdm(K, l1, beta, ga, gb, mid) > 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
+double orc_collapse_D_lcdm(const double lam[3], int nk, const double *D, const double *k2, const double *m2,
+                           const double *k3a, const double *m3a, const double *k3b, const double *m3b, int *found)
+{
+    orc_kappa K = {nk, D, k2, m2, k3a, m3a, k3b, m3b};
+    double l1 = lam[0], beta, c1;
+    orc_lpt_axis(lam, 0, &beta, &c1);
+    double ga = (1.0 / 9.0) * lam[0] * lam[1] * lam[2]; /* -(1/9) a1 a2 a3 with a_i = -l_i */
+    double gb = c1 - ga;
+    *found = 0;
+    if (!(isfinite(l1) && isfinite(beta) && isfinite(c1)))
+        return 0.0;
+    double L = fabs(lam[0]) > fabs(lam[2]) ? fabs(lam[0]) : fabs(lam[2]);
+    if (!(L > 0.0))
+        return 0.0;
+    const int npts = 4001;
+    const double d0 = 1e-4 / L;
+    const double ratio = pow(1e8, 1.0 / (npts - 1));
+    double prev = 0.0, Dj = d0;
+    for (int j = 0; j < npts; ++j) {
+        if (g_lcdm(&K, l1, beta, ga, gb, Dj) <= 0.0) {
+            *found = 1;
+            return bisect_lcdm(&K, l1, beta, ga, gb, prev, Dj);
+        }
+        prev = Dj;
+        Dj *= ratio;
+    }
+    /* past the grid (and past the last knot for any realistic L): the cubic
+     * with the coefficients held at their last-knot values */
+    double kb = k2[nk - 1] * beta, kc = k3a[nk - 1] * ga + k3b[nk - 1] * gb;
+    int falls = (kc < 0.0) || (kc == 0.0 && kb < 0.0);
+    if (!falls)
+        return 0.0;
+    double hi = 2.0 * prev;
+    while (g_lcdm(&K, l1, beta, ga, gb, hi) > 0.0) {
+        prev = hi;
+        hi *= 2.0;
+        if (hi > 1e300)
+            return 0.0;
+    }
+    *found = 1;
+    return bisect_lcdm(&K, l1, beta, ga, gb, prev, hi);
+}
+
+/* One smoothing radius of the Classic method with LCDM time coefficients
+ * (same per-particle flow as orc_update_radius). */
+void orc_update_radius_lcdm(int64_t n, const double *hxx, const double *hyy, const double *hzz, const double *hxy,
+                            const double *hxz, const double *hyz, int32_t radius_index, int nk, const double *gD,
+                            const double *ga, const double *gM, const double *k2, const double *m2,
+                            const double *k3a, const double *m3a, const double *k3b, const double *m3b, int reset,
+                            double *Fmax, int32_t *Rmax, double *acoll)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        if (reset) {
+            Fmax[i] = 0.0;
+            Rmax[i] = -1;
+            if (acoll)
+                acoll[i] = INFINITY;
+        }
+        double h[6] = {hxx[i], hyy[i], hzz[i], hxy[i], hxz[i], hyz[i]};
+        double lam[3];
+        orc_eig3(h, lam);
+        int found;
+        double Dc = orc_collapse_D_lcdm(lam, nk, gD, k2, m2, k3a, m3a, k3b, m3b, &found);
+        double F = found ? 1.0 / Dc : 0.0;
+        if (F > Fmax[i]) {
+            Fmax[i] = F;
+            Rmax[i] = radius_index;
+            if (acoll)
+                acoll[i] = orc_growth_invert(nk, gD, ga, gM, Dc);
+        }
+    }
+}
+
+/* G(D) of orc_collapse_D_lcdm and its derivative dG/dD by central
+ * difference at step 1e-6 D (test diagnostics: near-tangent roots) */
+double orc_g_lcdm(const double lam[3], int nk, const double *D, const double *k2, const double *m2,
+                  const double *k3a, const double *m3a, const double *k3b, const double *m3b, double Dq,
+                  double *dG)
+{
+    orc_kappa K = {nk, D, k2, m2, k3a, m3a, k3b, m3b};
+    double beta, c1;
+    orc_lpt_axis(lam, 0, &beta, &c1);
+    double ga = (1.0 / 9.0) * lam[0] * lam[1] * lam[2];
+    double gb = c1 - ga;
+    if (dG) {
+        double e = 1e-6 * Dq;
+        *dG = (g_lcdm(&K, lam[0], beta, ga, gb, Dq + e) - g_lcdm(&K, lam[0], beta, ga, gb, Dq - e)) / (2.0 * e);
+    }
+    return g_lcdm(&K, lam[0], beta, ga, gb, Dq);
+}
