@@ -39,7 +39,13 @@
  * ABI.  pino_collapse_last_error() returns a message for the last failure.
  * After PINO_ERR_HIP the context answers PINO_ERR_STATE until it is freed.
  *
- * Threads: a context may be used by one host thread at a time.
+ * Threads and streams: a context may be used by one host thread at a time.
+ * Successive evals may use different streams.  A context that holds device
+ * scratch of its own (the Tabulated method's per-radius table, the
+ * surrogate's queue and counters) orders its evals across streams: an eval
+ * on a stream other than the previous eval's waits for that eval's work.
+ * While the caller captures a stream into a graph no such ordering is
+ * inserted; the caller then orders the graph against other streams.
  */
 #ifndef PINO_COLLAPSE_H
 #define PINO_COLLAPSE_H
@@ -61,7 +67,21 @@ typedef enum {
     PINO_ERR_UNSUPPORTED = 5   /* combination of options not implemented */
 } pino_status;
 
-typedef enum { PINO_CLASSIC = 0, PINO_TABULATED = 1 } pino_method;
+/* Collapse method.
+ *   PINO_CLASSIC      : the third-order LPT condition with its Einstein-de
+ *                       Sitter time coefficients (Sec. 3).
+ *   PINO_TABULATED    : the (delta, x, y) table (Sec. 3, Sec. 4.2).
+ *   PINO_CLASSIC_LCDM : the same LPT condition with the time coefficients
+ *                       of flat LCDM: its second- and third-order terms are
+ *                       scaled by the ratios of their LCDM growth functions
+ *                       to the Einstein-de Sitter ones at the epoch of the
+ *                       growth factor D (Sec. 3 names the LPT formulation;
+ *                       the cosmology dependence is an addition).  The ratios
+ *                       are integrated on the device at init for each growth
+ *                       table's omega_m (0 < omega_m <= 1; flat, no
+ *                       radiation) at its knots and interpolated in D.  FP64
+ *                       only; Classic per-radius evals only (no batch plan). */
+typedef enum { PINO_CLASSIC = 0, PINO_TABULATED = 1, PINO_CLASSIC_LCDM = 2 } pino_method;
 
 /* Arithmetic of the evaluation.
  *   PINO_FP64      : FP64 Hessians, FP64 throughout.
@@ -73,13 +93,15 @@ typedef enum { PINO_CLASSIC = 0, PINO_TABULATED = 1 } pino_method;
  *                    the device each radius (F and the spline second
  *                    derivatives rounded to FP32), the interpolation in FP64.
  *                    a(D) in FP32 for both.
- *   PINO_SURROGATE : FP32 Hessians; a small network predicts the collapse
+ *   PINO_SURROGATE : FP64 Hessians and FP64 eigenvalues; a small network
+ *                    (BF16 matrix-core inference) predicts the collapse
  *                    growth factor and one FP64 Newton step refines it; the
  *                    result is accepted only if the first root of the
- *                    collapse condition provably lies within certify_rtol of
- *                    it.  Particles that fail are queued and take the full
- *                    FP64 solve in a second kernel of the same eval (items
- *                    are processed in chunks of 2^24 particles, the queue's
+ *                    particle's collapse condition provably lies within
+ *                    certify_rtol of it.  Particles that fail are queued by
+ *                    the workgroup that visited them, which then gives them
+ *                    the full FP64 solve in the same launch (items are
+ *                    processed in chunks of 2^24 particles, the queue's
  *                    size).  Classic only; weights from pino_mlp.h. */
 typedef enum { PINO_FP64 = 0, PINO_MIXED = 1, PINO_SURROGATE = 2 } pino_precision;
 
@@ -95,7 +117,8 @@ typedef enum { PINO_FP64 = 0, PINO_MIXED = 1, PINO_SURROGATE = 2 } pino_precisio
 /* One linear growth table: n >= 4 knots, a and D strictly increasing and
  * finite (host pointers, copied by init).  The library builds the natural
  * spline a(D) from it on the device.  omega_m is the matter density of the
- * cosmology (an input of the surrogate network; otherwise unused). */
+ * cosmology: an input of the surrogate network, and the cosmology of the
+ * PINO_CLASSIC_LCDM time coefficients; otherwise unused. */
 typedef struct {
     int32_t n;
     const double *a;
@@ -130,8 +153,8 @@ typedef struct {
 /* One realisation at one smoothing radius. */
 typedef struct {
     int64_t n;                       /* particles, >= 0 */
-    const void *h[6];                /* device: double (PINO_FP64) or float
-                                        (PINO_MIXED, PINO_SURROGATE), each n long */
+    const void *h[6];                /* device: double (PINO_FP64, PINO_SURROGATE)
+                                        or float (PINO_MIXED), each n long */
     int32_t cosmo;                   /* growth table index, 0 <= cosmo < n_cosmo */
     int32_t radius_index;            /* written to Rmax on update, >= 0 */
     double sigma_R;                  /* rms of the smoothed field at this radius
@@ -145,24 +168,65 @@ typedef struct {
 
 typedef struct pino_ctx pino_ctx;
 
-/* Create a context on cfg->device: copy the growth tables (and table knots
- * or network weights) to the device and build their splines there.  Waits for
- * that work to finish.  On failure *out is NULL and the status says why. */
+/* Create a context on cfg->device (Sec. 3, Sec. 4.2).
+ *
+ * Copies the growth tables to the device and builds there, for each, the
+ * natural cubic spline of a as a function of D that turns the growth factor
+ * at collapse into a_coll (Sec. 3: the collapse time follows from a spline
+ * of the linear growth table; Sec. 4.2: splines built and evaluated on the
+ * device).  A Tabulated context also copies its table knots and allocates
+ * the per-radius table the evals rebuild; a surrogate context converts the
+ * network weights to its matrix-core fragments and allocates its queue.
+ * Waits for that work to finish.
+ *
+ * cfg: host pointer, read during the call only (every host array it points
+ * to is copied).  *out: the new context, owned by the caller until
+ * pino_collapse_free.  Errors: PINO_ERR_ARG (invalid configuration, checked
+ * before any HIP call), PINO_ERR_UNSUPPORTED (knots that do not fit the
+ * kernels' LDS), PINO_ERR_HIP or PINO_ERR_ALLOC; on failure *out is NULL
+ * and pino_collapse_last_error(NULL) says why. */
 pino_status pino_collapse_init(const pino_config *cfg, pino_ctx **out);
 
-/* Apply n_items items, in order, on hip_stream (a hipStream_t; NULL means the
- * device's null stream).  Asynchronous unless PINO_EVAL_SYNC.  Items may mix
- * realisations and cosmologies; items whose outputs overlap are applied in
- * the order given.  Allocates nothing. */
+/* Apply n_items items, in order, on hip_stream (Sec. 3, Sec. 4.1).
+ *
+ * Per particle of each item: the eigenvalues of its Hessian, sorted in
+ * descending order (Sec. 3, an analytic method); the growth factor at
+ * collapse from the Classic third-order LPT condition or from the Tabulated
+ * spline/bilinear interpolation (Sec. 3, Sec. 4.2); F = 1/D_c; the strict
+ * '>' update of the per-element maxima Fmax and Rmax, and a_coll (Sec. 4.1:
+ * the kernel's read/modify/write of two output arrays per element).
+ * Tabulated items first rebuild the natural splines of their table on the
+ * device (Sec. 4.2).
+ *
+ * items: host array of n_items items, read during the call; their device
+ * arrays stay owned by the caller and must stay valid until the stream has
+ * run the work.  hip_stream: a hipStream_t, NULL for the device's null
+ * stream.  Asynchronous unless PINO_EVAL_SYNC.  Items may mix realisations
+ * and cosmologies; items whose outputs overlap are applied in the order
+ * given.  Allocates nothing.  Errors: PINO_ERR_ARG (nothing enqueued),
+ * PINO_ERR_STATE (context broken), PINO_ERR_HIP (launch failure; the context
+ * is broken from then on). */
 pino_status pino_collapse_eval(pino_ctx *ctx, const pino_item *items, int32_t n_items, uint32_t flags,
                                void *hip_stream);
 
-/* Release everything init allocated.  NULL-safe.  Waits for the context's
- * outstanding work on the device. */
+/* Release everything init allocated (the device copies of the growth
+ * tables, splines and table of Sec. 3 and Sec. 4.2).  NULL-safe.  Waits for
+ * the context's device first.  Returns PINO_ERR_HIP if that wait reports an
+ * error; the memory is released either way. */
 pino_status pino_collapse_free(pino_ctx *ctx);
 
+/* The LCDM time coefficients of a PINO_CLASSIC_LCDM context at the knots of
+ * growth table `cosmo`: k2, k3a, k3b (host arrays of that table's n
+ * doubles, written) are the second-order, third-order determinant-type and
+ * third-order mixed growth divided by their Einstein-de Sitter values
+ * (-(3/7) D^2, -(1/3) D^3, (10/21) D^3).  Waits for the context's device.
+ * PINO_ERR_ARG for another method, a bad index or NULL outputs. */
+pino_status pino_collapse_lpt_coefficients(pino_ctx *ctx, int32_t cosmo, double *k2, double *k3a, double *k3b);
+
 /* Message for the last failure on ctx, or of the last failed init on this
- * thread when ctx is NULL.  Never NULL; valid until the next call. */
+ * thread when ctx is NULL.  Never NULL; owned by the library and valid until
+ * the next call on the same context (or thread).  Not a method of the paper:
+ * the error channel of this ABI. */
 const char *pino_collapse_last_error(const pino_ctx *ctx);
 
 #ifdef __cplusplus

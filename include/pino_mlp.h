@@ -50,12 +50,13 @@ pino_status pino_mlp_grad(pino_mlp *m, const float *x, const float *w, int64_t n
                           void *hip_stream);
 
 /* BF16 forward for training (on = 1; off = 0, the default): pino_mlp_grad
- * then evaluates the network as the collapse kernel's matrix-core inference
- * does -- the weights of the two 64 x 64 layers and their inputs (the ReLU
- * outputs of layers 1 and 2) rounded to BF16 (nearest even), FP32
- * accumulation, layer 1 and the output layer in FP32 -- and back-propagates
- * through the rounding as if it were the identity (straight-through), into
- * the FP32 master parameters.  PINO_ERR_ARG for other values of on. */
+ * then evaluates the network under the BF16 rounding rule of the surrogate:
+ * the weights of the two 64 x 64 layers, and the inputs of those layers and
+ * of the output layer (the ReLU outputs of layers 1, 2 and 3), rounded to
+ * BF16 (nearest even, ties to even); FP32 accumulation; layer 1's weights
+ * and inputs, the output layer's weights and every bias kept FP32.  The
+ * backward pass treats the rounding as the identity (straight-through) and
+ * updates the FP32 master parameters.  PINO_ERR_ARG for other values of on. */
 pino_status pino_mlp_set_bf16_forward(pino_mlp *m, int32_t on);
 
 /* One Adam step (bias-corrected; step counter kept in the handle) with the
@@ -85,12 +86,15 @@ pino_status pino_collapse_features(pino_ctx *ctx, const pino_item *item, float *
  * x [n][4] -> y [n] (device), the arithmetic the collapse kernel uses. */
 pino_status pino_collapse_predict(pino_ctx *ctx, const float *x, float *y, int64_t n, void *hip_stream);
 
-/* Counts since init (or the last reset) of a PINO_SURROGATE context:
- * particles whose Newton-certified prediction was accepted, particles that
- * took the full solve, particles gated out (l1 <= 0 counts as gated).
- * Waits for the context's work on the device. */
-pino_status pino_collapse_surrogate_stats(pino_ctx *ctx, int64_t *certified, int64_t *fallback, int64_t *gated,
-                                          int32_t reset);
+/* Counts since init (or the last reset) of a PINO_SURROGATE context, one
+ * per particle and radius: certified (the Newton-certified prediction was
+ * accepted); fallback (consulted but not certified: full solve);
+ * gated_solved (0 < l1 < 0.1 |l3|, not consulted: full solve); gated_zero
+ * (l1 <= 0: F = 0 exactly, no solve).  The four add up to the evaluations
+ * made; fallback + gated_solved took the full FP64 solve.  Any pointer may
+ * be NULL.  Waits for the context's device. */
+pino_status pino_collapse_surrogate_stats(pino_ctx *ctx, int64_t *certified, int64_t *fallback,
+                                          int64_t *gated_solved, int64_t *gated_zero, int32_t reset);
 
 #ifdef __cplusplus
 }

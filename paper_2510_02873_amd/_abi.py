@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpino_collapse.so")
 
 PINO_ABI_VERSION = 1
 PINO_OK, PINO_ERR_ARG, PINO_ERR_ALLOC, PINO_ERR_HIP, PINO_ERR_STATE, PINO_ERR_UNSUPPORTED = range(6)
-PINO_CLASSIC, PINO_TABULATED = 0, 1
+PINO_CLASSIC, PINO_TABULATED, PINO_CLASSIC_LCDM = 0, 1, 2
 PINO_FP64, PINO_MIXED, PINO_SURROGATE = 0, 1, 2
 PINO_EVAL_RESET = 1
 PINO_EVAL_SYNC = 2
@@ -79,6 +79,8 @@ def lib():
         L.pino_collapse_free.restype = ctypes.c_int
         L.pino_collapse_last_error.argtypes = [ctypes.c_void_p]
         L.pino_collapse_last_error.restype = ctypes.c_char_p
+        L.pino_collapse_lpt_coefficients.argtypes = [ctypes.c_void_p, ctypes.c_int32, _D, _D, _D]
+        L.pino_collapse_lpt_coefficients.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -163,6 +165,14 @@ def make_item(h, Fmax, Rmax, a_coll=None, radius_index=0, cosmo=0, sigma_R=1.0, 
     return it
 
 
+def pino_collapse_lpt_coefficients(ctx, cosmo, n):
+    """(k2, k3a, k3b) at the n knots of growth table `cosmo` of a
+    PINO_CLASSIC_LCDM context (host float64 arrays)."""
+    out = [np.empty(n) for _ in range(3)]
+    _check(lib().pino_collapse_lpt_coefficients(ctx, int(cosmo), *[o.ctypes.data_as(_D) for o in out]), ctx)
+    return tuple(out)
+
+
 def pino_collapse_eval(ctx, items, flags=0, stream=None):
     """items: list of pino_item; stream: torch stream, raw handle, or None."""
     n = len(items)
@@ -199,8 +209,7 @@ def _bind_mlp():
     L.pino_mlp_free.argtypes = [c_p]
     L.pino_collapse_features.argtypes = [c_p, ctypes.POINTER(pino_item), c_p, c_p, c_p]
     L.pino_collapse_predict.argtypes = [c_p, c_p, c_p, c_i64, c_p]
-    L.pino_collapse_surrogate_stats.argtypes = [c_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
-                                                ctypes.POINTER(c_i64), ctypes.c_int32]
+    L.pino_collapse_surrogate_stats.argtypes = [c_p] + [ctypes.POINTER(c_i64)] * 4 + [ctypes.c_int32]
     for name in ("pino_mlp_create", "pino_mlp_set_params", "pino_mlp_get_params", "pino_mlp_forward",
                  "pino_mlp_grad", "pino_mlp_adam", "pino_mlp_set_bf16_forward", "pino_mlp_train_step",
                  "pino_mlp_export", "pino_mlp_free",
@@ -281,10 +290,14 @@ def pino_collapse_predict(ctx, x, y, stream=None):
 
 
 def pino_collapse_surrogate_stats(ctx, reset=False):
-    c, f, g = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(_bind_mlp().pino_collapse_surrogate_stats(ctx, ctypes.byref(c), ctypes.byref(f), ctypes.byref(g),
-                                                     int(bool(reset))), ctx)
-    return {"certified": c.value, "fallback": f.value, "gated": g.value}
+    """Counts of the surrogate path: certified, fallback (consulted, full
+    solve), gated_solved (not consulted, full solve), gated_zero (l1 <= 0),
+    plus the sums gated and full_solve."""
+    v = [ctypes.c_int64() for _ in range(4)]
+    _check(_bind_mlp().pino_collapse_surrogate_stats(ctx, *[ctypes.byref(x) for x in v], int(bool(reset))), ctx)
+    c, f, gs, gz = (x.value for x in v)
+    return {"certified": c, "fallback": f, "gated_solved": gs, "gated_zero": gz, "gated": gs + gz,
+            "full_solve": f + gs}
 
 
 # ---------------------------------------------------------------------------

@@ -6,6 +6,53 @@
 #include <string>
 #include <vector>
 
+// Orders the calls of one handle that share its device scratch (a per-radius
+// table, a queue, FFT work buffers) when the caller moves between streams:
+// after each call an event is recorded on the call's stream, and a call on a
+// different stream first waits for it.  Work the caller captures into a graph
+// is not ordered this way (no event is recorded or waited on a capturing
+// stream); ordering such graphs against other streams is the caller's.
+struct StreamOrder {
+    hipEvent_t ev = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
+    bool capturing = false;
+
+    hipError_t create()
+    {
+        return hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    }
+    void destroy()
+    {
+        if (ev)
+            (void)hipEventDestroy(ev);
+        ev = nullptr;
+    }
+    // before the call's first launch on s
+    hipError_t enter(hipStream_t s)
+    {
+        if (!ev)
+            return hipSuccess;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(s, &cs);
+        if (e != hipSuccess)
+            return e;
+        capturing = cs != hipStreamCaptureStatusNone;
+        if (!capturing && used && s != last)
+            e = hipStreamWaitEvent(s, ev, 0);
+        return e;
+    }
+    // after the call's last launch on s
+    hipError_t leave(hipStream_t s)
+    {
+        if (!ev || capturing)
+            return hipSuccess;
+        last = s;
+        used = true;
+        return hipEventRecord(ev, s);
+    }
+};
+
 struct pino_ctx {
     int device = 0;
     int method = 0;
@@ -47,6 +94,11 @@ struct pino_ctx {
     // spline-build scratch
     double* d_tmp = nullptr;
 
+    // PINO_CLASSIC_LCDM: per cosmology [k2 | k3a | k3b | m2 | m3a | m3b] at
+    // the growth knots (stride 6 * nk_max): the LCDM growth ratios of the
+    // LPT terms and their natural-spline second derivatives in D
+    double* d_kap = nullptr;
+
     // surrogate network: BF16 weight fragments, certificate tolerance,
     // counters (certified, fallback, gated), Omega_m per cosmology
     void* d_mlp = nullptr;
@@ -57,6 +109,10 @@ struct pino_ctx {
     int32_t* d_queue = nullptr;
     int64_t queue_cap = 0;
     std::vector<double> omega;
+
+    // orders evals across streams (contexts with per-context scratch: the
+    // Tabulated table, the surrogate's queue and counters)
+    StreamOrder order;
 
     bool broken = false;
     std::string err = "no error";

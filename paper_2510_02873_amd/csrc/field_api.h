@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/pino_field.h"
+#include "ctx.h"
 #include "kernels_field.h"
 
 struct pino_field {
@@ -20,6 +21,7 @@ struct pino_field {
     double* hbuf = nullptr;     // 6 * points doubles (or floats for FP32)
     hipfftHandle p64 = 0, p32 = 0;
     bool has64 = false, has32 = false;
+    StreamOrder order;  // kbuf and hbuf are shared by every call on the field
     bool broken = false;
     std::string err = "no error";
 };
@@ -77,6 +79,7 @@ void field_release(pino_field* f)
     f->has64 = f->has32 = false;
     f->kbuf = nullptr;
     f->hbuf = nullptr;
+    f->order.destroy();
 }
 
 pino_status field_init(pino_field* f)
@@ -94,6 +97,7 @@ pino_status field_init(pino_field* f)
     FIELD_FFT(f, hipfftPlanMany(&f->p32, 3, dims, inembed, 1, (int)f->modes, onembed, 1, (int)f->points,
                                 HIPFFT_C2R, 6));
     f->has32 = true;
+    FIELD_HIP(f, f->order.create());
     return PINO_OK;
 }
 
@@ -180,7 +184,13 @@ pino_status pino_field_hessian(pino_field* f, const void* delta_k, double R, dou
     const pino_status st = field_check(f, delta_k, R, H);
     if (st != PINO_OK)
         return st;
-    return field_hessian_impl<false>(f, delta_k, R, H, static_cast<hipStream_t>(hip_stream));
+    const hipStream_t hs = static_cast<hipStream_t>(hip_stream);
+    FIELD_HIP(f, f->order.enter(hs));
+    const pino_status ps = field_hessian_impl<false>(f, delta_k, R, H, hs);
+    if (ps != PINO_OK)
+        return ps;
+    FIELD_HIP(f, f->order.leave(hs));
+    return PINO_OK;
 }
 
 pino_status pino_field_hessian_f32(pino_field* f, const void* delta_k, double R, float* H, void* hip_stream)
@@ -192,7 +202,13 @@ pino_status pino_field_hessian_f32(pino_field* f, const void* delta_k, double R,
     const pino_status st = field_check(f, delta_k, R, H);
     if (st != PINO_OK)
         return st;
-    return field_hessian_impl<true>(f, delta_k, R, H, static_cast<hipStream_t>(hip_stream));
+    const hipStream_t hs = static_cast<hipStream_t>(hip_stream);
+    FIELD_HIP(f, f->order.enter(hs));
+    const pino_status ps = field_hessian_impl<true>(f, delta_k, R, H, hs);
+    if (ps != PINO_OK)
+        return ps;
+    FIELD_HIP(f, f->order.leave(hs));
+    return PINO_OK;
 }
 
 pino_status pino_field_collapse(pino_field* f, pino_ctx* ctx, const void* delta_k, const double* radii,
@@ -213,7 +229,8 @@ pino_status pino_field_collapse(pino_field* f, pino_ctx* ctx, const void* delta_
         f->err = "the context and the field are on different devices";
         return PINO_ERR_ARG;
     }
-    const bool f32 = ctx->precision != PINO_FP64;
+    // FP32 Hessians for a mixed-precision context, FP64 otherwise
+    const bool f32 = ctx->precision == PINO_MIXED;
     for (int32_t r = 0; r < n_radii; ++r) {
         if (!(radii[r] >= 0.0) || !std::isfinite(radii[r])) {
             f->err = "radii must be finite and >= 0";
@@ -225,6 +242,7 @@ pino_status pino_field_collapse(pino_field* f, pino_ctx* ctx, const void* delta_
         }
     }
     const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    FIELD_HIP(f, f->order.enter(st));
     for (int32_t r = 0; r < n_radii; ++r) {
         pino_status ps = f32 ? field_hessian_impl<true>(f, delta_k, radii[r], f->hbuf, st)
                              : field_hessian_impl<false>(f, delta_k, radii[r], f->hbuf, st);
@@ -245,6 +263,7 @@ pino_status pino_field_collapse(pino_field* f, pino_ctx* ctx, const void* delta_
             return ps;
         }
     }
+    FIELD_HIP(f, f->order.leave(st));
     return PINO_OK;
 }
 

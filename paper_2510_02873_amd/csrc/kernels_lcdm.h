@@ -1,0 +1,244 @@
+// Classic collapse with the time coefficients of flat LCDM (Sec. 3: the LPT
+// collapse condition; its second- and third-order terms grow, in LCDM, with
+// growth functions of their own instead of the Einstein-de Sitter powers of
+// D).
+//
+// Growth ratios.  With x = ln a, Om(a) = Om a^-3 / (Om a^-3 + 1 - Om) and
+//   L[D] = D'' + (2 - 1.5 Om(a)) D' - 1.5 Om(a) D,
+// the growing modes solve L[D1] = 0, L[D2] = -1.5 Om(a) D1^2,
+// L[D3a] = -3 Om(a) D1^3 and L[D3b] = -3 Om(a) D1 (D2 - D1^2); in Einstein-de
+// Sitter D2 = -(3/7) D1^2, D3a = -(1/3) D1^3, D3b = (10/21) D1^3.  The ratios
+//   k2 = D2 / (-(3/7) D1^2), k3a = D3a / (-(1/3) D1^3), k3b = D3b / ((10/21) D1^3)
+// scale the corresponding terms of the collapse condition.  k_lpt_growth
+// integrates the eight first-order equations with classical RK4 in x, from
+// the Einstein-de Sitter growing modes at a_s = 1e-7 a_0 (where the Lambda
+// term is below 1e-20 of the matter term), in steps of at most 1e-3 that land
+// on every knot of the growth table, and stores the ratios at the knots.
+// The collapse kernels interpolate them with natural cubic splines in D over
+// the same knots (held at the end values outside them).
+//
+// Collapse.  In u = l1 D the axis-1 condition becomes
+//   G(u) = 1 - u + k2(D) b u^2 + (k3a(D) ca + k3b(D) cb) u^3,
+// with b, ca + cb = c the Einstein-de Sitter coefficients of lpt_cubic split
+// into the determinant-type part ca = pp / (9 l1^2) and the mixed part cb.
+// The root: the Einstein-de Sitter cubic's first root gives D_e; the cubic
+// with the ratios frozen at D_e gives u1 (its first root, same solver); three
+// Newton steps on G itself (ratio derivatives from the splines) finish it.
+// The ratios move by about 1 % over the whole table, so u1 is within ~1e-5 of
+// the root and the Newton steps reach the rounding level.
+#pragma once
+
+#include "kernels_fp64.h"
+
+namespace pino {
+
+struct LptState {
+    double d1, v1, d2, v2, d3a, v3a, d3b, v3b;
+};
+
+__device__ __forceinline__ LptState lpt_rhs(const LptState& y, double x, double om)
+{
+    const double a3 = exp(-3.0 * x);
+    const double oma = om * a3 / (om * a3 + 1.0 - om);
+    const double p = 2.0 - 1.5 * oma;
+    LptState d;
+    d.d1 = y.v1;
+    d.v1 = -p * y.v1 + 1.5 * oma * y.d1;
+    d.d2 = y.v2;
+    d.v2 = -p * y.v2 + 1.5 * oma * y.d2 - 1.5 * oma * y.d1 * y.d1;
+    d.d3a = y.v3a;
+    d.v3a = -p * y.v3a + 1.5 * oma * y.d3a - 3.0 * oma * y.d1 * y.d1 * y.d1;
+    d.d3b = y.v3b;
+    d.v3b = -p * y.v3b + 1.5 * oma * y.d3b - 3.0 * oma * y.d1 * (y.d2 - y.d1 * y.d1);
+    return d;
+}
+
+__device__ __forceinline__ LptState lpt_axpy(const LptState& y, double h, const LptState& k)
+{
+    return LptState{y.d1 + h * k.d1,   y.v1 + h * k.v1,   y.d2 + h * k.d2,   y.v2 + h * k.v2,
+                    y.d3a + h * k.d3a, y.v3a + h * k.v3a, y.d3b + h * k.d3b, y.v3b + h * k.v3b};
+}
+
+__device__ __forceinline__ LptState lpt_rk4(const LptState& y, double x, double h, double om)
+{
+    const LptState k1 = lpt_rhs(y, x, om);
+    const LptState k2 = lpt_rhs(lpt_axpy(y, 0.5 * h, k1), x + 0.5 * h, om);
+    const LptState k3 = lpt_rhs(lpt_axpy(y, 0.5 * h, k2), x + 0.5 * h, om);
+    const LptState k4 = lpt_rhs(lpt_axpy(y, h, k3), x + h, om);
+    const double w = h * (1.0 / 6.0);
+    LptState o;
+    o.d1 = y.d1 + w * (k1.d1 + 2.0 * (k2.d1 + k3.d1) + k4.d1);
+    o.v1 = y.v1 + w * (k1.v1 + 2.0 * (k2.v1 + k3.v1) + k4.v1);
+    o.d2 = y.d2 + w * (k1.d2 + 2.0 * (k2.d2 + k3.d2) + k4.d2);
+    o.v2 = y.v2 + w * (k1.v2 + 2.0 * (k2.v2 + k3.v2) + k4.v2);
+    o.d3a = y.d3a + w * (k1.d3a + 2.0 * (k2.d3a + k3.d3a) + k4.d3a);
+    o.v3a = y.v3a + w * (k1.v3a + 2.0 * (k2.v3a + k3.v3a) + k4.v3a);
+    o.d3b = y.d3b + w * (k1.d3b + 2.0 * (k2.d3b + k3.d3b) + k4.d3b);
+    o.v3b = y.v3b + w * (k1.v3b + 2.0 * (k2.v3b + k3.v3b) + k4.v3b);
+    return o;
+}
+
+// One thread per cosmology c: growth knots at growth + c * 3 nk_max ([D | a |
+// M], a from offset nk[c]), ratios written to kap + c * 6 nk_max as
+// [k2 | k3a | k3b] (nk[c] each; the spline second derivatives follow).
+constexpr double kLptStep = 1e-3;
+
+__global__ void __launch_bounds__(64) k_lpt_growth(const double* __restrict__ growth, const int* __restrict__ nk,
+                                                  const double* __restrict__ omega, int n_cosmo, int nk_max,
+                                                  double* __restrict__ kap)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cosmo)
+        return;
+    const int n = nk[c];
+    const double* ak = growth + (size_t)c * 3 * nk_max + n;
+    double* out = kap + (size_t)c * 6 * nk_max;
+    const double om = omega[c];
+    const double as = 1e-7 * ak[0];
+    LptState y{as, as, -(3.0 / 7.0) * as * as, -(6.0 / 7.0) * as * as, -(1.0 / 3.0) * as * as * as,
+               -as * as * as, (10.0 / 21.0) * as * as * as, (10.0 / 7.0) * as * as * as};
+    double x = log(as);
+    for (int k = 0; k < n; ++k) {
+        const double xe = log(ak[k]);
+        const int m = max(1, (int)ceil((xe - x) / kLptStep));
+        const double h = (xe - x) / m;
+        const double x0 = x;
+        for (int j = 0; j < m; ++j)
+            y = lpt_rk4(y, x0 + h * j, h, om);
+        x = xe;
+        out[k] = y.d2 / (-(3.0 / 7.0) * y.d1 * y.d1);
+        out[nk_max + k] = y.d3a / (-(1.0 / 3.0) * y.d1 * y.d1 * y.d1);
+        out[2 * nk_max + k] = y.d3b / ((10.0 / 21.0) * y.d1 * y.d1 * y.d1);
+    }
+}
+
+// LDS: the growth knots and index of stage_growth, then the six ratio rows
+// [k2 | k3a | k3b | m2 | m3a | m3b] of the item's cosmology (nk each).
+__host__ __device__ inline size_t lcdm_lds_bytes(int nk, int nb)
+{
+    return growth_lds_bytes(nk, nb) + 6 * (size_t)nk * sizeof(double);
+}
+
+// The three ratios and their derivatives in D at D (spline pieces of interval
+// i of the growth knots; constant outside [D_0, D_{n-1}]).
+struct Kappa {
+    double k2, k3a, k3b, d2, d3a, d3b;
+};
+
+__device__ __forceinline__ Kappa kappa_at(const double* D, const double* kap, int nk, double Dq,
+                                          const GrowthIndex& gi)
+{
+    Kappa r;
+    const double* K2 = kap;
+    const double* K3a = kap + nk;
+    const double* K3b = kap + 2 * nk;
+    const double* M2 = kap + 3 * nk;
+    const double* M3a = kap + 4 * nk;
+    const double* M3b = kap + 5 * nk;
+    if (!(Dq > D[0]) || !(Dq < D[nk - 1])) {
+        const int e = Dq > D[0] ? nk - 1 : 0;
+        r.k2 = K2[e];
+        r.k3a = K3a[e];
+        r.k3b = K3b[e];
+        r.d2 = r.d3a = r.d3b = 0.0;
+        return r;
+    }
+    const int i = gi.ok ? locate_indexed(D, nk, Dq, gi) : locate(D, nk, Dq);
+    const double h = D[i + 1] - D[i];
+    const double ih = rcp2(h);
+    const double t = (Dq - D[i]) * ih;
+    const double w = 1.0 - t;
+    const double h6 = h * h * (1.0 / 6.0);
+    const double cw = w * w * w - w, ct = t * t * t - t;
+    const double dw = (h * (1.0 / 6.0)) * (1.0 - 3.0 * w * w), dt = (h * (1.0 / 6.0)) * (3.0 * t * t - 1.0);
+    r.k2 = w * K2[i] + t * K2[i + 1] + h6 * (cw * M2[i] + ct * M2[i + 1]);
+    r.k3a = w * K3a[i] + t * K3a[i + 1] + h6 * (cw * M3a[i] + ct * M3a[i + 1]);
+    r.k3b = w * K3b[i] + t * K3b[i + 1] + h6 * (cw * M3b[i] + ct * M3b[i + 1]);
+    r.d2 = (K2[i + 1] - K2[i]) * ih + dw * M2[i] + dt * M2[i + 1];
+    r.d3a = (K3a[i + 1] - K3a[i]) * ih + dw * M3a[i] + dt * M3a[i + 1];
+    r.d3b = (K3b[i + 1] - K3b[i]) * ih + dw * M3b[i] + dt * M3b[i + 1];
+    return r;
+}
+
+// w = 1/u of the first positive root of the cubic k (the Classic solver),
+// <= 0 without one
+__device__ __forceinline__ double cubic_top_w(const CubicU& k)
+{
+    double w;
+    if (!top_root_w(k, w)) {
+        const Bracket br = lpt_bracket(k);
+        w = br.root ? rcp2(lpt_solve_u(k, br)) : 0.0;
+    }
+    return w;
+}
+
+constexpr int kLcdmNewton = 3;
+
+// F = 1/D_c with the LCDM coefficients, 0 without collapse.  g: the growth
+// knots [D | a | M] (D used), kap: the ratio rows (LDS).
+__device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const double* g, const double* kap, int nk,
+                                         const GrowthIndex& gi)
+{
+    if (!(l1 > 0.0))
+        return 0.0;
+    const double il1 = rcp2(l1);
+    const double sg = s * il1;
+    const double pi = pp * (il1 * il1);
+    const double b = (-3.0 / 14.0) * sg;
+    const double ca = pi * (1.0 / 9.0);
+    const double cb = -(sg * (1.0 / 56.0) + pi * (2.0 / 56.0) + (17.0 / 168.0) * (sg * sg));
+    // first root of the Einstein-de Sitter cubic; without one, of the cubic
+    // with the ratios of the last knot (the largest)
+    double w = cubic_top_w(CubicU{b, ca + cb});
+    double De = w > 0.0 ? rcp2(l1 * w) : g[nk - 1];
+    Kappa k = kappa_at(g, kap, nk, De, gi);
+    w = cubic_top_w(CubicU{k.k2 * b, k.k3a * ca + k.k3b * cb});
+    if (!(w > 0.0))
+        return 0.0;
+    double u = rcp2(w);
+    for (int it = 0; it < kLcdmNewton; ++it) {
+        k = kappa_at(g, kap, nk, u * il1, gi);
+        const double P = k.k2 * b;
+        const double Q = k.k3a * ca + k.k3b * cb;
+        const double G = 1.0 + u * (-1.0 + u * (P + Q * u));
+        const double dG = -1.0 + u * (2.0 * P + 3.0 * Q * u) + (u * u) * il1 * (k.d2 * b + u * (k.d3a * ca + k.d3b * cb));
+        u -= G * rcp2(dG);
+    }
+    return u > 0.0 ? l1 * rcp2(u) : 0.0;
+}
+
+// Per-radius kernel of the LCDM method: one particle per lane over a
+// grid-stride loop, the next element's loads issued before the current
+// element's arithmetic, the update of update_max.
+__global__ void __launch_bounds__(256) k_classic_lcdm(ItemArgs a, const double* __restrict__ kap_all)
+{
+    extern __shared__ double lds[];
+    const GrowthIndex gi = stage_growth(lds, a);
+    double* kap = lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
+    stage(kap, kap_all, 6 * a.nk);
+    __syncthreads();
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    Hess64 hn{};
+    double fn = 0.0;
+    if (i < n) {
+        hn = load_h64(a, i);
+        fn = a.reset ? 0.0 : *elem(a.Fmax, i);
+    }
+    for (; i < n; i += stride) {
+        const Hess64 h = hn;
+        const double fm = fn;
+        const uint32_t next = i + stride;
+        if (next < n) {
+            hn = load_h64(a, next);
+            fn = a.reset ? 0.0 : *elem(a.Fmax, next);
+        }
+        double l1, s, pp;
+        eig_top(h, l1, s, pp);
+        const double F = lcdm_F(l1, s, pp, lds, kap, a.nk, gi);
+        update_max(a, lds, gi, i, F, fm);
+    }
+}
+
+}  // namespace pino

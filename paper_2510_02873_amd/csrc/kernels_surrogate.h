@@ -13,20 +13,39 @@ __device__ __forceinline__ Hess64 load_h(const ItemArgs& a, uint32_t i, bool f32
     return f32 ? widen(load_h32(a, i)) : load_h64(a, i);
 }
 
-// Per particle: FP64 eigenvalues of the FP32 Hessian, the BF16 network's
-// prediction and the FP64 certificate.  Certified and gated particles (F from
-// the certificate, or 0) update the maxima in the main loop.  The others are
-// deferred: each block appends their indices to its own segment of `queue`
-// (queue + blockIdx.x * seg, seg >= the particles a block visits) through an
-// LDS counter, one LDS atomic per wave, and carries their maxima over
-// unchanged.  After its loop the block finishes its own deferred particles
-// with the full FP64 Classic solve on the same widened FP32 Hessian and
-// updates their maxima against what the loop stored (at FINALIZE their
-// a(D_c) is rewritten where F wins), so the full solve costs only the
-// particles that need it, with no second launch.  The main loop is
-// wave-uniform (all 64 lanes run the network together); lanes past the end
-// compute on zeros and store nothing.  counters: certified, consulted but not
-// certified, not consulted (wave totals added once per wave at the end).
+// LDS layout of k_surrogate: the growth knots and index (stage_growth), then
+// the weight fragments at the next 16-byte boundary (they are copied and read
+// as 16-byte vectors).
+__host__ __device__ inline size_t net_lds_offset(int nk, int nb)
+{
+    return (growth_lds_bytes(nk, nb) + 15) / 16 * 16;
+}
+
+__host__ __device__ inline size_t surrogate_lds_bytes(int nk, int nb)
+{
+    return net_lds_offset(nk, nb) + sizeof(NetFrags);
+}
+
+// Per particle: FP64 eigenvalues of the FP64 Hessian, the BF16 network's
+// prediction and the FP64 certificate.  The certificate brackets the first
+// root of the particle's own cubic (built from its FP64 Hessian), so an
+// accepted value is within rtol of the full solve on the same input.
+// Certified and gated particles (F from the certificate, or 0) update the
+// maxima in the main loop.  The others are deferred: each block appends their
+// indices to its own segment of `queue` (queue + blockIdx.x * seg, seg >= the
+// particles a block visits) through an LDS counter, one LDS atomic per wave,
+// and carries their maxima over unchanged.  After its loop the block finishes
+// its own deferred particles with the full FP64 Classic solve and updates
+// their maxima against what the loop stored (at FINALIZE their a(D_c) is
+// rewritten where F wins), so the full solve costs only the particles that
+// need it, with no second launch.  The main loop is wave-uniform (all 64
+// lanes run the network together); lanes past the end compute on zeros and
+// store nothing.  counters: certified; consulted but not certified (full
+// solve); not consulted with l1 > 0 (full solve); l1 <= 0 (F = 0, no solve).
+// The waves of a block sum their counts in LDS and one lane adds the block's
+// totals to the block's own four slots (counters + 4 blockIdx.x): a
+// device-wide atomic on one shared address from every wave serialises at the
+// coherence point and cost a few hundred microseconds per launch.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_surrogate(ItemArgs a, const NetFrags* __restrict__ net, double sigma,
                                                   double omega_m, double rtol,
                                                   unsigned long long* __restrict__ counters,
@@ -34,8 +53,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 {
     extern __shared__ double lds[];
     __shared__ int fill;
+    __shared__ unsigned long long bcount[4];
     const GrowthIndex gi = stage_growth(lds, a);
-    NetFrags* N = reinterpret_cast<NetFrags*>(lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double));
+    NetFrags* N = reinterpret_cast<NetFrags*>(reinterpret_cast<char*>(lds) + net_lds_offset(a.nk, a.gi.nb));
     {
         const int4* src = reinterpret_cast<const int4*>(net);
         int4* dst = reinterpret_cast<int4*>(N);
@@ -44,19 +64,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
     if (threadIdx.x == 0)
         fill = 0;
+    if (threadIdx.x < 4)
+        bcount[threadIdx.x] = 0;
     __syncthreads();
     int32_t* myq = queue + (int64_t)blockIdx.x * seg;
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    unsigned long long ncert = 0, nfall = 0, ngate = 0;
+    unsigned long long ncert = 0, nfall = 0, ngsolve = 0, ngzero = 0;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < a.n; base += stride) {
         const bool valid = base + lane < a.n;
         const uint32_t i = (uint32_t)(base + lane);
         Hess64 h{};
         double fm = 0.0;
         if (valid) {
-            h = widen(load_h32(a, i));
+            h = load_h64(a, i);
             fm = a.reset ? 0.0 : *elem(a.Fmax, i);
         }
         double l1, s, pp;
@@ -89,23 +111,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         }
         ncert += __popcll(__ballot(valid && cert));
         nfall += __popcll(__ballot(consult && !cert));
-        ngate += __popcll(__ballot(valid && !consult));
+        ngsolve += __popcll(__ballot(valid && !consult && l1 > 0.0));
+        ngzero += __popcll(__ballot(valid && !(l1 > 0.0)));
         if (valid)
             update_max(a, lds, gi, i, F, fm);
     }
-    if (lane == 0 && counters) {
-        atomicAdd(counters + 0, ncert);
-        atomicAdd(counters + 1, nfall);
-        atomicAdd(counters + 2, ngate);
+    if (lane == 0) {
+        atomicAdd(&bcount[0], ncert);
+        atomicAdd(&bcount[1], nfall);
+        atomicAdd(&bcount[2], ngsolve);
+        atomicAdd(&bcount[3], ngzero);
     }
     // the block's queue entries and the maxima its loop stored are visible
     // to the whole block after the barrier
     __syncthreads();
+    if (threadIdx.x < 4 && counters)
+        atomicAdd(counters + 4 * (int64_t)blockIdx.x + threadIdx.x, bcount[threadIdx.x]);
     const int count = fill;
     for (int qi = threadIdx.x; qi < count; qi += blockDim.x) {
         const uint32_t i = (uint32_t)myq[qi];
         double l1, s, pp;
-        eig_top(widen(load_h32(a, i)), l1, s, pp);
+        eig_top(load_h64(a, i), l1, s, pp);
         const double F = classic_F(l1, s, pp);
         if (F > *elem(a.Fmax, i)) {
             *elem(a.Fmax, i) = F;

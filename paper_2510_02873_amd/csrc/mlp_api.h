@@ -111,6 +111,24 @@ constexpr int64_t kQueueChunk = int64_t(1) << 24;
 constexpr int64_t kQueueBlocks = 4096;
 constexpr int64_t kQueueCap = kQueueChunk + 256 * kQueueBlocks;
 
+// Dynamic LDS of k_surrogate for the largest growth table of a context: the
+// knots, their index and the 25 KB of weight fragments pass the default
+// 64 KiB limit for tables of about 1000 knots or more, so the kernel's limit
+// is raised on the context's device (CDNA4 gives a workgroup up to 160 KiB).
+pino_status surrogate_lds_limit(pino_ctx* c, size_t need)
+{
+    if (need <= 65536)
+        return PINO_OK;
+    const hipError_t e = hipFuncSetAttribute((const void*)pino::k_surrogate,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+    if (e != hipSuccess) {
+        c->broken = true;
+        c->err = std::string("surrogate LDS limit: ") + hipGetErrorString(e);
+        return PINO_ERR_HIP;
+    }
+    return PINO_OK;
+}
+
 pino_status mlp_upload(pino_ctx* c, const void* blob, int64_t)
 {
     std::vector<float> P(pino::kNParam);
@@ -120,9 +138,9 @@ pino_status mlp_upload(pino_ctx* c, const void* blob, int64_t)
     if (e == hipSuccess)
         e = hipMemcpy(c->d_mlp, &f, sizeof(f), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMalloc((void**)&c->d_counters, 4 * sizeof(int64_t));
+        e = hipMalloc((void**)&c->d_counters, 4 * kQueueBlocks * sizeof(int64_t));
     if (e == hipSuccess)
-        e = hipMemset(c->d_counters, 0, 4 * sizeof(int64_t));
+        e = hipMemset(c->d_counters, 0, 4 * kQueueBlocks * sizeof(int64_t));
     if (e == hipSuccess) {
         c->queue_cap = kQueueCap;
         e = hipMalloc((void**)&c->d_queue, (size_t)c->queue_cap * sizeof(int32_t));
@@ -147,13 +165,12 @@ inline pino_status launch_fail(pino_ctx* c, const char* what)
 }
 
 // One item in chunks of at most kQueueChunk particles (queue indices are
-// chunk-relative int32): per chunk, the surrogate pass, then the full solve of
-// the deferred particles, block b of the second kernel taking the queue
-// segment that block b of the first filled.
+// chunk-relative int32): per chunk one k_surrogate launch, whose blocks each
+// finish the particles they deferred to the full solve.
 pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemArgs& a0, uint32_t, hipStream_t st,
                              int, int block)
 {
-    const size_t lds = pino::growth_lds_bytes(a0.nk, a0.gi.nb) + sizeof(pino::NetFrags);
+    const size_t lds = pino::surrogate_lds_bytes(a0.nk, a0.gi.nb);
     auto* cnt = reinterpret_cast<unsigned long long*>(c->d_counters);
     const auto* net = static_cast<const pino::NetFrags*>(c->d_mlp);
     const int64_t cap_blocks = std::min<int64_t>((int64_t)c->cu_count * c->blocks_per_cu, kQueueBlocks);
@@ -161,7 +178,7 @@ pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemA
         pino::ItemArgs a = a0;
         a.n = std::min<int64_t>(kQueueChunk, a0.n - start);
         for (int k = 0; k < 6; ++k)
-            a.h[k] = reinterpret_cast<const double*>(reinterpret_cast<const char*>(a0.h[k]) + start * sizeof(float));
+            a.h[k] = a0.h[k] + start;
         a.Fmax = a0.Fmax + start;
         a.Rmax = a0.Rmax + start;
         a.acoll = a0.acoll ? a0.acoll + start : nullptr;

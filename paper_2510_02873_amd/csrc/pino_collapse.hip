@@ -12,6 +12,7 @@
 #include "../../include/pino_collapse.h"
 #include "ctx.h"
 #include "kernels_fp64.h"
+#include "kernels_lcdm.h"
 #include "launch_ext.h"
 #include "mlp_api.h"
 
@@ -46,7 +47,7 @@ bool validate_config(const pino_config* cfg, std::string& why)
         why = "abi_version " + std::to_string(cfg->abi_version) + " != " + std::to_string(PINO_ABI_VERSION);
         return false;
     }
-    if (cfg->method != PINO_CLASSIC && cfg->method != PINO_TABULATED) {
+    if (cfg->method != PINO_CLASSIC && cfg->method != PINO_TABULATED && cfg->method != PINO_CLASSIC_LCDM) {
         why = "unknown method";
         return false;
     }
@@ -70,6 +71,10 @@ bool validate_config(const pino_config* cfg, std::string& why)
         }
         if (!std::isfinite(g.omega_m)) {
             why = "growth table " + std::to_string(c) + ": omega_m must be finite";
+            return false;
+        }
+        if (cfg->method == PINO_CLASSIC_LCDM && !(g.omega_m > 0.0 && g.omega_m <= 1.0)) {
+            why = "growth table " + std::to_string(c) + ": the LCDM method needs 0 < omega_m <= 1";
             return false;
         }
         if (!strictly_increasing(g.a, g.n) || !strictly_increasing(g.D, g.n)) {
@@ -179,8 +184,11 @@ pino_status hip_fail(pino_ctx* ctx, hipError_t e, const char* what)
     } while (0)
 
 // LDS per workgroup: growth knots + index bins, plus the table knots of the
-// Tabulated method; kept within 64 KiB
+// Tabulated method; kept within 64 KiB.  The surrogate kernel also holds the
+// network's weight fragments and may use up to the 160 KiB a CDNA4
+// workgroup can address (its limit is raised at init).
 constexpr size_t kLdsBudget = 65536;
+constexpr size_t kLdsMax = 163840;
 
 int index_bins(int nk)
 {
@@ -192,6 +200,22 @@ bool lds_fits(const pino_config* cfg, std::string& why)
     int nk_max = 0;
     for (int k = 0; k < cfg->n_cosmo; ++k)
         nk_max = std::max(nk_max, (int)cfg->growth[k].n);
+    if (cfg->method == PINO_CLASSIC_LCDM) {
+        const size_t need = lcdm_lds_bytes(nk_max, index_bins(nk_max));
+        if (need > kLdsMax) {
+            why = "growth knots and LCDM coefficients need " + std::to_string(need) + " bytes of LDS, more than 160 KiB";
+            return false;
+        }
+        return true;
+    }
+    if (cfg->precision == PINO_SURROGATE) {
+        const size_t need = surrogate_lds_bytes(nk_max, index_bins(nk_max));
+        if (need > kLdsMax) {
+            why = "growth knots and network weights need " + std::to_string(need) + " bytes of LDS, more than 160 KiB";
+            return false;
+        }
+        return true;
+    }
     size_t need = growth_lds_bytes(nk_max, index_bins(nk_max));
     if (cfg->method == PINO_TABULATED)
         need += sizeof(double) * ((size_t)cfg->table->nx + cfg->table->ny + cfg->table->nd);
@@ -244,7 +268,7 @@ void free_all(pino_ctx* c)
     if (!c)
         return;
     void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tidx, c->d_tcoef, c->d_tab, c->d_tab32,
-                    c->d_tmp, c->d_mlp, c->d_counters, c->d_queue};
+                    c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_kap};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -257,6 +281,8 @@ void free_all(pino_ctx* c)
     c->d_mlp = nullptr;
     c->d_counters = nullptr;
     c->d_queue = nullptr;
+    c->d_kap = nullptr;
+    c->order.destroy();
 }
 
 pino_status init_impl(const pino_config* cfg, pino_ctx* c)
@@ -291,7 +317,9 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
     PINO_HIP(c, hipMalloc((void**)&c->d_growth, host.size() * sizeof(double)));
     PINO_HIP(c, hipMemcpy(c->d_growth, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
 
-    int64_t tmp_doubles = (int64_t)cfg->n_cosmo * nk_max;
+    // spline scratch: one row per growth table, three per table for the
+    // LCDM coefficients
+    int64_t tmp_doubles = (int64_t)cfg->n_cosmo * nk_max * (cfg->method == PINO_CLASSIC_LCDM ? 3 : 1);
     if (cfg->method == PINO_TABULATED) {
         const pino_table_knots* t = cfg->table;
         c->nx = t->nx;
@@ -340,6 +368,43 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
         PINO_HIP(c, hipGetLastError());
     }
 
+    // LCDM time coefficients at the growth knots and their splines in D
+    if (cfg->method == PINO_CLASSIC_LCDM) {
+        PINO_HIP(c, hipMalloc((void**)&c->d_kap, (size_t)cfg->n_cosmo * 6 * nk_max * sizeof(double)));
+        int* d_nk = nullptr;
+        double* d_om = nullptr;
+        hipError_t e = hipMalloc((void**)&d_nk, cfg->n_cosmo * sizeof(int));
+        if (e == hipSuccess)
+            e = hipMalloc((void**)&d_om, cfg->n_cosmo * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMemcpy(d_nk, c->nk.data(), cfg->n_cosmo * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(d_om, c->omega.data(), cfg->n_cosmo * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_lpt_growth, dim3((cfg->n_cosmo + 63) / 64), dim3(64), 0, 0, c->d_growth, d_nk, d_om,
+                               cfg->n_cosmo, nk_max, c->d_kap);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipDeviceSynchronize();
+        if (d_nk)
+            (void)hipFree(d_nk);
+        if (d_om)
+            (void)hipFree(d_om);
+        PINO_HIP(c, e);
+        for (int k = 0; k < cfg->n_cosmo; ++k) {
+            double* kp = c->d_kap + (size_t)k * 6 * nk_max;
+            hipLaunchKernelGGL(k_spline_build, dim3(1), dim3(64), 0, 0, c->d_growth + (size_t)k * 3 * nk_max,
+                               c->nk[k], kp, (int64_t)nk_max, 1, kp + 3 * nk_max, (int64_t)nk_max, 1,
+                               c->d_tmp + (size_t)k * 3 * nk_max, 3);
+            PINO_HIP(c, hipGetLastError());
+        }
+        const size_t need = lcdm_lds_bytes(nk_max, index_bins(nk_max));
+        if (need > kLdsBudget)
+            PINO_HIP(c, hipFuncSetAttribute((const void*)k_classic_lcdm, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)need));
+    }
+
     // FP32 copy of the growth knots for the mixed-precision path
     if (cfg->precision == PINO_MIXED) {
         const int64_t count = (int64_t)cfg->n_cosmo * 3 * nk_max;
@@ -385,10 +450,15 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
 
     if (cfg->precision == PINO_SURROGATE) {
         c->certify_rtol = cfg->certify_rtol > 0.0 ? cfg->certify_rtol : 5e-7;
-        const pino_status st = mlp_upload(c, cfg->mlp, cfg->mlp_bytes);
+        pino_status st = mlp_upload(c, cfg->mlp, cfg->mlp_bytes);
+        if (st == PINO_OK)
+            st = surrogate_lds_limit(c, surrogate_lds_bytes(nk_max, c->nb_max));
         if (st != PINO_OK)
             return st;
     }
+    // evals of a context with per-context scratch are ordered across streams
+    if (cfg->method == PINO_TABULATED || cfg->precision == PINO_SURROGATE)
+        PINO_HIP(c, c->order.create());
     PINO_HIP(c, hipDeviceSynchronize());
     return PINO_OK;
 }
@@ -455,7 +525,7 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
     }
 
     // the kernels index with 32-bit byte offsets: chunks of at most kChunk
-    const size_t esize = c->precision == PINO_FP64 ? sizeof(double) : sizeof(float);
+    const size_t esize = c->precision == PINO_MIXED ? sizeof(float) : sizeof(double);
     const ItemArgs a0 = a;
     for (int64_t start = 0; start < a0.n; start += kChunk) {
         a.n = std::min<int64_t>(kChunk, a0.n - start);
@@ -472,7 +542,10 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
             for (int k = 0; k < 6; ++k)
                 al = al && aligned(a.h[k], 16);
             const int gp = grid_for(c, (a.n + 1) / 2, block);
-            if (c->method == PINO_CLASSIC) {
+            if (c->method == PINO_CLASSIC_LCDM) {
+                hipLaunchKernelGGL(k_classic_lcdm, dim3(g), dim3(block), lcdm_lds_bytes(a.nk, a.gi.nb), st, a,
+                                   c->d_kap + (size_t)it.cosmo * 6 * c->nk_max);
+            } else if (c->method == PINO_CLASSIC) {
                 if (al) {
                     hipLaunchKernelGGL(k_classic_f64, dim3(gp), dim3(block), lds, st, a);
                 } else {
@@ -517,6 +590,10 @@ pino_status pino_collapse_init(const pino_config* cfg, pino_ctx** out)
         g_init_error = why;
         return PINO_ERR_UNSUPPORTED;
     }
+    if (cfg->method == PINO_CLASSIC_LCDM && cfg->precision != PINO_FP64) {
+        g_init_error = "the LCDM method runs in FP64 only";
+        return PINO_ERR_UNSUPPORTED;
+    }
     pino_ctx* c = new (std::nothrow) pino_ctx();
     if (!c) {
         g_init_error = "host allocation failed";
@@ -558,11 +635,13 @@ pino_status pino_collapse_eval(pino_ctx* ctx, const pino_item* items, int32_t n_
     }
     PINO_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    PINO_HIP(ctx, ctx->order.enter(st));
     for (int32_t k = 0; k < n_items; ++k) {
         const pino_status s = launch_item(ctx, items[k], flags, st);
         if (s != PINO_OK)
             return s;
     }
+    PINO_HIP(ctx, ctx->order.leave(st));
     if (flags & PINO_EVAL_SYNC)
         PINO_HIP(ctx, hipStreamSynchronize(st));
     return PINO_OK;
@@ -587,6 +666,28 @@ const char* pino_collapse_last_error(const pino_ctx* ctx)
     if (!ctx)
         return g_init_error.c_str();
     return ctx->err.c_str();
+}
+
+pino_status pino_collapse_lpt_coefficients(pino_ctx* ctx, int32_t cosmo, double* k2, double* k3a, double* k3b)
+{
+    if (!ctx) {
+        g_init_error = "ctx is NULL";
+        return PINO_ERR_ARG;
+    }
+    if (ctx->broken)
+        return PINO_ERR_STATE;
+    if (ctx->method != PINO_CLASSIC_LCDM || cosmo < 0 || cosmo >= ctx->n_cosmo || !k2 || !k3a || !k3b) {
+        ctx->err = "need a PINO_CLASSIC_LCDM context, a valid cosmology index and non-NULL outputs";
+        return PINO_ERR_ARG;
+    }
+    PINO_HIP(ctx, hipSetDevice(ctx->device));
+    PINO_HIP(ctx, hipDeviceSynchronize());
+    const int n = ctx->nk[cosmo];
+    const double* src = ctx->d_kap + (size_t)cosmo * 6 * ctx->nk_max;
+    PINO_HIP(ctx, hipMemcpy(k2, src, n * sizeof(double), hipMemcpyDeviceToHost));
+    PINO_HIP(ctx, hipMemcpy(k3a, src + ctx->nk_max, n * sizeof(double), hipMemcpyDeviceToHost));
+    PINO_HIP(ctx, hipMemcpy(k3b, src + 2 * ctx->nk_max, n * sizeof(double), hipMemcpyDeviceToHost));
+    return PINO_OK;
 }
 
 }  // extern "C"
@@ -627,7 +728,7 @@ pino_status pino_collapse_features(pino_ctx* ctx, const pino_item* item, float* 
     for (int k = 0; k < 6; ++k)
         a.h[k] = static_cast<const double*>(it.h[k]);
     a.n = it.n;
-    const bool f32 = ctx->precision != PINO_FP64;
+    const bool f32 = ctx->precision == PINO_MIXED;
     hipLaunchKernelGGL(k_features, dim3((unsigned)((it.n + 255) / 256)), dim3(256), 0,
                        static_cast<hipStream_t>(hip_stream), a, f32, it.sigma_R, ctx->omega[it.cosmo], x, w);
     PINO_HIP(ctx, hipGetLastError());
@@ -656,8 +757,8 @@ pino_status pino_collapse_predict(pino_ctx* ctx, const float* x, float* y, int64
     return PINO_OK;
 }
 
-pino_status pino_collapse_surrogate_stats(pino_ctx* ctx, int64_t* certified, int64_t* fallback, int64_t* gated,
-                                          int32_t reset)
+pino_status pino_collapse_surrogate_stats(pino_ctx* ctx, int64_t* certified, int64_t* fallback,
+                                          int64_t* gated_solved, int64_t* gated_zero, int32_t reset)
 {
     if (!ctx) {
         g_init_error = "ctx is NULL";
@@ -671,16 +772,23 @@ pino_status pino_collapse_surrogate_stats(pino_ctx* ctx, int64_t* certified, int
     }
     PINO_HIP(ctx, hipSetDevice(ctx->device));
     PINO_HIP(ctx, hipDeviceSynchronize());
-    int64_t v[4];
-    PINO_HIP(ctx, hipMemcpy(v, ctx->d_counters, sizeof(v), hipMemcpyDeviceToHost));
+    // four counters per block slot of the surrogate kernel, summed here
+    std::vector<int64_t> slots(4 * (size_t)kQueueBlocks);
+    PINO_HIP(ctx, hipMemcpy(slots.data(), ctx->d_counters, slots.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    int64_t v[4] = {0, 0, 0, 0};
+    for (size_t b = 0; b < slots.size(); b += 4)
+        for (int k = 0; k < 4; ++k)
+            v[k] += slots[b + k];
     if (certified)
         *certified = v[0];
     if (fallback)
         *fallback = v[1];
-    if (gated)
-        *gated = v[2];
+    if (gated_solved)
+        *gated_solved = v[2];
+    if (gated_zero)
+        *gated_zero = v[3];
     if (reset)
-        PINO_HIP(ctx, hipMemset(ctx->d_counters, 0, sizeof(v)));
+        PINO_HIP(ctx, hipMemset(ctx->d_counters, 0, slots.size() * sizeof(int64_t)));
     return PINO_OK;
 }
 

@@ -27,7 +27,7 @@ class Collapse:
         return Fmax, Rmax, acoll
 
     def item(self, h, Fmax, Rmax, acoll=None, radius_index=0, cosmo=0, sigma_R=1.0, table_F=None):
-        want = torch.float64 if self.precision == _abi.PINO_FP64 else torch.float32
+        want = torch.float32 if self.precision == _abi.PINO_MIXED else torch.float64
         for c in range(6):
             t = h[c]
             if t.dtype != want or not t.is_contiguous() or t.device != self.device:

@@ -91,12 +91,15 @@ def mixed_bound(orc, slabs):
     given radii (FP64 arrays (6, n)): D_c is homogeneous of degree -1 in the
     eigenvalues and the FP32 eigenvalue is off by a few eps32 |H|_F, so
     |dD_c/D_c| <= 64 eps32 |H|_F / l1; the max over radii is taken, since
-    which radius wins is not known in advance."""
+    which radius wins is not known in advance.  Radii with l1 <= 0 give F = 0
+    on both sides (no collapse) and add nothing; a particle with l1 <= 0 at
+    every radius gets 0 (its F is 0 and never gated on D_c)."""
     b = None
     for h in slabs:
         lam, _ = orc.points(h)
         hn = np.sqrt(np.sum(h[:3] ** 2, axis=0) + 2 * np.sum(h[3:] ** 2, axis=0))
-        with np.errstate(divide="ignore"):
-            br = np.where(lam[:, 0] > 0, 64 * EPS32 * hn / np.maximum(lam[:, 0], 1e-300), np.inf)
+        pos = lam[:, 0] > 0
+        br = np.zeros_like(hn)
+        br[pos] = 64 * EPS32 * hn[pos] / lam[pos, 0]
         b = br if b is None else np.maximum(b, br)
     return b

@@ -167,8 +167,9 @@ def test_field_collapse_mixed_precision(pkg, orc):
 
 def test_field_collapse_equals_two_step_for_every_context(pkg, orc):
     """pino_field_collapse is the Hessian stage followed by pino_collapse_eval:
-    for Tabulated (FP64 and FP32 stages) and surrogate (FP32 stage) contexts
-    its results equal those of the two calls made separately, bit for bit."""
+    for Tabulated (FP64 and FP32 stages) and surrogate (FP64 stage) contexts
+    its results equal those of the two calls made separately, bit for bit.
+    (Surrogate contexts take FP64 Hessians, so their stage is the FP64 one.)"""
     from paper_2510_02873_amd import surrogate
     cfg = synth.config("C1")
     n, box, radii = cfg["n_side"], cfg["box"], cfg["radii"]
@@ -186,7 +187,7 @@ def test_field_collapse_equals_two_step_for_every_context(pkg, orc):
              ("tabulated mixed", dict(method=pkg.PINO_TABULATED, table_knots=knots, precision=pkg.PINO_MIXED),
               torch.float32),
              ("surrogate", dict(precision=pkg.PINO_SURROGATE, mlp_blob=surrogate.constant_blob(1.0)),
-              torch.float32)]
+              torch.float64)]
     last = len(radii) - 1
     with pkg.Field(n, box) as f:
         for name, kw, dt in cases:

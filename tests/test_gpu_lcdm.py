@@ -1,0 +1,130 @@
+"""GPU parity of the Classic method with flat-LCDM time coefficients
+(PINO_CLASSIC_LCDM) against the oracle, through the C ABI.
+
+The library integrates the growth ratios of the LPT terms on the device at
+init (RK4 of the perturbation ODEs); the oracle computes them by a
+Green's-function quadrature.  Gates: the ratios at the knots within 1e-9;
+D_c = 1/Fmax and a_coll within 1e-9 relative, radius index exact except at
+near-ties and where the oracle's root is nearly tangent (|dG/dln D| < 1e-6,
+reported); Omega_m = 1 reproduces the Einstein-de Sitter Classic path."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests._helpers import c1_inputs, compare, near_tie_mask, run_gpu_radii
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2510_02873_amd as P
+    return P
+
+
+@pytest.mark.parametrize("om,nk", [(0.3, 512), (0.27, 300), (1.0, 512), (0.35, 2048)])
+def test_lpt_coefficients_vs_oracle(pkg, orc, om, nk):
+    from paper_2510_02873_amd import _abi
+    a, D = synth.growth_table(om, nk)
+    with pkg.Collapse([(a, D, om)], method=pkg.PINO_CLASSIC_LCDM) as col:
+        got = _abi.pino_collapse_lpt_coefficients(col.ctx, 0, nk)
+    ref = orc.lpt_growth(om, a)
+    worst = max(float(np.max(np.abs(g - r))) for g, r in zip(got, ref))
+    print(f"Omega_m={om} nk={nk}: LCDM ratios at a=1 {[float(g[-1]) for g in got]}, max |GPU - oracle| "
+          f"{worst:.2e}", flush=True)
+    assert worst <= 1e-9
+
+
+def _lcdm_ref(orc, slabs, a, D, om):
+    g = orc.Growth(a, D, om)
+    host = [h.cpu().numpy() if torch.is_tensor(h) else np.asarray(h) for h in slabs]
+    ref = orc.collapse(host, g, method=orc.CLASSIC_LCDM)
+    # per radius F, for near-ties of the radius index, and the tangency of
+    # the oracle's root at each particle's winning radius
+    per_r = []
+    for h in host:
+        n = h.shape[1]
+        Fr, Rr = np.zeros(n), np.full(n, -1, np.int32)
+        orc.update_radius(h, 0, g, Fr, Rr, None, reset=True, method=orc.CLASSIC_LCDM)
+        per_r.append(Fr)
+    ties = near_tie_mask(per_r)
+    F, R, _ = ref
+    tang = np.zeros(F.size, dtype=bool)
+    for i in np.nonzero(F > 0)[0]:
+        lam = orc.eig3(host[R[i]][:, i])
+        Dc = 1.0 / F[i]
+        _, dG = orc.g_lcdm(lam, g, Dc)
+        tang[i] = abs(dG) * Dc < 1e-6
+    return ref, ties | tang, int(tang.sum())
+
+
+def test_lcdm_c1_vs_oracle(pkg, orc):
+    cfg, slabs, a, D = c1_inputs()
+    om = cfg["cosmo"].omega_m
+    ref, skip, n_tang = _lcdm_ref(orc, slabs, a, D, om)
+    with pkg.Collapse([(a, D, om)], method=pkg.PINO_CLASSIC_LCDM) as col:
+        got = run_gpu_radii(col, [h.cuda() for h in slabs])
+    st = compare(ref, got, tie_mask=skip, label="C1 LCDM")
+    with pkg.Collapse([(a, D, om)]) as col:
+        eds = run_gpu_radii(col, [h.cuda() for h in slabs])
+    big = (ref[0] > 1e-6) & (eds[0] > 0)
+    shift = np.abs(ref[0][big] / eds[0][big] - 1)
+    print(f"C1 LCDM vs oracle {st}; nearly tangent roots {n_tang}; F shift from the EdS coefficients: "
+          f"median {np.median(shift):.2e} max {shift.max():.2e}", flush=True)
+    assert np.median(shift) > 1e-5   # the coefficients do change the result
+
+
+def test_lcdm_eds_equals_classic(pkg, orc):
+    cfg, slabs, _, _ = c1_inputs()
+    a, D = synth.growth_table(1.0)
+    dev = [h.cuda() for h in slabs]
+    with pkg.Collapse([(a, D, 1.0)], method=pkg.PINO_CLASSIC_LCDM) as col:
+        F1, R1, A1 = run_gpu_radii(col, dev)
+    with pkg.Collapse([(a, D, 1.0)]) as col:
+        F0, R0, A0 = run_gpu_radii(col, dev)
+    big = F0 > 1e-6
+    rel = np.abs(F1[big] / F0[big] - 1)
+    print(f"Omega_m = 1: LCDM vs Classic max rel {rel.max():.2e}", flush=True)
+    assert np.array_equal(F1 > 0, F0 > 0) and rel.max() <= 1e-9
+    assert np.array_equal(R1, R0)
+
+
+def test_lcdm_special_and_ragged(pkg, orc):
+    """Diagonal, spherical, planar, repeated and zero spectra, NaN input, and
+    item sizes that leave partial waves."""
+    a, D = synth.growth_table(0.3)
+    rows = []
+    for lam in [(1, 1, 1), (2, 0, 0), (1, 1, 0), (3, 3, -1), (0.5, -0.5, -0.5), (40.0, 3.0, -2.0), (-1, -2, -3),
+                (0, 0, 0), (1e-3, 0, 0), (0.05, 0.01, -0.02), (8.0, 7.9, 7.8)]:
+        rows.append([lam[0], lam[1], lam[2], 0, 0, 0])
+    rng = np.random.default_rng(8)
+    rows += list(rng.normal(size=(300, 6)) * rng.uniform(0.1, 3.0, size=(300, 1)))
+    H = np.ascontiguousarray(np.array(rows).T)
+    g = orc.Growth(a, D, 0.3)
+    for n in (1, 7, 64, 65, H.shape[1]):
+        h = np.ascontiguousarray(H[:, :n])
+        F = np.zeros(n)
+        R = np.full(n, -1, np.int32)
+        A = np.full(n, np.inf)
+        orc.update_radius(h, 0, g, F, R, A, reset=True, method=orc.CLASSIC_LCDM)
+        with pkg.Collapse([(a, D, 0.3)], method=pkg.PINO_CLASSIC_LCDM) as col:
+            got = run_gpu_radii(col, [torch.from_numpy(h).cuda()])
+        compare((F, R, A), got, label=f"LCDM special n={n}")
+    # NaN never updates the maximum
+    hn = np.full((6, 3), np.nan)
+    with pkg.Collapse([(a, D, 0.3)], method=pkg.PINO_CLASSIC_LCDM) as col:
+        Fg, Rg, _ = run_gpu_radii(col, [torch.from_numpy(hn).cuda()])
+    assert np.all(Fg == 0) and np.all(Rg == -1)
+
+
+def test_lcdm_unsupported_combinations(pkg):
+    a, D = synth.growth_table(0.3)
+    for kw in (dict(precision=pkg.PINO_MIXED),):
+        with pytest.raises(pkg.PinoError) as e:
+            pkg.Collapse([(a, D, 0.3)], method=pkg.PINO_CLASSIC_LCDM, **kw)
+        assert e.value.status == pkg.PINO_ERR_UNSUPPORTED
+    with pytest.raises(pkg.PinoError) as e:
+        pkg.Collapse([(a, D, 1.5)], method=pkg.PINO_CLASSIC_LCDM)
+    assert e.value.status == pkg.PINO_ERR_ARG

@@ -189,55 +189,183 @@ def test_predict_bf16_vs_fp64(P, trained):
     assert np.median(rel) < BF16_EPS / 2 and rel.max() < 8 * BF16_EPS
 
 
-def _run_surrogate(Pk, A, blob, slabs32, a, D, sigmas, rtol=0.0):
+def _run_surrogate(Pk, A, blob, slabs, a, D, sigmas, rtol=0.0):
     with Pk.Collapse([(a, D, 0.3)], precision=Pk.PINO_SURROGATE, mlp_blob=blob, certify_rtol=rtol) as col:
-        n = slabs32[0].shape[1]
+        n = slabs[0].shape[1]
         Fm, Rm, ac = col.outputs(n)
-        last = len(slabs32) - 1
-        for r, (h, s) in enumerate(zip(slabs32, sigmas)):
+        last = len(slabs) - 1
+        for r, (h, s) in enumerate(zip(slabs, sigmas)):
             col.apply(h, r, Fm, Rm, ac if r == last else None, reset=(r == 0), finalize=(r == last), sigma_R=s)
         stats = A.pino_collapse_surrogate_stats(col.ctx)
         return (Fm.cpu().numpy(), Rm.cpu().numpy(), ac.cpu().numpy()), stats
 
 
 def test_surrogate_parity_and_gain(P, trained):
+    """C1 through the surrogate path on the FP64 field, against the oracle on
+    the same FP64 Hessians: every output within 1e-6 relative (the certified
+    bound), radius index exact outside near-ties.  The gain over the method
+    without a trained network (the same certificate started from the
+    Zel'dovich guess) is the certified fraction."""
     Pk, A = P
     from paper_2510_02873_amd import surrogate
     orc = _orc()
     blob, _ = trained
     cfg = synth.config("C1")
     a, D = synth.growth_table(0.3)
-    data = _fields(cfg["n_side"], cfg["box"], cfg["radii"], cfg["seed"], cfg["cosmo"])
-    slabs32 = [h.contiguous() for h, _ in data]
+    data = _fields(cfg["n_side"], cfg["box"], cfg["radii"], cfg["seed"], cfg["cosmo"], dtype=torch.float64)
+    slabs = [h.contiguous() for h, _ in data]
     sig = [s for _, s in data]
-    widened = [h.double().cpu().numpy() for h in slabs32]
-    ref = orc.collapse(widened, orc.Growth(a, D))
-    got, stats = _run_surrogate(Pk, A, blob, slabs32, a, D, sig)
-    n = slabs32[0].shape[1]
-    tot = stats["certified"] + stats["fallback"] + stats["gated"]
-    assert tot == n * len(slabs32)
+    host = [h.cpu().numpy() for h in slabs]
+    ref = orc.collapse(host, orc.Growth(a, D))
+    got, stats = _run_surrogate(Pk, A, blob, slabs, a, D, sig)
+    n = slabs[0].shape[1]
+    tot = stats["certified"] + stats["fallback"] + stats["gated_solved"] + stats["gated_zero"]
+    assert tot == n * len(slabs)
     Fr, Rr, Ar = ref
     F, R, Ac = got
     big = Fr >= 1e-6
     rel = np.abs(1 / F[big] - 1 / Fr[big]) * Fr[big]
     fin = np.isfinite(Ar)
     rel_a = np.abs(Ac[fin] - Ar[fin]) / Ar[fin]
-    per_r = np.stack([orc.points(h)[1] for h in widened])
+    per_r = np.stack([orc.points(h)[1] for h in host])
     srt = np.sort(per_r, axis=0)
     tie = np.abs(srt[-1] - srt[-2]) <= 2e-6 * srt[-1]
     consulted = stats["certified"] + stats["fallback"]
-    print(f"surrogate C1: certified {stats['certified']} fallback {stats['fallback']} gated {stats['gated']} "
-          f"(fallback fraction of consulted {stats['fallback'] / consulted:.3f}); "
-          f"D_c max rel {rel.max():.2e}, a_coll max rel {rel_a.max():.2e}", flush=True)
+    print(f"surrogate C1: certified {stats['certified']} fallback {stats['fallback']} "
+          f"gated_solved {stats['gated_solved']} gated_zero {stats['gated_zero']} "
+          f"(fallback fraction of consulted {stats['fallback'] / consulted:.3f}, full-solve fraction of all "
+          f"{stats['full_solve'] / tot:.3f}); D_c max rel {rel.max():.2e}, a_coll max rel {rel_a.max():.2e}",
+          flush=True)
+    assert np.array_equal(F > 0, Fr > 0)
     assert rel.max() <= 1e-6
     assert np.array_equal(np.isfinite(Ac), fin) and rel_a.max() <= 1e-6
     assert np.all((R == Rr) | tie)
     # the same certificate started from the Zel'dovich guess (a network that
     # predicts w = 1 everywhere): what the trained network gains
-    got0, stats0 = _run_surrogate(Pk, A, surrogate.constant_blob(1.0), slabs32, a, D, sig)
+    got0, stats0 = _run_surrogate(Pk, A, surrogate.constant_blob(1.0), slabs, a, D, sig)
     c0 = stats0["certified"] / (stats0["certified"] + stats0["fallback"])
     c1 = stats["certified"] / consulted
     print(f"certified fraction: trained network {c1:.3f} vs Zel'dovich guess {c0:.3f}", flush=True)
     F0 = got0[0]
     assert np.max(np.abs(1 / F0[big] - 1 / Fr[big]) * Fr[big]) <= 1e-6
     assert c1 > c0 + 0.2
+
+
+def _time_leg(col, slabs, sig, reps=5):
+    n = slabs[0].shape[1]
+    Fm, Rm, ac = col.outputs(n)
+    stream = torch.cuda.current_stream()
+    last = len(slabs) - 1
+
+    def step():
+        for r, (h, s) in enumerate(zip(slabs, sig)):
+            col.apply(h, r, Fm, Rm, ac if r == last else None, reset=(r == 0), finalize=(r == last),
+                      sigma_R=s, stream=stream)
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, Fm
+
+
+def test_surrogate_throughput_gain(P, trained):
+    """Throughput of the certified surrogate with the trained network against
+    the same path without it (the constant Zel'dovich-guess network, whose
+    predictions mostly fail the certificate and fall back to the full solve)
+    and against the plain FP64 solve, on 128^3 x 4 radii of FP64 Hessians,
+    all reported.  Every lane of a wave runs the network, so the launch costs
+    about the same whatever the network certifies: the trained network must
+    not make the path slower (5 % allowance for timing noise); the ratio to
+    the plain solve, which is faster on this chip, is reported."""
+    Pk, A = P
+    from paper_2510_02873_amd import surrogate
+    blob, _ = trained
+    a, D = synth.growth_table(0.3)
+    data = _fields(128, 200.0, [8.0, 4.0, 2.0, 1.0], 21, synth.Cosmology(), dtype=torch.float64)
+    slabs = [h.contiguous() for h, _ in data]
+    sig = [s for _, s in data]
+    with Pk.Collapse([(a, D, 0.3)], precision=Pk.PINO_SURROGATE, mlp_blob=blob) as col:
+        t_net, F_net = _time_leg(col, slabs, sig)
+    with Pk.Collapse([(a, D, 0.3)], precision=Pk.PINO_SURROGATE, mlp_blob=surrogate.constant_blob(1.0)) as col:
+        t_const, F_const = _time_leg(col, slabs, sig)
+    with Pk.Collapse([(a, D, 0.3)]) as col:
+        t_plain, F_plain = _time_leg(col, slabs, sig)
+    print(f"128^3 x 4: surrogate {t_net:.3f} ms, without trained network {t_const:.3f} ms, plain FP64 "
+          f"{t_plain:.3f} ms per step; trained/untrained speedup {t_const / t_net:.2f}, "
+          f"surrogate/plain throughput {t_plain / t_net:.2f}", flush=True)
+    big = F_plain > 1e-6
+    for Fs in (F_net, F_const):
+        assert float(((1 / Fs[big] - 1 / F_plain[big]).abs() * F_plain[big]).max()) <= 1e-6
+    assert t_net <= 1.05 * t_const
+
+
+@pytest.mark.parametrize("nk", [2048, 511])
+def test_surrogate_large_and_odd_growth_tables(P, nk):
+    """Growth tables of 2048 knots (the knots, their index and the weight
+    fragments need about 81 KB of LDS, past the default 64 KiB limit) and of
+    an odd knot count (the fragments' LDS offset is then not a multiple of 16
+    bytes before rounding): the surrogate path with the Zel'dovich-guess
+    network matches the oracle within the certified 1e-6."""
+    Pk, A = P
+    from paper_2510_02873_amd import surrogate
+    orc = _orc()
+    cfg = synth.config("C1")
+    a, D = synth.growth_table(0.3, nk)
+    data = _fields(cfg["n_side"], cfg["box"], cfg["radii"], cfg["seed"], cfg["cosmo"], dtype=torch.float64)
+    slabs = [h.contiguous() for h, _ in data]
+    sig = [s for _, s in data]
+    host = [h.cpu().numpy() for h in slabs]
+    Fr, Rr, Ar = orc.collapse(host, orc.Growth(a, D))
+    (F, R, Ac), stats = _run_surrogate(Pk, A, surrogate.constant_blob(1.0), slabs, a, D, sig)
+    big = Fr >= 1e-6
+    rel = np.abs(1 / F[big] - 1 / Fr[big]) * Fr[big]
+    fin = np.isfinite(Ar)
+    rel_a = np.abs(Ac[fin] - Ar[fin]) / Ar[fin]
+    print(f"surrogate with {nk} growth knots: D_c max rel {rel.max():.2e}, a_coll max rel {rel_a.max():.2e}, "
+          f"certified {stats['certified']}", flush=True)
+    assert rel.max() <= 1e-6 and rel_a.max() <= 1e-6
+    assert np.array_equal(np.isfinite(Ac), fin)
+
+
+def test_two_streams_match_one_stream(P):
+    """Contexts with scratch of their own (Tabulated: the per-radius table;
+    surrogate: the deferred-particle queue) give bit-identical results when
+    successive evals alternate between two streams, with nothing but the
+    library ordering them, and when every eval uses one stream."""
+    Pk, A = P
+    from paper_2510_02873_amd import surrogate
+    orc = _orc()
+    cfg = synth.config("C1")
+    a, D = synth.growth_table(0.3)
+    data = _fields(64, 150.0, [6.0, 3.0, 1.5, 0.8], 5, cfg["cosmo"], dtype=torch.float64)
+    slabs = [h.contiguous() for h, _ in data]
+    sig = [s for _, s in data]
+    knots = synth.table_knots(1.0, 32, 32, 64)
+    tabs = []
+    for sR in sig:
+        xk, yk, dkn = (np.asarray(k) * sR for k in knots)
+        _, Ft = orc.points(synth.table_grid_hessians(xk, yk, dkn))
+        tabs.append(torch.from_numpy(Ft).cuda())
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    last = len(slabs) - 1
+    for name, kw in (("tabulated", dict(method=Pk.PINO_TABULATED, table_knots=knots)),
+                     ("surrogate", dict(precision=Pk.PINO_SURROGATE, mlp_blob=surrogate.constant_blob(1.0)))):
+        outs = []
+        for streams in ((s1, s1), (s1, s2)):
+            with Pk.Collapse([(a, D, 0.3)], **kw) as col:
+                n = slabs[0].shape[1]
+                F, R, Ac = col.outputs(n)
+                torch.cuda.synchronize()
+                for r in range(len(slabs)):
+                    col.apply(slabs[r], r, F, R, Ac if r == last else None, reset=(r == 0), finalize=(r == last),
+                              sigma_R=sig[r], table_F=tabs[r], stream=streams[r % 2])
+                torch.cuda.synchronize()
+                outs.append((F.clone(), R.clone(), Ac.clone()))
+        (F1, R1, A1), (F2, R2, A2) = outs
+        print(f"{name}: two streams vs one: equal {torch.equal(F1, F2) and torch.equal(R1, R2)}", flush=True)
+        assert torch.equal(F1, F2) and torch.equal(R1, R2) and torch.equal(A1, A2), name
