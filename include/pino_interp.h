@@ -56,6 +56,23 @@ pino_status pino_table_eval(int32_t device, const double *xk, int32_t nx, const 
                             const double *dk, int32_t nd, const double *tab, const double *qx, const double *qy,
                             const double *qd, double *out, int64_t m, void *hip_stream);
 
+/* pino_table_build followed by pino_table_eval in one call that allocates
+ * nothing and needs no work or table buffer from the caller: for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The spline coefficients
+ * and the interleaved (F, M) table are built in a static device array of
+ * the library (about 16.1 MiB per GPU, held until the process ends): at
+ * most 2^20 table values (nx * ny * nd) and nd <= 4096, PINO_ERR_ARG beyond.
+ * F: the table values F[(ix * ny + iy) * nd + id] (device, caller-owned);
+ * knots, queries and out as for pino_table_eval.  Every call on a GPU uses
+ * that GPU's one array, whose contents the call rewrites before reading, so
+ * calls that overlap on one GPU (other threads, or streams not ordered with
+ * each other) race and must not be made. */
+pino_status pino_table_interp_noalloc(int32_t device, const double *xk, int32_t nx, const double *yk, int32_t ny,
+                                      const double *dk, int32_t nd, const double *F, const double *qx,
+                                      const double *qy, const double *qd, double *out, int64_t m,
+                                      void *hip_stream);
+
 const char *pino_interp_last_error(void);
 
 #ifdef __cplusplus

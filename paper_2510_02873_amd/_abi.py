@@ -483,9 +483,12 @@ def _bind_interp():
         L.pino_spline_eval.argtypes = [c_i32, c_p, c_p, c_p, c_i32, c_p, c_p, c_i64, c_p]
         L.pino_table_build.argtypes = [c_i32, c_i32, c_i32, c_i32, c_p, c_p, c_p, c_p, c_p]
         L.pino_table_eval.argtypes = [c_i32, c_p, c_i32, c_p, c_i32, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p]
+        L.pino_table_interp_noalloc.argtypes = [c_i32, c_p, c_i32, c_p, c_i32, c_p, c_i32, c_p, c_p, c_p, c_p, c_p,
+                                                c_i64, c_p]
         L.pino_interp_last_error.argtypes = []
         L.pino_interp_last_error.restype = ctypes.c_char_p
-        for name in ("pino_spline_build", "pino_spline_eval", "pino_table_build", "pino_table_eval"):
+        for name in ("pino_spline_build", "pino_spline_eval", "pino_table_build", "pino_table_eval",
+                     "pino_table_interp_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _interp_bound = True
     return L
@@ -516,6 +519,15 @@ def pino_table_build(dk, F, tab, work, stream=None):
     nx, ny, nd = F.shape
     _check_interp(_bind_interp().pino_table_build(_dev(F), nx, ny, nd, _ptr(dk), _ptr(F), _ptr(tab), _ptr(work),
                                                   _stream(stream)))
+
+
+def pino_table_interp_noalloc(xk, yk, dk, F, qx, qy, qd, out, stream=None):
+    """Table build and evaluation in the library's static device scratch
+    (F shaped (nx, ny, nd) on the device; no work or table buffer)."""
+    nx, ny, nd = xk.numel(), yk.numel(), dk.numel()
+    _check_interp(_bind_interp().pino_table_interp_noalloc(_dev(xk), _ptr(xk), nx, _ptr(yk), ny, _ptr(dk), nd,
+                                                           _ptr(F), _ptr(qx), _ptr(qy), _ptr(qd), _ptr(out),
+                                                           qx.numel(), _stream(stream)))
 
 
 def pino_table_eval(xk, yk, dk, tab, qx, qy, qd, out, stream=None):
