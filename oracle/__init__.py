@@ -80,6 +80,12 @@ def lib():
                                              + [_D] * 9 + [ctypes.c_int, _D, _I32, _D])
         L.orc_g_lcdm.argtypes = [_D, ctypes.c_int] + [_D] * 7 + [ctypes.c_double, _D]
         L.orc_g_lcdm.restype = ctypes.c_double
+        L.orc_ell_alpha.argtypes = [_D, ctypes.c_int]
+        L.orc_ell_alpha.restype = ctypes.c_double
+        L.orc_ellipsoid_F.argtypes = [_D] + [ctypes.c_double] * 5 + [_D]
+        L.orc_ellipsoid_F.restype = ctypes.c_double
+        L.orc_ellipsoid_axes.argtypes = [_D] + [ctypes.c_double] * 4 + [_D, _D]
+        L.orc_ellipsoid_table.argtypes = [ctypes.c_int] * 3 + [_D] * 3 + [ctypes.c_double] * 5 + [_D]
         _lib = L
     return _lib
 
@@ -206,6 +212,45 @@ class Growth:
         if self.omega_m is None:
             raise ValueError("this growth table has no LCDM coefficients (pass omega_m)")
         return [_p(x) for x in (self.D, self.k2, self.m2, self.k3a, self.m3a, self.k3b, self.m3b)]
+
+
+# the homogeneous-ellipsoid integration: start, stop and the oracle's step
+# (in ln a) and step limit near collapse
+ELL_A_I = 1e-7
+ELL_A_STOP = 10.0
+ELL_STEP = 2e-3
+ELL_KAPPA = 0.02
+
+
+def ell_alpha(x, i):
+    """Internal-tide coefficient alpha_i of an ellipsoid with axes x."""
+    return lib().orc_ell_alpha(_p(_f64(x)), int(i))
+
+
+def ellipsoid_F(lam, omega_m, step=ELL_STEP, kappa=ELL_KAPPA, a_i=ELL_A_I, a_stop=ELL_A_STOP):
+    """(F = 1/D_c, a_c) of the homogeneous ellipsoid with eigenvalues lam."""
+    ac = ctypes.c_double()
+    F = lib().orc_ellipsoid_F(_p(_f64(lam)), float(omega_m), float(a_i), float(a_stop), float(step), float(kappa),
+                              ctypes.byref(ac))
+    return F, ac.value
+
+
+def ellipsoid_axes(lam, omega_m, a_out, step=ELL_STEP, a_i=ELL_A_I):
+    """(axes x_i = R_i/a, D/D1) of the ellipsoid at a_out."""
+    x = np.empty(3)
+    d = ctypes.c_double()
+    lib().orc_ellipsoid_axes(_p(_f64(lam)), float(omega_m), float(a_i), float(a_out), float(step), _p(x),
+                             ctypes.byref(d))
+    return x, d.value
+
+
+def ellipsoid_table(xk, yk, dk, omega_m, step=ELL_STEP, kappa=ELL_KAPPA, a_i=ELL_A_I, a_stop=ELL_A_STOP):
+    """F over the nodes of knots (already scaled), shaped (nx, ny, nd)."""
+    xk, yk, dk = _f64(xk), _f64(yk), _f64(dk)
+    F = np.empty((len(xk), len(yk), len(dk)))
+    lib().orc_ellipsoid_table(len(xk), len(yk), len(dk), _p(xk), _p(yk), _p(dk), float(omega_m), float(a_i),
+                              float(a_stop), float(step), float(kappa), _p(F))
+    return F
 
 
 def collapse_D_lcdm(lam, growth: Growth):

@@ -762,3 +762,255 @@ double orc_g_lcdm(const double lam[3], int nk, const double *D, const double *k2
     }
     return g_lcdm(&K, lam[0], beta, ga, gb, Dq);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Homogeneous-ellipsoid collapse: the source of the Tabulated table         */
+/* (Sec. 3: nine ODEs integrated with fourth-order Runge-Kutta until the     */
+/* density diverges).  The equations are those of a homogeneous ellipsoid in */
+/* an expanding flat LCDM background with the external tide of linear theory */
+/* (the form of Bond & Myers 1996).  For semi-axes R_i = a x_i (unit          */
+/* Lagrangian radius), with 1 + delta = 1/(x1 x2 x3):                         */
+/*   d2R_i/dt2 = -(3/2) Om a^-3 R_i [(1 + delta)/3 + (alpha_i - 2/3) delta/2  */
+/*               + (D/D1) (l_i - (l1 + l2 + l3)/3)] + (1 - Om) R_i,           */
+/*   alpha_i = |x1 x2 x3| int_0^inf dtau / ((x_i^2 + tau)^(3/2)              */
+/*                                        sqrt((x_j^2 + tau)(x_k^2 + tau))), */
+/* D the linear growing mode and D1 its value at a = 1.                       */
+/*                                                                          */
+/* The oracle does NOT integrate that form.  It integrates the equivalent     */
+/* comoving system in s = ln a (eight ODEs; ' = d/ds, Om(a) = Om a^-3/E^2):   */
+/*   x_i'' = -(2 - 1.5 Om(a)) x_i' - 1.5 Om(a) x_i [delta/3                   */
+/*            + (alpha_i - 2/3) delta/2 + (D/D1)(l_i - (l1+l2+l3)/3)],        */
+/*   D''   = -(2 - 1.5 Om(a)) D' + 1.5 Om(a) D,                               */
+/* with classical RK4 at a fixed step in s, alpha_i by the trapezoid rule in  */
+/* v = ln tau (step 0.5 over the range where the integrand is above 1e-17 of  */
+/* its scale; the integrand is analytic within |Im v| < pi, where this rule   */
+/* converges geometrically, error ~ exp(-2 pi^2 / 0.5)), and the crossing of  */
+/* x_1 = 0 located by bisection of the last step's length.  Initial state at  */
+/* a_i: the Zel'dovich growing mode D = a, x_i = 1 - l_i a_i / D1.  No        */
+/* collapse by a_stop gives F = 0.  Output F = 1/D_c, D_c = D(a_c)/D1.        */
+/* ------------------------------------------------------------------------ */
+static double ell_f(double v, double xi2, double xj2, double xk2)
+{
+    double t = exp(v);
+    double u = xi2 + t;
+    return t / (u * sqrt(u) * sqrt((xj2 + t) * (xk2 + t)));
+}
+
+/* alpha_i of axes x[0..2] */
+double orc_ell_alpha(const double x[3], int i)
+{
+    int j = (i + 1) % 3, k = (i + 2) % 3;
+    double xi2 = x[i] * x[i], xj2 = x[j] * x[j], xk2 = x[k] * x[k];
+    double lo = xi2, hi = xi2;
+    if (xj2 < lo) lo = xj2;
+    if (xk2 < lo) lo = xk2;
+    if (xj2 > hi) hi = xj2;
+    if (xk2 > hi) hi = xk2;
+    if (!(lo > 0.0))
+        return (xi2 > 0.0) ? 0.0 : 2.0; /* a degenerate axis: the flat limits */
+    const double h = 0.5;
+    double v0 = log(lo) - 40.0, v1 = log(hi) + 28.0;
+    int n = (int)ceil((v1 - v0) / h);
+    double sum = 0.5 * (ell_f(v0, xi2, xj2, xk2) + ell_f(v0 + n * h, xi2, xj2, xk2));
+    for (int m = 1; m < n; ++m)
+        sum += ell_f(v0 + m * h, xi2, xj2, xk2);
+    double I = h * sum;
+    /* the part below v0, where the integrand is its tau -> 0 value times tau */
+    I += exp(v0) / (xi2 * sqrt(xi2) * sqrt(xj2 * xk2));
+    return fabs(x[0] * x[1] * x[2]) * I;
+}
+
+typedef struct {
+    double om, D1, lext[3];
+} ell_par;
+
+/* state y = (x1, x2, x3, x1', x2', x3', D, D') in s = ln a */
+static void ell_rhs(const ell_par *P, double s, const double y[8], double dy[8])
+{
+    double a3 = exp(-3.0 * s);
+    double oma = P->om * a3 / (P->om * a3 + 1.0 - P->om);
+    double damp = 2.0 - 1.5 * oma;
+    double x[3] = {y[0], y[1], y[2]};
+    double delta = 1.0 / (x[0] * x[1] * x[2]) - 1.0;
+    double dn = y[6] / P->D1;
+    for (int i = 0; i < 3; ++i) {
+        double al = orc_ell_alpha(x, i);
+        dy[i] = y[3 + i];
+        /* uniform excess delta/3 plus internal tide (alpha - 2/3) delta/2,
+         * written as their sum alpha delta/2 */
+        dy[3 + i] = -damp * y[3 + i] - 1.5 * oma * x[i] * (0.5 * al * delta + dn * P->lext[i]);
+    }
+    dy[6] = y[7];
+    dy[7] = -damp * y[7] + 1.5 * oma * y[6];
+}
+
+static void ell_rk4(const ell_par *P, double s, double h, const double y[8], double out[8])
+{
+    double k1[8], k2[8], k3[8], k4[8], t[8];
+    ell_rhs(P, s, y, k1);
+    for (int c = 0; c < 8; ++c) t[c] = y[c] + 0.5 * h * k1[c];
+    ell_rhs(P, s + 0.5 * h, t, k2);
+    for (int c = 0; c < 8; ++c) t[c] = y[c] + 0.5 * h * k2[c];
+    ell_rhs(P, s + 0.5 * h, t, k3);
+    for (int c = 0; c < 8; ++c) t[c] = y[c] + h * k3[c];
+    ell_rhs(P, s + h, t, k4);
+    for (int c = 0; c < 8; ++c)
+        out[c] = y[c] + h / 6.0 * (k1[c] + 2.0 * (k2[c] + k3[c]) + k4[c]);
+}
+
+/* D(a = 1) of the growing mode started as D = a at a_i, RK4 in s with the
+ * same step as the ellipsoid (the normalisation both use) */
+double orc_ell_growth1(double om, double a_i, double h)
+{
+    double s = log(a_i);
+    int n = (int)ceil(-s / h);
+    double hh = -s / n;
+    double y[2] = {a_i, a_i};
+    for (int m = 0; m < n; ++m) {
+        double ss = s + m * hh;
+        double k[4][2], t[2];
+        double oma, damp;
+#define GROW(sv, yv, kv)                                                   \
+        oma = om * exp(-3.0 * (sv)) / (om * exp(-3.0 * (sv)) + 1.0 - om); \
+        damp = 2.0 - 1.5 * oma;                                            \
+        kv[0] = yv[1];                                                     \
+        kv[1] = -damp * yv[1] + 1.5 * oma * yv[0];
+        GROW(ss, y, k[0]);
+        t[0] = y[0] + 0.5 * hh * k[0][0]; t[1] = y[1] + 0.5 * hh * k[0][1];
+        GROW(ss + 0.5 * hh, t, k[1]);
+        t[0] = y[0] + 0.5 * hh * k[1][0]; t[1] = y[1] + 0.5 * hh * k[1][1];
+        GROW(ss + 0.5 * hh, t, k[2]);
+        t[0] = y[0] + hh * k[2][0]; t[1] = y[1] + hh * k[2][1];
+        GROW(ss + hh, t, k[3]);
+#undef GROW
+        for (int c = 0; c < 2; ++c)
+            y[c] += hh / 6.0 * (k[0][c] + 2.0 * (k[1][c] + k[2][c]) + k[3][c]);
+    }
+    return y[0];
+}
+
+/* F = 1/D_c of the ellipsoid with eigenvalues lam (any order: the axis that
+ * reaches zero first collapses), 0 without collapse by a_stop.  h: the RK4
+ * step in ln a, shortened near collapse to kappa sqrt(x / |x''|) of the
+ * smallest axis (the time over which its acceleration changes it: this
+ * follows a regular crossing, where x'' stays finite, and the free-fall
+ * approach of a nearly spherical collapse, where x ~ (s_c - s)^(2/3)).  A
+ * step that ends with an axis <= 0 is bisected in length down to adjacent
+ * doubles; an axis whose remaining time x / |x'| falls below 1e-12 (in ln a)
+ * is taken as collapsed there.  *a_c receives the collapse scale factor (or
+ * a_stop). */
+double orc_ellipsoid_F(const double lam[3], double om, double a_i, double a_stop, double h, double kappa,
+                       double *a_c)
+{
+    ell_par P;
+    P.om = om;
+    P.D1 = orc_ell_growth1(om, a_i, h);
+    double dl = lam[0] + lam[1] + lam[2];
+    for (int i = 0; i < 3; ++i)
+        P.lext[i] = lam[i] - dl / 3.0;
+    double y[8], yn[8], dy[8];
+    for (int i = 0; i < 3; ++i) {
+        y[i] = 1.0 - lam[i] * a_i / P.D1;
+        y[3 + i] = -lam[i] * a_i / P.D1;
+    }
+    y[6] = a_i;
+    y[7] = a_i;
+    double s = log(a_i), se = log(a_stop);
+    for (long step = 0; step < 100000000L && s < se; ++step) {
+        int im = 0;
+        for (int i = 1; i < 3; ++i)
+            if (y[i] < y[im])
+                im = i;
+        if (y[im] < 1e-12 * fabs(y[3 + im]) && y[3 + im] < 0.0) {
+            if (a_c)
+                *a_c = exp(s);
+            return P.D1 / y[6];
+        }
+        ell_rhs(&P, s, y, dy);
+        double hs = h;
+        double acc = fabs(dy[3 + im]);
+        if (acc > 0.0) {
+            double lim = kappa * sqrt(y[im] / acc);
+            if (lim < hs)
+                hs = lim;
+        }
+        if (s + hs > se)
+            hs = se - s;
+        ell_rk4(&P, s, hs, y, yn);
+        double xmin = yn[0] < yn[1] ? yn[0] : yn[1];
+        if (yn[2] < xmin) xmin = yn[2];
+        if (!(xmin > 0.0)) {
+            double lo = 0.0, hi = hs;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (!(mid > lo && mid < hi))
+                    break;
+                ell_rk4(&P, s, mid, y, yn);
+                double xm = yn[0] < yn[1] ? yn[0] : yn[1];
+                if (yn[2] < xm) xm = yn[2];
+                if (xm > 0.0)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            ell_rk4(&P, s, hi, y, yn);
+            if (a_c)
+                *a_c = exp(s + hi);
+            return P.D1 / yn[6];
+        }
+        s += hs;
+        for (int c = 0; c < 8; ++c)
+            y[c] = yn[c];
+    }
+    if (a_c)
+        *a_c = a_stop;
+    return 0.0;
+}
+
+/* The axes x_i = R_i/a of the ellipsoid at scale factor a_out (no collapse
+ * check; for early-time checks).  Same integration as orc_ellipsoid_F. */
+void orc_ellipsoid_axes(const double lam[3], double om, double a_i, double a_out, double h, double x_out[3],
+                        double *D_out)
+{
+    ell_par P;
+    P.om = om;
+    P.D1 = orc_ell_growth1(om, a_i, h);
+    double dl = lam[0] + lam[1] + lam[2];
+    for (int i = 0; i < 3; ++i)
+        P.lext[i] = lam[i] - dl / 3.0;
+    double y[8], yn[8];
+    for (int i = 0; i < 3; ++i) {
+        y[i] = 1.0 - lam[i] * a_i / P.D1;
+        y[3 + i] = -lam[i] * a_i / P.D1;
+    }
+    y[6] = a_i;
+    y[7] = a_i;
+    double s = log(a_i), se = log(a_out);
+    int n = (int)ceil((se - s) / h);
+    double hh = (se - s) / n;
+    for (int m = 0; m < n; ++m) {
+        ell_rk4(&P, s + m * hh, hh, y, yn);
+        for (int c = 0; c < 8; ++c)
+            y[c] = yn[c];
+    }
+    for (int i = 0; i < 3; ++i)
+        x_out[i] = y[i];
+    if (D_out)
+        *D_out = y[6] / P.D1;
+}
+
+/* The ellipsoid table at nodes (delta, x, y) -> eigenvalues
+ * l1 = (d + 2x + y)/3, l2 = (d - x + y)/3, l3 = (d - x - 2y)/3:
+ * F[(ix * ny + iy) * nd + id] over the knots xk, yk, dk (already scaled). */
+void orc_ellipsoid_table(int nx, int ny, int nd, const double *xk, const double *yk, const double *dk, double om,
+                         double a_i, double a_stop, double h, double kappa, double *F)
+{
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    for (int ix = 0; ix < nx; ++ix)
+        for (int iy = 0; iy < ny; ++iy)
+            for (int id = 0; id < nd; ++id) {
+                double x = xk[ix], yv = yk[iy], d = dk[id];
+                double lam[3] = {(d + 2.0 * x + yv) / 3.0, (d - x + yv) / 3.0, (d - x - 2.0 * yv) / 3.0};
+                F[((size_t)ix * ny + iy) * nd + id] = orc_ellipsoid_F(lam, om, a_i, a_stop, h, kappa, NULL);
+            }
+}

@@ -5,12 +5,16 @@ order W1[64][4], b1, W2[64][64], b2, W3[64][64], b3, W4[64], b4; loss the mean
 relative squared error over samples with target w > 0.  Written out layer by
 layer in numpy float64, forward and backward by the chain rule.
 
-bf16=True evaluates the network the way the BF16 matrix-core inference
-does: the weights of the two 64 x 64 layers and the inputs of those layers
-and of the output layer (the ReLU outputs of layers 1, 2 and 3) rounded to
-BF16 (8 significant bits, ties to even), everything else unrounded.  Its gradient treats each rounding as the
-identity (straight-through): it is the exact gradient of the same network
-with the rounding offsets frozen at their current values.
+bf16=True evaluates the network under the surrogate's BF16 rounding rule (a
+choice of this build, stated on its own; the paper has no network): the
+weights of the two 64 x 64 layers and the inputs of those layers and of the
+output layer (the ReLU outputs of layers 1, 2 and 3) are rounded to BF16
+(8 significant bits, round to nearest, ties to even); layer 1's weights and
+inputs, the output layer's weights and every bias stay unrounded.  The
+gradient treats each rounding as the identity (straight-through): it is the
+exact gradient of the same network with the rounding offsets frozen at their
+current values.  A change to which tensors are rounded is a change of that
+rule, made in its statement first and then here and in the kernels.
 """
 
 from __future__ import annotations
