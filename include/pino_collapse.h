@@ -215,6 +215,24 @@ pino_status pino_collapse_eval(pino_ctx *ctx, const pino_item *items, int32_t n_
  * error; the memory is released either way. */
 pino_status pino_collapse_free(pino_ctx *ctx);
 
+/* Fill a Tabulated table from the homogeneous-ellipsoid collapse (Sec. 3:
+ * the table of the Tabulated method comes from integrating nine ODEs with
+ * fourth-order Runge-Kutta until the density diverges).  For every node
+ * (x_ix, y_iy, delta_id) of the context's table knots scaled by sigma_R, the
+ * eigenvalues l1 = (delta + 2x + y)/3, l2 = (delta - x + y)/3,
+ * l3 = (delta - x - 2y)/3 set the linear deformation of a unit sphere in the
+ * flat LCDM cosmology of growth table `cosmo` (its omega_m, 0 < omega_m <= 1);
+ * the axes, the scale factor and the linear growth are integrated from
+ * a = 1e-7 with the ellipsoid's own gravity and the linear external tide
+ * until the first axis reaches zero, and F = 1/D_c is written, D_c the linear
+ * growth factor then (normalised to 1 today); 0 if no axis collapses by
+ * a = 10.  table_F: device, caller-owned, nx * ny * nd doubles in the layout
+ * pino_item.table_F takes.  One thread per node; asynchronous on hip_stream;
+ * allocates nothing.  PINO_ERR_ARG for another method, a bad index or
+ * omega_m, a non-positive sigma_R or NULL table_F. */
+pino_status pino_collapse_ellipsoid_table(pino_ctx *ctx, int32_t cosmo, double sigma_R, double *table_F,
+                                          void *hip_stream);
+
 /* The LCDM time coefficients of a PINO_CLASSIC_LCDM context at the knots of
  * growth table `cosmo`: k2, k3a, k3b (host arrays of that table's n
  * doubles, written) are the second-order, third-order determinant-type and

@@ -81,6 +81,9 @@ def lib():
         L.pino_collapse_last_error.restype = ctypes.c_char_p
         L.pino_collapse_lpt_coefficients.argtypes = [ctypes.c_void_p, ctypes.c_int32, _D, _D, _D]
         L.pino_collapse_lpt_coefficients.restype = ctypes.c_int
+        L.pino_collapse_ellipsoid_table.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                                    ctypes.c_void_p, ctypes.c_void_p]
+        L.pino_collapse_ellipsoid_table.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -163,6 +166,13 @@ def make_item(h, Fmax, Rmax, a_coll=None, radius_index=0, cosmo=0, sigma_R=1.0, 
     it.Rmax = Rmax.data_ptr()
     it.a_coll = None if a_coll is None else a_coll.data_ptr()
     return it
+
+
+def pino_collapse_ellipsoid_table(ctx, cosmo, sigma_R, table_F, stream=None):
+    """Fill table_F (device float64, nx * ny * nd) with the homogeneous-
+    ellipsoid F at the context's table knots scaled by sigma_R."""
+    handle = stream.cuda_stream if stream is not None and hasattr(stream, "cuda_stream") else stream
+    _check(lib().pino_collapse_ellipsoid_table(ctx, int(cosmo), float(sigma_R), table_F.data_ptr(), handle), ctx)
 
 
 def pino_collapse_lpt_coefficients(ctx, cosmo, n):

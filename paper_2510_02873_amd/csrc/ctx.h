@@ -90,6 +90,9 @@ struct pino_ctx {
     double* d_tcoef = nullptr;
     // mixed precision: FP32 knot-pair table (F_j, M_j, F_j+1, M_j+1) per row
     void* d_tab32 = nullptr;
+    // homogeneous-ellipsoid table fill: the growing mode's D(a = 1) of each
+    // cosmology in that integration's normalisation (computed at first use)
+    std::vector<double> ell_D1;
 
     // spline-build scratch
     double* d_tmp = nullptr;

@@ -11,6 +11,7 @@
 
 #include "../../include/pino_collapse.h"
 #include "ctx.h"
+#include "kernels_ellipsoid.h"
 #include "kernels_fp64.h"
 #include "kernels_lcdm.h"
 #include "launch_ext.h"
@@ -666,6 +667,38 @@ const char* pino_collapse_last_error(const pino_ctx* ctx)
     if (!ctx)
         return g_init_error.c_str();
     return ctx->err.c_str();
+}
+
+pino_status pino_collapse_ellipsoid_table(pino_ctx* ctx, int32_t cosmo, double sigma_R, double* table_F,
+                                          void* hip_stream)
+{
+    if (!ctx) {
+        g_init_error = "ctx is NULL";
+        return PINO_ERR_ARG;
+    }
+    if (ctx->broken)
+        return PINO_ERR_STATE;
+    if (ctx->method != PINO_TABULATED || cosmo < 0 || cosmo >= ctx->n_cosmo || !table_F ||
+        !(std::isfinite(sigma_R) && sigma_R > 0.0)) {
+        ctx->err = "need a PINO_TABULATED context, a valid cosmology index, a finite sigma_R > 0 and table_F";
+        return PINO_ERR_ARG;
+    }
+    const double om = ctx->omega[cosmo];
+    if (!(om > 0.0 && om <= 1.0)) {
+        ctx->err = "the ellipsoid table needs 0 < omega_m <= 1 (flat, no radiation)";
+        return PINO_ERR_ARG;
+    }
+    PINO_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->ell_D1.empty())
+        ctx->ell_D1.assign(ctx->n_cosmo, 0.0);
+    if (!(ctx->ell_D1[cosmo] > 0.0))
+        ctx->ell_D1[cosmo] = ell_growth_today(om);
+    const int64_t nodes = (int64_t)ctx->nx * ctx->ny * ctx->nd;
+    hipLaunchKernelGGL(k_ellipsoid_table, dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), ctx->d_tknots, ctx->nx, ctx->ny, ctx->nd, sigma_R, om,
+                       ctx->ell_D1[cosmo], table_F);
+    PINO_HIP(ctx, hipGetLastError());
+    return PINO_OK;
 }
 
 pino_status pino_collapse_lpt_coefficients(pino_ctx* ctx, int32_t cosmo, double* k2, double* k3a, double* k3b)

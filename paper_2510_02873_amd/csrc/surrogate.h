@@ -113,10 +113,13 @@ __device__ __forceinline__ void dense_cols(const float* __restrict__ W, int u0, 
 }
 
 // pq: the parameters whose W2 and W3 the hidden layers use (the BF16-rounded
-// copy when bf16, else p itself); bf16 also rounds the inputs of those layers
-// and of the output layer (the ReLU outputs of layers 1, 2 and 3) to BF16, as
-// the matrix-core inference does.  The backward pass uses the same weights and stored activations and
-// treats the rounding as the identity (straight-through).
+// copy when bf16, else p itself).  bf16 applies the surrogate's BF16
+// rounding rule, which the inference network below follows too: the weights
+// of the two 64 x 64 layers and the inputs of those layers and of the output
+// layer (the ReLU outputs of layers 1, 2 and 3) rounded to BF16 (nearest,
+// ties to even); layer 1, the output layer's weights and the biases in FP32.
+// The backward pass uses the same weights and stored activations and treats
+// the rounding as the identity (straight-through).
 __global__ void __launch_bounds__(kGradThreads) k_mlp_grad_block(const float* __restrict__ p,
                                                                 const float* __restrict__ pq, int bf16,
                                                                 const float* __restrict__ X,
@@ -372,7 +375,10 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ P
 // the lane supplies as B of the next layer's K tile kt, once the next layer's
 // weight columns are permuted to match (done when the fragments are built).
 // So the network stays in registers; the FP32 -> BF16 step is the hardware
-// packed convert (round to nearest even).
+// packed convert (round to nearest even).  Rounding rule: the weights of the
+// two 64 x 64 layers and the inputs of those layers and of the output layer
+// are BF16; layer 1 and the output layer's weights carry FP32 accuracy as
+// BF16 high + low pairs; biases and accumulation are FP32.
 // ---------------------------------------------------------------------------
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
