@@ -177,6 +177,50 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
     mtcol.close()
     del s32
 
+    # Tabulated table from the homogeneous-ellipsoid integration: one
+    # 64 x 64 x 128 table (524288 nodes) per radius; time the fill at the
+    # smallest and the largest sigma
+    from paper_2510_02873_amd import _abi
+    ecol = P.Collapse([(a, D, cfg["cosmo"].omega_m)], method=P.PINO_TABULATED, table_knots=knots)
+    Fe = torch.empty(64 * 64 * 128, dtype=torch.float64, device=slabs[0].device)
+    fills = {}
+    for r in (0, len(radii) - 1):
+        _abi.pino_collapse_ellipsoid_table(ecol.ctx, 0, sig[r], Fe, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _abi.pino_collapse_ellipsoid_table(ecol.ctx, 0, sig[r], Fe, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fills[f"sigma_{sig[r]:.3f}"] = round(e0.elapsed_time(e1), 3)
+    frac_collapsing = float((Fe > 0).double().mean().item())
+    ecol.close()
+    out["ellipsoid_table"] = {"nodes": 64 * 64 * 128, "fill_ms": fills,
+                              "collapsing_fraction_at_last_sigma": round(frac_collapsing, 4),
+                              "method": "homogeneous ellipsoid, nine ODEs, RK4 (h = 0.01 in ln a), one thread "
+                                        "per node"}
+    log(f"ellipsoid table fill (64x64x128): {fills} ms")
+
+    # Classic with flat-LCDM LPT time coefficients on the same FP64 fields
+    lcol = P.Collapse([(a, D, cfg["cosmo"].omega_m)], method=P.PINO_CLASSIC_LCDM)
+    Fl, Rl, Al = lcol.outputs(n)
+    litems = [lcol.item(slabs[r], Fl, Rl, Al if r == last else None, radius_index=r) for r in range(len(radii))]
+
+    def lstep():
+        for r, it in enumerate(litems):
+            lcol.eval([it], reset=(r == 0), finalize=(r == last), stream=stream)
+
+    ms = _time_steps(lstep, steps, stream)
+    bothl = (F64 > 1e-6) & (Fl > 0)
+    shift = (Fl[bothl] / F64[bothl] - 1).abs().cpu().numpy()
+    out["classic_lcdm"] = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s",
+                           "ms_per_step": round(ms, 4), "dtype": "f64",
+                           "F_shift_vs_eds_coefficients": {"median": float(np.median(shift)),
+                                                           "max": float(shift.max())},
+                           "roofline": step_roofline(step_bytes(48), ms)}
+    lcol.close()
+    del Fl, Rl, Al
+
     if dk is not None:
         out["field_fused"] = measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps, [(a, D)])
     out["interp_sweep"] = measure_interp()
@@ -406,6 +450,173 @@ def measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R
     return res
 
 
+def _probes():
+    import ctypes
+    from paper_2510_02873_amd import build as libbuild
+    L = ctypes.CDLL(libbuild.PROBES)
+    L.pino_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    L.pino_probe_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_int32, ctypes.c_void_p]
+    L.pino_probe_fma_f64.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    for f in (L.pino_probe_copy, L.pino_probe_stream, L.pino_probe_fma_f64):
+        f.restype = ctypes.c_int
+    return L
+
+
+def measure_ceilings(slabs, n, stream, reps=10):
+    """Ceilings measured on this GPU next to the spec sheet's: a streaming
+    copy (2 GiB read + 2 GiB written), the headline kernel's own data
+    movement with no arithmetic (six FP64 Hessian streams, Fmax and Rmax
+    read and written back as whole lines: 72 B per particle, on the
+    benchmark's resident fields), and independent FP64 FMA chains."""
+    import ctypes
+    import torch
+
+    L = _probes()
+    dev = slabs[0].device
+    h = stream.cuda_stream
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    ms = timed(lambda: L.pino_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes // 16, h))
+    out["copy_GBps"] = round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    F = torch.zeros(n, dtype=torch.float64, device=dev)
+    R = torch.full((n,), -1, dtype=torch.int32, device=dev)
+    ptrs = (ctypes.c_void_p * 6)(*[slabs[0][c].data_ptr() for c in range(6)])
+    ms = timed(lambda: L.pino_probe_stream(ptrs, F.data_ptr(), R.data_ptr(), n, 1, h))
+    out["collapse_pattern_GBps"] = round(72 * n / (ms * 1e-3) / 1e9, 1)
+    out["collapse_pattern_us_per_launch"] = round(ms * 1e3, 2)
+    del F, R
+    blocks, iters = 256 * 16, 4096
+    buf = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+    ms = timed(lambda: L.pino_probe_fma_f64(buf.data_ptr(), blocks, iters, h))
+    out["fp64_fma_TFs"] = round(blocks * 256 * 8 * iters * 2 / (ms * 1e-3) / 1e12, 2)
+    out["probes"] = ("copy: 16 B per lane, nontemporal loads; collapse pattern: six f64 SoA streams (nontemporal) "
+                     "+ Fmax/Rmax read and written as whole lines, pairs of particles per lane; fma: 8 "
+                     "independent f64 FMA chains per lane, 4096 blocks of 256")
+    log(f"ceilings: copy {out['copy_GBps']} GB/s, collapse pattern {out['collapse_pattern_GBps']} GB/s "
+        f"({out['collapse_pattern_us_per_launch']} us), FP64 FMA {out['fp64_fma_TFs']} TF/s")
+    return out
+
+
+def measure_512(P, blob, steps=1):
+    """The 512^3 x 40-radius configuration (one GPU's share of a 2048^3 run,
+    seed 3, a field the surrogate never saw in training): per radius the
+    FP64 Hessians come from the device's Hessian stage (pino_field) and the
+    FP32 slab is their rounded copy; the mixed-precision path (FP32 slab)
+    and the surrogate + certify path (FP64 Hessians) are each timed per
+    launch with HIP events on the launch stream, the Hessian stage excluded.
+    Errors of both against the FP64 oracle on a seeded sample of 20k
+    particles over all 40 radii."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_2510_02873_amd import _abi
+
+    cfg = synth.config("C3")
+    n_side, box, radii, cosmo = cfg["n_side"], cfg["box"], cfg["radii"], cfg["cosmo"]
+    n = n_side ** 3
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    a, D = synth.growth_table(cosmo.omega_m, cfg["n_growth"])
+    sig = synth.grid_sigma_gauss(n_side, box, radii, cosmo)
+    t0 = time.time()
+    fld = synth.fields.field(n_side, box, cfg["seed"], cosmo, device=dev)
+    dk = fld.dk.contiguous()
+    del fld
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(99)
+    idx = np.sort(rng.choice(n, size=20000, replace=False))
+    tidx = torch.from_numpy(idx).to(dev)
+    H64 = torch.empty((6, n), dtype=torch.float64, device=dev)
+    H32 = torch.empty((6, n), dtype=torch.float32, device=dev)
+    mix = P.Collapse([(a, D, cosmo.omega_m)], precision=P.PINO_MIXED)
+    sur = P.Collapse([(a, D, cosmo.omega_m)], precision=P.PINO_SURROGATE, mlp_blob=blob)
+    Fm, Rm, Am = mix.outputs(n)
+    Fs, Rs, As = sur.outputs(n)
+    last = len(radii) - 1
+    t_mix, t_sur = [], []
+    sample = []
+    _abi.pino_collapse_surrogate_stats(sur.ctx, reset=True)
+    with P.Field(n_side, box) as f:
+        for step in range(steps):
+            for r, R in enumerate(radii):
+                f.hessian(dk, R, H64, stream=stream)
+                H32.copy_(H64)
+                if step == 0:
+                    sample.append(H64[:, tidx].cpu().numpy())
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                ev[0].record(stream)
+                mix.apply(H32, r, Fm, Rm, Am if r == last else None, reset=(r == 0), finalize=(r == last),
+                          stream=stream)
+                ev[1].record(stream)
+                ev[2].record(stream)
+                sur.apply(H64, r, Fs, Rs, As if r == last else None, reset=(r == 0), finalize=(r == last),
+                          sigma_R=sig[r], stream=stream)
+                ev[3].record(stream)
+                torch.cuda.synchronize()
+                t_mix.append(ev[0].elapsed_time(ev[1]))
+                t_sur.append(ev[2].elapsed_time(ev[3]))
+            log(f"512^3 x {len(radii)}: pass {step + 1}/{steps} done ({time.time() - t0:.0f}s)")
+    st = _abi.pino_collapse_surrogate_stats(sur.ctx)
+    got_m = [t[tidx].cpu().numpy() for t in (Fm, Rm, Am)]
+    got_s = [t[tidx].cpu().numpy() for t in (Fs, Rs, As)]
+    mix.close()
+    sur.close()
+    del H64, H32, dk, Fm, Rm, Am, Fs, Rs, As
+    torch.cuda.empty_cache()
+    ref = oracle.collapse(sample, oracle.Growth(a, D))
+
+    def errs(got):
+        Fr, Rr, Ar = ref
+        big = Fr >= 1e-6
+        both = big & (got[0] > 0)
+        rD = np.abs(1 / got[0][both] - 1 / Fr[both]) * Fr[both]
+        fin = np.isfinite(Ar) & np.isfinite(got[2])
+        ra = np.abs(got[2][fin] - Ar[fin]) / Ar[fin]
+        stat = lambda x: {"max": float(x.max()), "p99.9": float(np.percentile(x, 99.9)), "mean": float(x.mean())}
+        return {"rel_Dc": stat(rD), "rel_acoll": stat(ra), "index_mismatches": int(np.sum(got[1] != Rr)),
+                "collapse_set_differs": int(np.sum((got[0] > 0) != (Fr > 0))), "sample": int(Fr.size)}
+
+    evals = n * len(radii) * steps
+    wl = f"512cube-{len(radii)}radii"
+    out = {"mixed": {"workload": wl, "value": round(evals / (sum(t_mix) * 1e-3), 1), "unit": "evals/s",
+                     "ms_per_pass": round(sum(t_mix) / steps, 3),
+                     "dtype": "f32 slab (rounded fp64 field), f32 eigen/interp, f64 root",
+                     "vs_fp64_oracle_on_fp64_field": errs(got_m),
+                     "roofline": step_roofline(n * len(radii) * (24 + 8) + n * 20, sum(t_mix) / steps)},
+           "surrogate": {"workload": wl, "value": round(evals / (sum(t_sur) * 1e-3), 1), "unit": "evals/s",
+                         "ms_per_pass": round(sum(t_sur) / steps, 3),
+                         "dtype": "fp64 inputs/eigen/certificate, bf16 MFMA network",
+                         "held_out": "field seed 3 (training used the 256^3 seed-2 fields and seeds 51-54)",
+                         "certified": st["certified"], "fallback": st["fallback"],
+                         "gated_solved": st["gated_solved"], "gated_zero": st["gated_zero"],
+                         "fallback_fraction_of_consulted": round(st["fallback"] / max(1, st["certified"] +
+                                                                                     st["fallback"]), 4),
+                         "full_solve_fraction_of_all": round(st["full_solve"] / max(1, evals), 4),
+                         "vs_fp64_oracle_on_fp64_field": errs(got_s)},
+           "timing": "sum of per-launch HIP-event times over the radii (Hessian stage excluded)"}
+    log(f"512^3: mixed {out['mixed']['value']:.3e} evals/s, surrogate {out['surrogate']['value']:.3e} evals/s; "
+        f"surrogate max rel D_c vs fp64 {out['surrogate']['vs_fp64_oracle_on_fp64_field']['rel_Dc']['max']:.2e}")
+    return out
+
+
 def measure_batched(P, steps):
     """C4: 64 realisations (grid sides uniform in 64..192, cell 0.78125 Mpc/h),
     each with its own cosmology and 512-point growth table, 20 radii 16 -> 1
@@ -486,6 +697,8 @@ def main():
     ap.add_argument("--n-side", type=int, default=None, help="override the grid side (testing only)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (mixed precision, Tabulated) on the same fields")
+    ap.add_argument("--no-512", action="store_true",
+                    help="skip the 512^3 x 40-radius mixed-precision and surrogate legs")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched 64-realisation workload (182 GB of resident Hessians)")
     ap.add_argument("--train-steps", type=int, default=TRAIN_STEPS,
@@ -626,6 +839,16 @@ def main():
 
     extras = {}
     blob = None
+    try:
+        roofline["measured_ceilings"] = measure_ceilings(slabs, n, stream)
+        mc = roofline["measured_ceilings"]
+        roofline["frac_of_measured_copy"] = round(achieved_gbs / mc["copy_GBps"], 4)
+        roofline["launch_vs_collapse_pattern"] = round(mc["collapse_pattern_us_per_launch"] /
+                                                       (mean_launch_ms * 1e3), 4)
+        if roofline.get("fp64"):
+            roofline["fp64"]["frac_of_measured_fma"] = round(roofline["fp64"]["achieved"] / mc["fp64_fma_TFs"], 4)
+    except (OSError, RuntimeError) as e:
+        roofline["measured_ceilings"] = {"error": str(e)[:200]}
     if not args.no_extras:
         extras = measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, args.steps, dk,
                                 updates, args.train_steps, plain_ms=ms_per_step)
@@ -676,9 +899,19 @@ def main():
         cpu["parity_index_mismatches"] = int(np.sum(got_R != rR))
         log(f"cpu baseline {cpu['value']:.3e} evals/s; sample parity max rel D_c {rel:.2e} a_coll {rel_a:.2e}")
 
-    if not args.no_batched and args.n_side is None:
+    run_512 = blob is not None and not args.no_512 and args.n_side is None
+    run_batched = not args.no_batched and args.n_side is None
+    if run_512 or run_batched:
         del slabs, items
         torch.cuda.empty_cache()
+    if run_512:
+        try:
+            extras["c512"] = measure_512(P, blob)
+        except (RuntimeError, torch.cuda.OutOfMemoryError) as e:
+            extras["c512"] = {"error": str(e)[:300]}
+            log(f"512^3 leg failed: {e}")
+        torch.cuda.empty_cache()
+    if run_batched:
         try:
             extras["batched"] = measure_batched(P, max(3, args.steps // 2))
         except (RuntimeError, torch.cuda.OutOfMemoryError) as e:

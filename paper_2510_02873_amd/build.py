@@ -1,4 +1,5 @@
-"""Build the HIP library libpino_collapse.so for gfx950 in-tree."""
+"""Build the HIP library libpino_collapse.so for gfx950 in-tree, and the
+ceiling probes of the benchmark, libpino_probes.so."""
 
 from __future__ import annotations
 
@@ -9,6 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpino_collapse.so")
+PROBES = os.path.join(HERE, "libpino_probes.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -29,14 +31,18 @@ FLAGS = [
 LINK = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lhipfft"]
 
 
-def build(verbose: bool = False) -> str:
-    src = os.path.join(CSRC, "pino_collapse.hip")
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, src, "-o", tmp, *LINK]
+def _compile(src, out, link, verbose):
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, src, "-o", tmp, *link]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(os.path.join(CSRC, "pino_collapse.hip"), LIB, LINK, verbose)
+    _compile(os.path.join(CSRC, "probes.hip"), PROBES, [], verbose)
     return LIB
 
 
