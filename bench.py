@@ -71,7 +71,7 @@ def _time_steps(step, steps, stream):
 
 
 def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, steps, dk=None,
-                   updates=None, train_steps=TRAIN_STEPS, plain_ms=None):
+                   updates=None, train_steps=TRAIN_STEPS, plain_ms=None, blob_path=None, blob_out=None):
     """Secondary rates on the same resident fields: mixed precision (FP32
     copies of the Hessians) and the Tabulated method (64 x 64 x 128 tables
     filled per radius by the library's Classic kernel on the table's sample
@@ -114,7 +114,7 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
     mcol.close()
 
     out["surrogate"] = measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps,
-                                         train_steps)
+                                         train_steps, blob_path, blob_out)
     out["_blob"] = out["surrogate"].pop("blob")
     # stream floor: FP64 Hessians once per particle (the deferred particles'
     # second read by the block's tail is not counted)
@@ -368,19 +368,25 @@ def measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps, co
 
 
 def measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps,
-                      train_steps=TRAIN_STEPS):
+                      train_steps=TRAIN_STEPS, blob_path=None, blob_out=None):
     """Learned surrogate + certify on the same FP64 fields: train the network
     with the library's kernels on 20M (inputs, target) pairs from the
     benchmark fields and four perturbed cosmologies (untimed), then time the
     certified collapse.  Reports evals/s, the certified / full-solve / gated
     counts and the error against the plain FP64 run on the same Hessians
-    (the certificate bounds it by certify_rtol)."""
+    (the certificate bounds it by certify_rtol).  blob_path: take the network
+    from that file instead of training (profiling runs reuse the bench's
+    network); blob_out: write the trained network there."""
     import numpy as np
     import torch
 
     import synth
     from paper_2510_02873_amd import _abi, surrogate
 
+    if blob_path:
+        blob = open(blob_path, "rb").read()
+        return _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, steps,
+                               {"loaded_from": os.path.basename(blob_path)})
     t0 = time.time()
     om = cfg["cosmo"].omega_m
     perturbed = [synth.Cosmology(0.27, 0.8), synth.Cosmology(0.33, 0.8), synth.Cosmology(0.30, 0.75),
@@ -411,6 +417,20 @@ def measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R
                                     log=lambda m: log(m))
     train_s = time.time() - t1
     del x, w
+    if blob_out:
+        with open(blob_out, "wb") as f:
+            f.write(blob)
+    training = {"pairs": int(n_pairs), "steps": train_steps, "batch": 16384, "bf16_forward": True,
+                "seconds": round(train_s, 1), "final_loss": hist[-1][1] if hist else None}
+    return _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, steps, training)
+
+
+def _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, steps, training):
+    import numpy as np
+
+    from paper_2510_02873_amd import _abi
+    om = cfg["cosmo"].omega_m
+    n_side = round(n ** (1.0 / 3.0))
     last = len(radii) - 1
     scol = P.Collapse([(a, D, om)], precision=P.PINO_SURROGATE, mlp_blob=blob)
     Fs, Rs, As = scol.outputs(n)
@@ -440,8 +460,7 @@ def measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R
            "rel_Dc_vs_fp64_field": {"max": float(rel.max()), "p99.9": float(np.percentile(rel, 99.9)),
                                     "mean": float(rel.mean())},
            "index_mismatch_frac": float((Rs != R64).double().mean().item()),
-           "training": {"pairs": int(n_pairs), "steps": train_steps, "batch": 16384, "bf16_forward": True,
-                        "seconds": round(train_s, 1), "final_loss": hist[-1][1] if hist else None}}
+           "training": training}
     scol.close()
     log(f"surrogate+certify {res['value']:.3e} evals/s, fallback {res['fallback_fraction_of_consulted']:.3f} of "
         f"consulted, full solve {res['full_solve_fraction_of_all']:.3f} of all, max rel D_c vs fp64 "
@@ -697,6 +716,9 @@ def main():
     ap.add_argument("--n-side", type=int, default=None, help="override the grid side (testing only)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (mixed precision, Tabulated) on the same fields")
+    ap.add_argument("--save-blob", default=None, help="write the trained surrogate network to this file")
+    ap.add_argument("--load-blob", default=None,
+                    help="take the surrogate network from this file instead of training one (profiling runs)")
     ap.add_argument("--no-512", action="store_true",
                     help="skip the 512^3 x 40-radius mixed-precision and surrogate legs")
     ap.add_argument("--no-batched", action="store_true",
@@ -851,7 +873,8 @@ def main():
         roofline["measured_ceilings"] = {"error": str(e)[:200]}
     if not args.no_extras:
         extras = measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rmax, ac, args.steps, dk,
-                                updates, args.train_steps, plain_ms=ms_per_step)
+                                updates, args.train_steps, plain_ms=ms_per_step, blob_path=args.load_blob,
+                                blob_out=args.save_blob)
         blob = extras.pop("_blob", None)
 
     cpu = None

@@ -134,10 +134,14 @@ def _mean_counter(rows, counter, kernel):
     return float(np.mean(v)) if v else None
 
 
-def summarize(kernel, trace, fetch, write, calib_mib, out, command, flops=None, evals_per_launch=None):
+def summarize(kernel, trace, fetch, write, calib_mib, out, command, flops=None, evals_per_launch=None, extra=None):
     stats = _csv(trace, "kernel_stats.csv")
     ks = [r for r in stats if _named(kernel).search(r["Name"])]
-    lines = [f"# rocprofv3 summary: {kernel}", f"command: {command}", f"kernel_digest: {kernel_digest(kernel)}", ""]
+    try:
+        digest = kernel_digest(kernel)
+    except (KeyError, ValueError):
+        digest = "-"  # not in the collapse library (the benchmark's probes)
+    lines = [f"# rocprofv3 summary: {kernel}", f"command: {command}", f"kernel_digest: {digest}", ""]
     lines.append("kernel stats (--kernel-trace --stats):")
     for r in ks:
         lines.append(f"  {r['Name']}: calls={r['Calls']} total_ns={r['TotalDurationNs']} "
@@ -149,9 +153,11 @@ def summarize(kernel, trace, fetch, write, calib_mib, out, command, flops=None, 
         rows = _csv(d, "counter_collection.csv")
         kvals = _counter(rows, counter, kernel)
         # the calibration copy is the largest dispatch of a kernel named *copy*
+        # (torch's copy of calib_mib MiB); the benchmark's own copy probe has
+        # another size and is not it
         allv = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter]
         copies = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter
-                  and re.search("copy", r["Kernel_Name"], re.I)]
+                  and re.search("copy", r["Kernel_Name"], re.I) and not re.search("probe", r["Kernel_Name"])]
         ref = max(copies) if copies else max(allv)
         factor = calib_kib / ref
         per = np.array([v for v, _ in kvals]) * factor * 1024.0
@@ -187,6 +193,24 @@ def summarize(kernel, trace, fetch, write, calib_mib, out, command, flops=None, 
                 tail.append(f"valu_instructions_per_wave_of_64_evals: {c['SQ_INSTS_VALU'] * 64.0 / evals_per_launch:.1f}")
         if avg_ns:
             tail.append(f"fp64_TFLOPs_at_average_duration: {fl / avg_ns / 1e3:.3f}")
+    if extra:
+        # every counter of one more --pmc run, mean per dispatch of the kernel
+        rows = _csv(extra, "counter_collection.csv")
+        names = sorted({r["Counter_Name"] for r in rows})
+        vals = {k: _mean_counter(rows, k, kernel) for k in names}
+        lines.append("more counters (mean per dispatch): " + ", ".join(
+            f"{k}={v:.6e}" for k, v in vals.items() if v is not None))
+        waves = vals.get("SQ_WAVES")
+        if evals_per_launch:
+            for k in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD"):
+                if vals.get(k) is not None:
+                    tail.append(f"{k.lower()}_per_64_evals: {vals[k] * 64.0 / evals_per_launch:.1f}")
+        if vals.get("SQ_INSTS_VALU_MFMA_MOPS_BF16") is not None and avg_ns:
+            # MOPS counts 512-flop units of matrix work
+            tail.append(f"bf16_mfma_TFLOPs_at_average_duration: "
+                        f"{vals['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512.0 / avg_ns / 1e3:.3f}")
+        if waves:
+            tail.append(f"waves_per_dispatch: {waves:.0f}")
     lines += tail
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     with open(out, "w") as f:
@@ -194,7 +218,7 @@ def summarize(kernel, trace, fetch, write, calib_mib, out, command, flops=None, 
     print("\n".join(lines))
 
 
-def kernel_table(trace, out, command, pattern=r"pino::"):
+def kernel_table(trace, out, command, pattern=r"pino::|k_probe"):
     """Per-kernel duration statistics of one --kernel-trace --stats run, for
     every kernel whose name matches `pattern`, with each kernel's digest."""
     stats = _csv(trace, "kernel_stats.csv")
@@ -203,7 +227,8 @@ def kernel_table(trace, out, command, pattern=r"pino::"):
     for r in stats:
         if not re.search(pattern, r["Name"]):
             continue
-        short = re.sub(r"\(.*", "", r["Name"]).replace("pino::", "").replace("void ", "")
+        short = re.sub(r"\(.*", "", r["Name"].replace("(anonymous namespace)::", ""))
+        short = short.replace("pino::", "").replace("void ", "")
         try:
             dig = kernel_digest(short.split("<")[0].strip())
         except (KeyError, ValueError):
@@ -244,6 +269,7 @@ def main():
     s.add_argument("--command", default="")
     s.add_argument("--flops", default=None, help="rocprofv3 --pmc output of the FP64 counters")
     s.add_argument("--evals-per-launch", type=float, default=None)
+    s.add_argument("--extra", default=None, help="one more rocprofv3 --pmc output (any counters)")
     t = sub.add_parser("table")
     t.add_argument("--trace", required=True)
     t.add_argument("--out", required=True)
@@ -257,7 +283,8 @@ def main():
     if a.cmd == "table":
         kernel_table(a.trace, a.out, a.command)
         return
-    summarize(a.kernel, a.trace, a.fetch, a.write, a.calib_mib, a.out, a.command, a.flops, a.evals_per_launch)
+    summarize(a.kernel, a.trace, a.fetch, a.write, a.calib_mib, a.out, a.command, a.flops, a.evals_per_launch,
+              a.extra)
 
 
 if __name__ == "__main__":
