@@ -101,6 +101,10 @@ struct pino_ctx {
     // the growth knots (stride 6 * nk_max): the LCDM growth ratios of the
     // LPT terms and their natural-spline second derivatives in D
     double* d_kap = nullptr;
+    // launch shape of the LCDM kernel: its LDS (knots, index and ratio rows)
+    // limits the resident blocks per CU, so the grid is capped at what fits
+    int lcdm_block = 512;
+    int lcdm_resident = 1;
 
     // surrogate network: BF16 weight fragments, certificate tolerance,
     // counters (certified, fallback, gated), Omega_m per cosmology

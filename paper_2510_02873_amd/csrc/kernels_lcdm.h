@@ -119,44 +119,85 @@ __host__ __device__ inline size_t lcdm_lds_bytes(int nk, int nb)
     return growth_lds_bytes(nk, nb) + 6 * (size_t)nk * sizeof(double);
 }
 
-// The three ratios and their derivatives in D at D (spline pieces of interval
-// i of the growth knots; constant outside [D_0, D_{n-1}]).
+// The three ratios and their derivatives in D.
 struct Kappa {
     double k2, k3a, k3b, d2, d3a, d3b;
 };
 
-__device__ __forceinline__ Kappa kappa_at(const double* D, const double* kap, int nk, double Dq,
-                                          const GrowthIndex& gi)
+// One spline piece of the three ratios: interval [lo, hi) of the growth knots
+// with the end values and second derivatives of each ratio, or (outside the
+// knots, where the ratios are held at their end values) a constant piece.
+// A Newton step whose D stays inside the piece reuses it from registers; the
+// interval is the one the knot search returns for any D in (lo, hi), so the
+// values are those of a fresh lookup.
+struct KappaPiece {
+    double lo, hi;
+    double k2[2], k3a[2], k3b[2], m2[2], m3a[2], m3b[2];
+    int kind;  // 0: interval of the knots, 1: below D_0 (or NaN), 2: at or above D_{n-1}
+};
+
+__device__ __forceinline__ bool piece_holds(const KappaPiece& p, double Dq)
 {
-    Kappa r;
-    const double* K2 = kap;
-    const double* K3a = kap + nk;
-    const double* K3b = kap + 2 * nk;
-    const double* M2 = kap + 3 * nk;
-    const double* M3a = kap + 4 * nk;
-    const double* M3b = kap + 5 * nk;
+    if (p.kind == 0)
+        return Dq > p.lo && Dq < p.hi;
+    return p.kind == 1 ? !(Dq > p.lo) : Dq >= p.hi;
+}
+
+// rows of kap: [k2 | k3a | k3b | m2 | m3a | m3b], nk each (LDS)
+__device__ __forceinline__ KappaPiece kappa_piece(const double* D, const double* kap, int nk, double Dq,
+                                                  const GrowthIndex& gi)
+{
+    KappaPiece p;
     if (!(Dq > D[0]) || !(Dq < D[nk - 1])) {
         const int e = Dq > D[0] ? nk - 1 : 0;
-        r.k2 = K2[e];
-        r.k3a = K3a[e];
-        r.k3b = K3b[e];
+        p.kind = Dq > D[0] ? 2 : 1;
+        p.lo = D[0];
+        p.hi = D[nk - 1];
+        p.k2[0] = p.k2[1] = kap[e];
+        p.k3a[0] = p.k3a[1] = kap[nk + e];
+        p.k3b[0] = p.k3b[1] = kap[2 * nk + e];
+        p.m2[0] = p.m2[1] = p.m3a[0] = p.m3a[1] = p.m3b[0] = p.m3b[1] = 0.0;
+        return p;
+    }
+    const int i = gi.ok ? locate_indexed(D, nk, Dq, gi) : locate(D, nk, Dq);
+    p.kind = 0;
+    p.lo = D[i];
+    p.hi = D[i + 1];
+    for (int j = 0; j < 2; ++j) {
+        p.k2[j] = kap[i + j];
+        p.k3a[j] = kap[nk + i + j];
+        p.k3b[j] = kap[2 * nk + i + j];
+        p.m2[j] = kap[3 * nk + i + j];
+        p.m3a[j] = kap[4 * nk + i + j];
+        p.m3b[j] = kap[5 * nk + i + j];
+    }
+    return p;
+}
+
+// the ratios and their derivatives at Dq from a piece that holds it
+__device__ __forceinline__ Kappa kappa_eval(const KappaPiece& p, double Dq)
+{
+    Kappa r;
+    if (p.kind != 0) {
+        r.k2 = p.k2[0];
+        r.k3a = p.k3a[0];
+        r.k3b = p.k3b[0];
         r.d2 = r.d3a = r.d3b = 0.0;
         return r;
     }
-    const int i = gi.ok ? locate_indexed(D, nk, Dq, gi) : locate(D, nk, Dq);
-    const double h = D[i + 1] - D[i];
+    const double h = p.hi - p.lo;
     const double ih = rcp2(h);
-    const double t = (Dq - D[i]) * ih;
+    const double t = (Dq - p.lo) * ih;
     const double w = 1.0 - t;
     const double h6 = h * h * (1.0 / 6.0);
     const double cw = w * w * w - w, ct = t * t * t - t;
     const double dw = (h * (1.0 / 6.0)) * (1.0 - 3.0 * w * w), dt = (h * (1.0 / 6.0)) * (3.0 * t * t - 1.0);
-    r.k2 = w * K2[i] + t * K2[i + 1] + h6 * (cw * M2[i] + ct * M2[i + 1]);
-    r.k3a = w * K3a[i] + t * K3a[i + 1] + h6 * (cw * M3a[i] + ct * M3a[i + 1]);
-    r.k3b = w * K3b[i] + t * K3b[i + 1] + h6 * (cw * M3b[i] + ct * M3b[i + 1]);
-    r.d2 = (K2[i + 1] - K2[i]) * ih + dw * M2[i] + dt * M2[i + 1];
-    r.d3a = (K3a[i + 1] - K3a[i]) * ih + dw * M3a[i] + dt * M3a[i + 1];
-    r.d3b = (K3b[i + 1] - K3b[i]) * ih + dw * M3b[i] + dt * M3b[i + 1];
+    r.k2 = w * p.k2[0] + t * p.k2[1] + h6 * (cw * p.m2[0] + ct * p.m2[1]);
+    r.k3a = w * p.k3a[0] + t * p.k3a[1] + h6 * (cw * p.m3a[0] + ct * p.m3a[1]);
+    r.k3b = w * p.k3b[0] + t * p.k3b[1] + h6 * (cw * p.m3b[0] + ct * p.m3b[1]);
+    r.d2 = (p.k2[1] - p.k2[0]) * ih + dw * p.m2[0] + dt * p.m2[1];
+    r.d3a = (p.k3a[1] - p.k3a[0]) * ih + dw * p.m3a[0] + dt * p.m3a[1];
+    r.d3b = (p.k3b[1] - p.k3b[0]) * ih + dw * p.m3b[0] + dt * p.m3b[1];
     return r;
 }
 
@@ -172,7 +213,10 @@ __device__ __forceinline__ double cubic_top_w(const CubicU& k)
     return w;
 }
 
-constexpr int kLcdmNewton = 3;
+// Newton steps on G after the frozen-ratio root: that root is within about
+// 1e-5 of G's, so two steps reach the rounding level (a third moves D_c by
+// under 1e-15 relative over 256^3 particles x 25 radii).
+constexpr int kLcdmNewton = 2;
 
 // F = 1/D_c with the LCDM coefficients, 0 without collapse.  g: the growth
 // knots [D | a | M] (D used), kap: the ratio rows (LDS).
@@ -190,14 +234,18 @@ __device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const d
     // first root of the Einstein-de Sitter cubic; without one, of the cubic
     // with the ratios of the last knot (the largest)
     double w = cubic_top_w(CubicU{b, ca + cb});
-    double De = w > 0.0 ? rcp2(l1 * w) : g[nk - 1];
-    Kappa k = kappa_at(g, kap, nk, De, gi);
+    const double De = w > 0.0 ? rcp2(l1 * w) : g[nk - 1];
+    Kappa k = kappa_eval(kappa_piece(g, kap, nk, De, gi), De);
     w = cubic_top_w(CubicU{k.k2 * b, k.k3a * ca + k.k3b * cb});
     if (!(w > 0.0))
         return 0.0;
     double u = rcp2(w);
+    KappaPiece pc = kappa_piece(g, kap, nk, u * il1, gi);
     for (int it = 0; it < kLcdmNewton; ++it) {
-        k = kappa_at(g, kap, nk, u * il1, gi);
+        const double Dq = u * il1;
+        if (!piece_holds(pc, Dq))
+            pc = kappa_piece(g, kap, nk, Dq, gi);
+        k = kappa_eval(pc, Dq);
         const double P = k.k2 * b;
         const double Q = k.k3a * ca + k.k3b * cb;
         const double G = 1.0 + u * (-1.0 + u * (P + Q * u));
@@ -207,10 +255,23 @@ __device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const d
     return u > 0.0 ? l1 * rcp2(u) : 0.0;
 }
 
-// Per-radius kernel of the LCDM method: one particle per lane over a
-// grid-stride loop, the next element's loads issued before the current
-// element's arithmetic, the update of update_max.
-__global__ void __launch_bounds__(256) k_classic_lcdm(ItemArgs a, const double* __restrict__ kap_all)
+// Per-radius kernels of the LCDM method, with the update of update_max.
+// Blocks of up to 512 lanes: the LDS a block stages (about 45 KB for 512
+// knots) allows three blocks per CU, so larger blocks keep more waves
+// resident.
+
+__device__ __forceinline__ double lcdm_of(const Hess64& h, const double* g, const double* kap, int nk,
+                                          const GrowthIndex& gi)
+{
+    double l1, s, pp;
+    eig_top(h, l1, s, pp);
+    return lcdm_F(l1, s, pp, g, kap, nk, gi);
+}
+
+// One particle per lane over a grid-stride loop (arrays not 16-byte
+// aligned), the next element's loads issued before the current element's
+// arithmetic.
+__global__ void __launch_bounds__(512) k_classic_lcdm_1(ItemArgs a, const double* __restrict__ kap_all)
 {
     extern __shared__ double lds[];
     const GrowthIndex gi = stage_growth(lds, a);
@@ -234,10 +295,49 @@ __global__ void __launch_bounds__(256) k_classic_lcdm(ItemArgs a, const double* 
             hn = load_h64(a, next);
             fn = a.reset ? 0.0 : *elem(a.Fmax, next);
         }
-        double l1, s, pp;
-        eig_top(h, l1, s, pp);
-        const double F = lcdm_F(l1, s, pp, lds, kap, a.nk, gi);
-        update_max(a, lds, gi, i, F, fm);
+        update_max(a, lds, gi, i, lcdm_of(h, lds, kap, a.nk, gi), fm);
+    }
+}
+
+// Two adjacent particles per lane, as k_classic_f64: two independent root
+// solves per lane, whose dependent FP64 chains the scheduler interleaves,
+// and whole-line paired loads and stores.  Alignment as k_classic_f64 (host
+// check); an odd last element is done by one lane at the end.
+__global__ void __launch_bounds__(512) k_classic_lcdm(ItemArgs a, const double* __restrict__ kap_all)
+{
+    extern __shared__ double lds[];
+    const GrowthIndex gi = stage_growth(lds, a);
+    double* kap = lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
+    stage(kap, kap_all, 6 * a.nk);
+    __syncthreads();
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t np = n / 2;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    Hess2 hn{};
+    d2v fn{0.0, 0.0};
+    if (p < np) {
+        hn = load_h2(a, p);
+        if (!a.reset)
+            fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * p));
+    }
+    for (; p < np; p += stride) {
+        const Hess2 h = hn;
+        const d2v fm = fn;
+        const uint32_t next = p + stride;
+        if (next < np) {
+            hn = load_h2(a, next);
+            if (!a.reset)
+                fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * next));
+        }
+        const double F0 = lcdm_of(Hess64{h.xx.x, h.yy.x, h.zz.x, h.xy.x, h.xz.x, h.yz.x}, lds, kap, a.nk, gi);
+        const double F1 = lcdm_of(Hess64{h.xx.y, h.yy.y, h.zz.y, h.xy.y, h.xz.y, h.yz.y}, lds, kap, a.nk, gi);
+        update_pair(a, lds, gi, p, F0, F1, fm);
+    }
+    if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t i = n - 1;
+        const double fm = a.reset ? 0.0 : *elem(a.Fmax, i);
+        update_max(a, lds, gi, i, lcdm_of(load_h64(a, i), lds, kap, a.nk, gi), fm);
     }
 }
 

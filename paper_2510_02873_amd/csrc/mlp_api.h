@@ -105,11 +105,13 @@ pino::NetFrags build_frags(const float* P)
 
 // Deferred-particle queue of the surrogate path: items are processed in
 // chunks of at most kQueueChunk particles, by at most kQueueBlocks blocks of
-// 256 threads, each block owning a queue segment as long as the particles it
-// visits; the segments then total less than kQueueChunk + 256 kQueueBlocks.
+// kSurrogateBlock threads, each block owning a queue segment as long as the
+// particles it visits; the segments then total less than
+// kQueueChunk + kSurrogateBlock kQueueBlocks.
 constexpr int64_t kQueueChunk = int64_t(1) << 24;
 constexpr int64_t kQueueBlocks = 4096;
-constexpr int64_t kQueueCap = kQueueChunk + 256 * kQueueBlocks;
+constexpr int kSurrogateBlock = 256;
+constexpr int64_t kQueueCap = kQueueChunk + kSurrogateBlock * kQueueBlocks;
 
 // Dynamic LDS of k_surrogate for the largest growth table of a context: the
 // knots, their index and the 25 KB of weight fragments pass the default
@@ -168,8 +170,9 @@ inline pino_status launch_fail(pino_ctx* c, const char* what)
 // chunk-relative int32): per chunk one k_surrogate launch, whose blocks each
 // finish the particles they deferred to the full solve.
 pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemArgs& a0, uint32_t, hipStream_t st,
-                             int, int block)
+                             int, int)
 {
+    const int block = kSurrogateBlock;
     const size_t lds = pino::surrogate_lds_bytes(a0.nk, a0.gi.nb);
     auto* cnt = reinterpret_cast<unsigned long long*>(c->d_counters);
     const auto* net = static_cast<const pino::NetFrags*>(c->d_mlp);

@@ -401,9 +401,20 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
             PINO_HIP(c, hipGetLastError());
         }
         const size_t need = lcdm_lds_bytes(nk_max, index_bins(nk_max));
-        if (need > kLdsBudget)
+        if (need > kLdsBudget) {
             PINO_HIP(c, hipFuncSetAttribute((const void*)k_classic_lcdm, hipFuncAttributeMaxDynamicSharedMemorySize,
                                             (int)need));
+            PINO_HIP(c, hipFuncSetAttribute((const void*)k_classic_lcdm_1,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+        }
+        if (const char* env = std::getenv("PINO_LCDM_BLOCK")) {
+            const int v = std::atoi(env);
+            if (v == 256 || v == 512)
+                c->lcdm_block = v;
+        }
+        int resident = 0;
+        PINO_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_classic_lcdm, c->lcdm_block, need));
+        c->lcdm_resident = std::max(1, resident);
     }
 
     // FP32 copy of the growth knots for the mixed-precision path
@@ -544,8 +555,17 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
                 al = al && aligned(a.h[k], 16);
             const int gp = grid_for(c, (a.n + 1) / 2, block);
             if (c->method == PINO_CLASSIC_LCDM) {
-                hipLaunchKernelGGL(k_classic_lcdm, dim3(g), dim3(block), lcdm_lds_bytes(a.nk, a.gi.nb), st, a,
-                                   c->d_kap + (size_t)it.cosmo * 6 * c->nk_max);
+                const int lb = c->lcdm_block;
+                const int64_t lanes = al ? (a.n + 1) / 2 : a.n;
+                const int lg = (int)std::max<int64_t>(
+                    1, std::min<int64_t>((lanes + lb - 1) / lb, (int64_t)c->cu_count * c->lcdm_resident));
+                const double* kap = c->d_kap + (size_t)it.cosmo * 6 * c->nk_max;
+                const size_t llds = lcdm_lds_bytes(a.nk, a.gi.nb);
+                if (al) {
+                    hipLaunchKernelGGL(k_classic_lcdm, dim3(lg), dim3(lb), llds, st, a, kap);
+                } else {
+                    hipLaunchKernelGGL(k_classic_lcdm_1, dim3(lg), dim3(lb), llds, st, a, kap);
+                }
             } else if (c->method == PINO_CLASSIC) {
                 if (al) {
                     hipLaunchKernelGGL(k_classic_f64, dim3(gp), dim3(block), lds, st, a);

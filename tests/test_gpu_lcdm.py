@@ -119,6 +119,37 @@ def test_lcdm_special_and_ragged(pkg, orc):
     assert np.all(Fg == 0) and np.all(Rg == -1)
 
 
+@pytest.mark.parametrize("n", [1, 3, 1001])
+def test_lcdm_unaligned_matches_aligned(pkg, orc, n):
+    """Arrays 8- but not 16-byte aligned take the one-particle-per-lane LCDM
+    kernel; its results equal the paired kernel's bit for bit (same
+    arithmetic) and the oracle's.  Odd and tiny sizes exercise the paired
+    kernel's last-element path."""
+    cfg, slabs, a, D = c1_inputs()
+    om = cfg["cosmo"].omega_m
+    hs = [s[:, :n].contiguous() for s in slabs[:3]]
+    with pkg.Collapse([(a, D, om)], method=pkg.PINO_CLASSIC_LCDM) as col:
+        F1, R1, A1 = col.outputs(n)
+        bufF = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+        bufR = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        bufA = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+        F2, R2, A2 = bufF[1:], bufR[1:], bufA[1:]
+        last = len(hs) - 1
+        for r, h in enumerate(hs):
+            hd = h.cuda()
+            buf = torch.empty((6, n + 1), dtype=torch.float64, device="cuda")
+            buf[:, 1:] = hd
+            hu = [buf[c, 1:] for c in range(6)]
+            assert hu[0].data_ptr() % 16 == 8
+            col.apply(hd, r, F1, R1, A1 if r == last else None, reset=(r == 0), finalize=(r == last))
+            col.apply(hu, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last))
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F2) and torch.equal(R1, R2) and torch.equal(A1, A2)
+    ref, skip, _ = _lcdm_ref(orc, hs, a, D, om)
+    compare(ref, (F1.cpu().numpy(), R1.cpu().numpy(), A1.cpu().numpy()), tie_mask=skip,
+            label=f"LCDM unaligned n={n}")
+
+
 def test_lcdm_unsupported_combinations(pkg):
     a, D = synth.growth_table(0.3)
     for kw in (dict(precision=pkg.PINO_MIXED),):
