@@ -151,8 +151,9 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                                          "from L2/MALL (8.4 MB table)"}
     tcol.close()
 
-    # Tabulated in mixed precision: FP32 Hessians, FP32 knot-pair table (four
-    # 16-byte corner reads per evaluation), FP64 interpolation arithmetic
+    # Tabulated in mixed precision: FP32 Hessians, FP32 eigenvalues (FP64 for
+    # nearly repeated pairs), FP32 cell search and interpolation on the FP32
+    # knot-pair table (four 16-byte corner reads per evaluation)
     mtcol = P.Collapse([(a, D)], method=P.PINO_TABULATED, precision=P.PINO_MIXED, table_knots=knots)
     Fq, Rq, Aq = mtcol.outputs(n)
     qitems = [mtcol.item(s32[r], Fq, Rq, Aq if r == last else None, radius_index=r, sigma_R=sig[r],
@@ -166,7 +167,8 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
     relq = ((Fq[both] - Ft[both]).abs() / Ft[both]).cpu().numpy()
     out["tabulated_mixed"] = {"value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s",
                               "ms_per_step": round(ms, 4),
-                              "dtype": "f32 inputs and table, f64 eigen/search/interpolation",
+                              "dtype": "f32 inputs, eigenvalues, search, interpolation and table; f64 for nearly "
+                                       "repeated pairs",
                               "rel_F_vs_fp64_tabulated": {"max": float(relq.max()),
                                                           "p99.9": float(np.percentile(relq, 99.9)),
                                                           "mean": float(relq.mean())},

@@ -42,6 +42,39 @@ __host__ __device__ __forceinline__ bool eig_top_f32(const Hess32& h, float& l1,
     return 1.0f + r >= kNearRepeated32;
 }
 
+// All three eigenvalues in FP32, descending: l1 and l3 from the closed form
+// (the smallest root of x^3 - 3x = 2r is minus the largest root for -r), l2
+// from the trace.  Returns false when a pair is nearly repeated at either end
+// of r (1 -/+ r below kNearRepeated32), where the FP32 closed form loses the
+// pair's digits; the FP64 path (eig_all, with its deflation) decides those.
+__host__ __device__ __forceinline__ bool eig_all_f32(const Hess32& h, float& l1, float& l2, float& l3)
+{
+    const float tr = h.xx + h.yy + h.zz;
+    const float q = tr * (1.0f / 3.0f);
+    const float dx = h.xx - q, dy = h.yy - q, dz = h.zz - q;
+    const float off = h.xy * h.xy + h.xz * h.xz + h.yz * h.yz;
+    const float ss = dx * dx + dy * dy + dz * dz + 2.0f * off;
+    const float p = sqrtf(ss * (1.0f / 6.0f));
+    const float det = dx * (dy * dz - h.yz * h.yz) - h.xy * (h.xy * dz - h.yz * h.xz) + h.xz * (h.xy * h.yz - dy * h.xz);
+    const float ip = p > 0.0f ? 1.0f / p : 0.0f;
+    float r = 0.5f * det * (ip * ip * ip);
+    r = fminf(fmaxf(r, -1.0f), 1.0f);
+    l1 = q + 2.0f * p * cos_acos3(0.5f + 0.5f * r);
+    l3 = q - 2.0f * p * cos_acos3(0.5f - 0.5f * r);
+    l2 = fminf(fmaxf(tr - l1 - l3, l3), l1);
+    return 1.0f + r >= kNearRepeated32 && 1.0f - r >= kNearRepeated32;
+}
+
+// Natural-spline piece in FP32 (as spline_piece).
+__host__ __device__ __forceinline__ float spline_piece32(float x0, float x1, float y0, float y1, float m0, float m1,
+                                                  float q)
+{
+    const float h = x1 - x0;
+    const float t = (q - x0) / h;
+    const float w = 1.0f - t;
+    return w * y0 + t * y1 + (h * h * (1.0f / 6.0f)) * ((w * w * w - w) * m0 + (t * t * t - t) * m1);
+}
+
 // a(D) through the natural spline with FP32 knots [D | a | M] (n each) and the
 // same interval index as the FP64 path.
 __host__ __device__ __forceinline__ int locate32(const float* x, int n, float q)

@@ -194,13 +194,13 @@ __host__ __device__ inline size_t growth32_lds_bytes(int nk, int nb)
 }
 
 // ---------------------------------------------------------------------------
-// Mixed-precision Tabulated kernels: FP32 Hessians (24 B per particle),
-// widened to FP64 for the eigenvalues and the cell search, and an FP32 copy
-// of the table in which each (row, knot interval j) holds the 16-byte tuple
+// Mixed-precision Tabulated kernels: FP32 Hessians (24 B per particle), FP32
+// eigenvalues (the FP64 path for nearly repeated pairs), the cell search in
+// FP32 copies of the scaled knots, and FP32 interpolation on an FP32 copy of
+// the table in which each (row, knot interval j) holds the 16-byte tuple
 // (F_j, M_j, F_{j+1}, M_{j+1}), so one corner spline is one 16-byte read
-// (four per particle instead of eight).  The interpolation arithmetic is
-// FP64 on the FP32 table values; a(D) from the FP32 growth knots, as in the
-// mixed Classic kernel.
+// (four per particle instead of eight); a(D) from the FP32 growth knots, as
+// in the mixed Classic kernel.
 // ---------------------------------------------------------------------------
 
 // tab32[r (nd - 1) + j] = (F_j, M_j, F_{j+1}, M_{j+1}) of row r, from the
@@ -217,8 +217,100 @@ __global__ void __launch_bounds__(256) k_table_pairs_f32(const double* __restric
     tab32[k] = f4v{(float)s[0], (float)s[1], (float)s[2], (float)s[3]};
 }
 
+// FP32 copies of the scaled knots [x | y | delta], then the interval index
+// (at most table_lds_bytes(t) bytes)
+__device__ __forceinline__ const int* stage_table32(float* base, const TabArgs& t)
+{
+    float* xs = base;
+    float* ys = xs + t.nx;
+    float* ds = ys + t.ny;
+    int* idx = reinterpret_cast<int*>(ds + t.nd);
+    for (int k = threadIdx.x; k < t.nx; k += blockDim.x)
+        xs[k] = (float)(t.xk[k] * t.scale);
+    for (int k = threadIdx.x; k < t.ny; k += blockDim.x)
+        ys[k] = (float)(t.yk[k] * t.scale);
+    for (int k = threadIdx.x; k < t.nd; k += blockDim.x)
+        ds[k] = (float)(t.dk[k] * t.scale);
+    if (t.indexed)
+        for (int k = threadIdx.x; k < t.nb[0] + t.nb[1] + t.nb[2]; k += blockDim.x)
+            idx[k] = t.bidx[k];
+    return idx;
+}
+
+// locate_after and table_locate on FP32 knots.  The index bins carry a margin
+// of 1 % of a bin, far above the FP32 rounding of the bin arithmetic and of
+// the knots, so the bin's interval is never past the query's.
+__device__ __forceinline__ int locate_after32(const float* xs, int n, float q, int i)
+{
+    constexpr int K = kIndexCompares;
+    float xv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        xv[k] = xs[min(i + 1 + k, n - 1)];
+    int r = i, c = 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        c = c & ((i + 1 + k <= n - 2 && xv[k] <= q) ? 1 : 0);
+        r += c;
+    }
+    return r;
+}
+
+__device__ __forceinline__ int table_locate32(const TabArgs& t, int axis, const int* idx, const float* xs, int n,
+                                              float q)
+{
+    if (!t.indexed)
+        return locate32(xs, n, q);
+    float fb = (q * (float)t.inv_scale - (float)t.k0[axis]) * (float)t.bpu[axis];
+    fb = fminf(fmaxf(fb, 0.0f), (float)(t.nb[axis] - 1));
+    return locate_after32(xs, n, q, idx[(int)fb]);
+}
+
+struct TabQ32 {
+    uint32_t rp;  // (row (nd - 1) + j) in the knot-pair table
+    float tt, uu, d0, d1, dq;
+};
+
+__device__ __forceinline__ TabQ32 table_query32(const TabArgs& t, const float* xs, const float* ys, const float* ds,
+                                                const int* idx, float x, float y, float delta)
+{
+    const int ix = table_locate32(t, 0, idx, xs, t.nx, x);
+    const int iy = table_locate32(t, 1, idx + t.nb[0], ys, t.ny, y);
+    TabQ32 q;
+    q.tt = fminf(fmaxf((x - xs[ix]) / (xs[ix + 1] - xs[ix]), 0.0f), 1.0f);
+    q.uu = fminf(fmaxf((y - ys[iy]) / (ys[iy + 1] - ys[iy]), 0.0f), 1.0f);
+    q.dq = fminf(fmaxf(delta, ds[0]), ds[t.nd - 1]);
+    const int j = table_locate32(t, 2, idx + t.nb[0] + t.nb[1], ds, t.nd, q.dq);
+    q.d0 = ds[j];
+    q.d1 = ds[j + 1];
+    q.rp = (uint32_t)((ix * t.ny + iy) * (t.nd - 1) + j);
+    return q;
+}
+
+// The cell of a particle from its FP32 Hessian: x = l1 - l2, y = l2 - l3 from
+// the FP32 eigenvalues (FP64 for nearly repeated pairs, rounded to FP32
+// after the differences), delta = the FP32 trace.
+__device__ __forceinline__ TabQ32 tabulated_query32(const TabArgs& t, const float* xs, const float* ys,
+                                                    const float* ds, const int* idx, const Hess32& h, bool& finite)
+{
+    float l1, l2, l3, x, y;
+    if (eig_all_f32(h, l1, l2, l3)) {
+        x = l1 - l2;
+        y = l2 - l3;
+    } else {
+        double e1, e2, e3;
+        eig_all(widen(h), e1, e2, e3);
+        l1 = (float)e1;
+        x = (float)(e1 - e2);
+        y = (float)(e2 - e3);
+    }
+    const float delta = h.xx + h.yy + h.zz;
+    finite = isfinite(x) && isfinite(y) && isfinite(delta) && isfinite(l1);
+    return table_query32(t, xs, ys, ds, idx, x, y, delta);
+}
+
 // corners (ix, iy), (ix, iy + 1), (ix + 1, iy), (ix + 1, iy + 1)
-__device__ __forceinline__ void table_load32(const TabArgs& t, const f4v* __restrict__ tab32, const TabQ& q,
+__device__ __forceinline__ void table_load32(const TabArgs& t, const f4v* __restrict__ tab32, const TabQ32& q,
                                              f4v (&c)[4])
 {
     const f4v* p = tab32 + q.rp;
@@ -230,27 +322,27 @@ __device__ __forceinline__ void table_load32(const TabArgs& t, const f4v* __rest
     c[3] = p[sx + sy];
 }
 
-__device__ __forceinline__ double table_eval32(const TabQ& q, const f4v (&c)[4])
+__device__ __forceinline__ float table_eval32(const TabQ32& q, const f4v (&c)[4])
 {
-    const double v00 = spline_piece(q.d0, q.d1, c[0].x, c[0].z, c[0].y, c[0].w, q.dq);
-    const double v01 = spline_piece(q.d0, q.d1, c[1].x, c[1].z, c[1].y, c[1].w, q.dq);
-    const double v10 = spline_piece(q.d0, q.d1, c[2].x, c[2].z, c[2].y, c[2].w, q.dq);
-    const double v11 = spline_piece(q.d0, q.d1, c[3].x, c[3].z, c[3].y, c[3].w, q.dq);
-    const double tt = q.tt, uu = q.uu;
-    const double f = (1.0 - tt) * (1.0 - uu) * v00 + tt * (1.0 - uu) * v10 + (1.0 - tt) * uu * v01 + tt * uu * v11;
-    return f > 0.0 ? f : 0.0;
+    const float v00 = spline_piece32(q.d0, q.d1, c[0].x, c[0].z, c[0].y, c[0].w, q.dq);
+    const float v01 = spline_piece32(q.d0, q.d1, c[1].x, c[1].z, c[1].y, c[1].w, q.dq);
+    const float v10 = spline_piece32(q.d0, q.d1, c[2].x, c[2].z, c[2].y, c[2].w, q.dq);
+    const float v11 = spline_piece32(q.d0, q.d1, c[3].x, c[3].z, c[3].y, c[3].w, q.dq);
+    const float tt = q.tt, uu = q.uu;
+    const float f = (1.0f - tt) * (1.0f - uu) * v00 + tt * (1.0f - uu) * v10 + (1.0f - tt) * uu * v01 + tt * uu * v11;
+    return f > 0.0f ? f : 0.0f;
 }
 
 __device__ __forceinline__ double tabulated_mixed_of(const TabArgs& t, const f4v* __restrict__ tab32,
-                                                    const double* xs, const double* ys, const double* ds,
+                                                    const float* xs, const float* ys, const float* ds,
                                                     const int* idx, const Hess32& h)
 {
     bool finite;
-    const TabQ q = tabulated_query(t, xs, ys, ds, idx, widen(h), finite);
+    const TabQ32 q = tabulated_query32(t, xs, ys, ds, idx, h, finite);
     f4v c[4];
     table_load32(t, tab32, q, c);
-    const double F = table_eval32(q, c);
-    return finite ? F : 0.0;
+    const float F = table_eval32(q, c);
+    return finite ? (double)F : 0.0;
 }
 
 // One particle per lane (FP32 components not 8-byte aligned).
@@ -260,10 +352,10 @@ __global__ void __launch_bounds__(256) k_tabulated_mixed_1(ItemArgs a, TabArgs t
     extern __shared__ double lds[];
     float* g = reinterpret_cast<float*>(lds);
     const GrowthIndex gi = stage_growth32(g, growth32, a);
-    double* xs = lds + growth32_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
-    double* ys = xs + t.nx;
-    double* ds = ys + t.ny;
-    const int* idx = stage_table(xs, t);
+    float* xs = g + growth32_lds_bytes(a.nk, a.gi.nb) / sizeof(float);
+    float* ys = xs + t.nx;
+    float* ds = ys + t.ny;
+    const int* idx = stage_table32(xs, t);
     __syncthreads();
     const uint32_t n = (uint32_t)a.n;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -294,10 +386,10 @@ __global__ void __launch_bounds__(256) k_tabulated_mixed(ItemArgs a, TabArgs t, 
     extern __shared__ double lds[];
     float* g = reinterpret_cast<float*>(lds);
     const GrowthIndex gi = stage_growth32(g, growth32, a);
-    double* xs = lds + growth32_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
-    double* ys = xs + t.nx;
-    double* ds = ys + t.ny;
-    const int* idx = stage_table(xs, t);
+    float* xs = g + growth32_lds_bytes(a.nk, a.gi.nb) / sizeof(float);
+    float* ys = xs + t.nx;
+    float* ds = ys + t.ny;
+    const int* idx = stage_table32(xs, t);
     __syncthreads();
     const uint32_t n = (uint32_t)a.n;
     const uint32_t np = n / 2;
@@ -322,16 +414,16 @@ __global__ void __launch_bounds__(256) k_tabulated_mixed(ItemArgs a, TabArgs t, 
         if (p + stride < np)
             load(p + stride);
         bool f0, f1;
-        const TabQ q0 =
-            tabulated_query(t, xs, ys, ds, idx, widen(Hess32{h[0].x, h[1].x, h[2].x, h[3].x, h[4].x, h[5].x}), f0);
-        const TabQ q1 =
-            tabulated_query(t, xs, ys, ds, idx, widen(Hess32{h[0].y, h[1].y, h[2].y, h[3].y, h[4].y, h[5].y}), f1);
+        const TabQ32 q0 =
+            tabulated_query32(t, xs, ys, ds, idx, Hess32{h[0].x, h[1].x, h[2].x, h[3].x, h[4].x, h[5].x}, f0);
+        const TabQ32 q1 =
+            tabulated_query32(t, xs, ys, ds, idx, Hess32{h[0].y, h[1].y, h[2].y, h[3].y, h[4].y, h[5].y}, f1);
         f4v c0[4], c1[4];
         table_load32(t, tab32, q0, c0);
         table_load32(t, tab32, q1, c1);
-        const double F0 = table_eval32(q0, c0);
-        const double F1 = table_eval32(q1, c1);
-        update_pair_f32(a, g, gi, p, f0 ? F0 : 0.0, f1 ? F1 : 0.0, fm);
+        const float F0 = table_eval32(q0, c0);
+        const float F1 = table_eval32(q1, c1);
+        update_pair_f32(a, g, gi, p, f0 ? (double)F0 : 0.0, f1 ? (double)F1 : 0.0, fm);
     }
     if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t i = n - 1;

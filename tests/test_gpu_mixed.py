@@ -1,7 +1,8 @@
 """Mixed-precision paths against the FP64 oracle.  Classic: FP32 Hessians
 and eigenvalues, FP64 root polish and nearly-repeated branch, FP32 growth
-interpolation.  Tabulated: FP32 Hessians, FP32 copy of the table (gated by
-the bound its rounding sets), FP64 interpolation arithmetic.
+interpolation.  Tabulated: FP32 Hessians, FP32 eigenvalues (FP64 for nearly
+repeated pairs), FP32 cell search and interpolation on an FP32 copy of the
+table, gated per particle by the bound derived in _tab32_bound.
 
 The oracle runs on the same inputs the kernel reads (the FP32 Hessians
 widened to FP64), which isolates the arithmetic error, and on the original
@@ -98,17 +99,65 @@ def test_mixed_special_and_ragged(pkg, orc):
         assert np.array_equal(R, R0)
 
 
-def _tab32_bound(orc, tables):
-    """Bound on |F_mixed - F_oracle| from rounding the table to FP32: the
-    interpolant is linear in the table values, with weights (1 - t), t and
-    h^2/6 ((1-t)^3 - (1-t)) etc. (|.| <= 0.385 h^2/6) inside convex bilinear
-    weights, so |dF| <= 2^-24 (max|F| + 0.1284 h^2 max|M|) over the cell; the
-    maximum over radii is 1-Lipschitz."""
-    b = 0.0
-    for t in tables:
-        h = np.max(np.diff(t.dk))
-        b = max(b, EPS32 * (np.max(np.abs(t.F)) + 0.1284 * h * h * np.max(np.abs(t.M))))
-    return 1.01 * b
+def _table_lipschitz(t):
+    """Bounds on |dF/dx|, |dF/dy| and |dF/ddelta| of the interpolant of one
+    oracle table (knots in the kernel's units).  Along delta each row is a
+    natural spline: on [d_i, d_i+1], S' = slope_i + h/6 ((1 - 3A^2) M_i +
+    (3B^2 - 1) M_i+1) with A + B = 1 in [0, 1], so |S'| <= |slope_i| +
+    h/3 (|M_i| + |M_i+1|).  Across x (and y) the interpolant is linear in the
+    corner rows; the difference of two rows is the natural spline of the
+    differences, whose piece is the chord plus h^2/6 ((A^3 - A) dM_i +
+    (B^3 - B) dM_i+1), |A^3 - A| <= 0.385, so sup|S_b - S_a| over an interval
+    <= max(|dF_i|, |dF_i+1|) + 0.0642 h^2 (|dM_i| + |dM_i+1|)."""
+    F, M = t.F, t.M
+    h = np.diff(t.dk)
+
+    def row_diff_sup(dF, dM):
+        a = np.maximum(np.abs(dF[..., :-1]), np.abs(dF[..., 1:]))
+        return np.max(a + 0.0642 * h * h * (np.abs(dM[..., :-1]) + np.abs(dM[..., 1:])))
+
+    Lx = max(row_diff_sup(F[i + 1] - F[i], M[i + 1] - M[i]) / (t.xk[i + 1] - t.xk[i])
+             for i in range(len(t.xk) - 1))
+    Ly = max(row_diff_sup(F[:, j + 1] - F[:, j], M[:, j + 1] - M[:, j]) / (t.yk[j + 1] - t.yk[j])
+             for j in range(len(t.yk) - 1))
+    slope = np.diff(F, axis=2) / h
+    Ld = np.max(np.abs(slope) + h / 3 * (np.abs(M[..., :-1]) + np.abs(M[..., 1:])))
+    return Lx, Ly, Ld
+
+
+def _tab32_bound(orc, tables, slabs):
+    """Per-particle bound on |F_mixed - F_oracle| (the oracle on the FP32
+    inputs widened to FP64), the maximum over radii of (the maximum is
+    1-Lipschitz):
+      - the table rounded to FP32: the interpolant is linear in the table
+        values with weights (1 - t), t and h^2/6 ((1-t)^3 - (1-t)) etc.
+        (|.| <= 0.385 h^2/6) inside convex bilinear weights, so
+        eps (max|F| + 0.1284 h^2 max|M|);
+      - the FP32 spline and bilinear arithmetic: a few roundings of terms of
+        that size, taken as 10 eps (max|F| + 0.1284 h^2 max|M|);
+      - the cell coordinates: each FP32 eigenvalue is within 64 eps |H|_F
+        outside the nearly repeated band (the FP64 path decides inside it;
+        a host build of the same FP32 code reaches 44 eps |H|_F on 2.4M
+        matrices with gaps down to 1e-4 of the scale), so x = l1 - l2 and
+        y = l2 - l3 move by <= 128 eps |H|_F, rounded to FP32 within
+        another 4 eps |H|_F and 2 eps |H|_F of FP32 trace; the FP32 knots
+        and the cell fractions add 4 eps max|knot| per axis; each moves F by
+        the axis' Lipschitz bound (_table_lipschitz) times the shift."""
+    b = None
+    for h, t in zip(slabs, tables):
+        h = np.asarray(h, dtype=np.float64)
+        with np.errstate(invalid="ignore", over="ignore"):
+            hn = np.sqrt(np.sum(h[:3] ** 2, axis=0) + 2 * np.sum(h[3:] ** 2, axis=0))
+        hn[~np.isfinite(hn)] = 0.0   # non-finite input: F = 0 on both sides
+        hmax = np.max(np.diff(t.dk))
+        base = 11 * EPS32 * (np.max(np.abs(t.F)) + 0.1284 * hmax * hmax * np.max(np.abs(t.M)))
+        Lx, Ly, Ld = _table_lipschitz(t)
+        dx = 132 * EPS32 * hn + 4 * EPS32 * np.max(np.abs(t.xk))
+        dy = 132 * EPS32 * hn + 4 * EPS32 * np.max(np.abs(t.yk))
+        dd = 4 * EPS32 * hn + 4 * EPS32 * np.max(np.abs(t.dk))
+        br = 1.01 * (base + Lx * dx + Ly * dy + Ld * dd)
+        b = br if b is None else np.maximum(b, br)
+    return b
 
 
 def _mixed_tab_run(pkg, orc, knots, slabs32, sigmas, a, D, col_kw=None):
@@ -136,14 +185,16 @@ def _mixed_tab_run(pkg, orc, knots, slabs32, sigmas, a, D, col_kw=None):
                       finalize=(r == last), sigma_R=s, table_F=tF)
         torch.cuda.synchronize()
         got = (Fm.cpu().numpy(), Rm.cpu().numpy(), ac.cpu().numpy())
-    return ref, got, np.stack(per_r), _tab32_bound(orc, tabs)
+    return ref, got, np.stack(per_r), _tab32_bound(orc, tabs, widened)
 
 
 def _check_mixed_tab(ref, got, per_r, b, label):
     Fr, Rr, Ar = ref
     F, R, A = got
+    b = np.broadcast_to(np.asarray(b, dtype=np.float64), Fr.shape)
     dF = np.abs(F - Fr)
-    print(f"{label}: |dF| max {dF.max():.2e} (bound {b:.2e}), index mismatches {int(np.sum(R != Rr))}", flush=True)
+    print(f"{label}: |dF| max {dF.max():.2e} (bound: median {np.median(b):.2e}, min {np.min(b):.2e}; "
+          f"largest |dF|/bound {np.max(dF / b):.3f}), index mismatches {int(np.sum(R != Rr))}", flush=True)
     assert np.all(dF <= b + 1e-12 * np.abs(Fr)), f"{label}: worst excess {np.max(dF - b):.3e}"
     # radius index: exact unless the top two radii are within the bound (or F ~ 0)
     srt = np.sort(per_r, axis=0)
@@ -151,10 +202,11 @@ def _check_mixed_tab(ref, got, per_r, b, label):
     close = (np.abs(srt[-1] - second) <= 2 * b) | (np.abs(Fr) <= b)
     assert np.all((R == Rr) | close)
     fin = np.isfinite(Ar) & np.isfinite(A)
-    assert np.array_equal(np.isfinite(Ar), np.isfinite(A)) or np.all(np.abs(Fr[np.isfinite(Ar) != np.isfinite(A)]) <= b)
+    odd = np.isfinite(Ar) != np.isfinite(A)
+    assert np.all(np.abs(Fr[odd]) <= b[odd])
     big = fin & (Fr > 1e3 * b)
     ra = np.abs(A[big] - Ar[big]) / Ar[big]
-    tol = b / Fr[big] + 16 * EPS32
+    tol = b[big] / Fr[big] + 16 * EPS32
     assert np.all(ra <= tol), f"{label}: a_coll worst excess {np.max(ra - tol):.3e}"
 
 

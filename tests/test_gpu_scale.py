@@ -112,8 +112,8 @@ def test_256cube_25radii_tabulated_sampled(orc):
     The tables are filled by the oracle's Classic solve at their sample
     points; the oracle then interpolates them for a seeded sample of
     particles.  Gates: FP64, the plain-path gate (1e-9 relative, index exact
-    outside near-ties); mixed, the FP32-table bound against the oracle on the
-    FP32 inputs widened to FP64."""
+    outside near-ties); mixed, the per-particle FP32 bound of the mixed tests
+    against the oracle on the FP32 inputs widened to FP64."""
     import paper_2510_02873_amd as P
     from tests._helpers import compare, near_tie_mask
     from tests.test_gpu_mixed import _check_mixed_tab, _tab32_bound
@@ -172,7 +172,7 @@ def test_256cube_25radii_tabulated_sampled(orc):
 
     st = compare(ref64, g64, tie_mask=near_tie_mask(per_radius(s64)), label="tabulated 256^3 sample")
     print("tabulated 256^3 x 25 sample (FP64)", st, flush=True)
-    _check_mixed_tab(ref32, g32, per_radius(s32), _tab32_bound(orc, tabs), "tabulated 256^3 sample (mixed)")
+    _check_mixed_tab(ref32, g32, per_radius(s32), _tab32_bound(orc, tabs, s32), "tabulated 256^3 sample (mixed)")
 
 
 def test_c4_batched_full_size_sampled(orc):
