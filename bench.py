@@ -221,6 +221,17 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                                                            "max": float(shift.max())},
                            "roofline": step_roofline(step_bytes(48), ms)}
     lcol.close()
+    lcdm_ms = ms
+
+    # the surrogate on the LCDM condition: network trained on LCDM targets of
+    # the five cosmologies (its Omega_m input now matters), LCDM certificate
+    # and full solve, against the plain LCDM run on the same fields
+    sl = measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, Fl, Rl, steps, train_steps,
+                           method=P.PINO_CLASSIC_LCDM)
+    sl.pop("blob")
+    sl["roofline"] = step_roofline(step_bytes(48), sl["ms_per_step"])
+    sl["vs_plain_lcdm_throughput"] = round(lcdm_ms / sl["ms_per_step"], 4)
+    out["surrogate_lcdm"] = sl
     del Fl, Rl, Al
 
     if dk is not None:
@@ -370,7 +381,7 @@ def measure_field(P, col, dk, radii, n, n_side, cfg, stream, F64, R64, steps, co
 
 
 def measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps,
-                      train_steps=TRAIN_STEPS, blob_path=None, blob_out=None):
+                      train_steps=TRAIN_STEPS, blob_path=None, blob_out=None, method=None):
     """Learned surrogate + certify on the same FP64 fields: train the network
     with the library's kernels on 20M (inputs, target) pairs from the
     benchmark fields and four perturbed cosmologies (untimed), then time the
@@ -378,17 +389,21 @@ def measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R
     counts and the error against the plain FP64 run on the same Hessians
     (the certificate bounds it by certify_rtol).  blob_path: take the network
     from that file instead of training (profiling runs reuse the bench's
-    network); blob_out: write the trained network there."""
+    network); blob_out: write the trained network there.  method: the
+    collapse condition (PINO_CLASSIC by default; with PINO_CLASSIC_LCDM the
+    targets, the certificate and the full solve are the LCDM ones, and F64,
+    R64 the plain LCDM run)."""
     import numpy as np
     import torch
 
     import synth
     from paper_2510_02873_amd import _abi, surrogate
 
+    method = P.PINO_CLASSIC if method is None else method
     if blob_path:
         blob = open(blob_path, "rb").read()
         return _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, steps,
-                               {"loaded_from": os.path.basename(blob_path)})
+                               {"loaded_from": os.path.basename(blob_path)}, method)
     t0 = time.time()
     om = cfg["cosmo"].omega_m
     perturbed = [synth.Cosmology(0.27, 0.8), synth.Cosmology(0.33, 0.8), synth.Cosmology(0.30, 0.75),
@@ -398,13 +413,13 @@ def measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R
     n_slabs = len(pick) + 2 * len(perturbed)
     per = 20_000_000 // n_slabs + 1
     fields = [(slabs[r], sig[r], 0) for r in pick]
-    x0, w0 = surrogate.training_pairs(fields, tables, per_slab=per)
+    x0, w0 = surrogate.training_pairs(fields, tables, per_slab=per, method=method)
     xs, ws = [x0], [w0]
     for k, c in enumerate(perturbed):
         fld = synth.fields.field(n_side, cfg["box"], 51 + k, c, device=slabs[0].device)
         sp = synth.grid_sigma_gauss(n_side, cfg["box"], [4.0, 1.0], c)
         pf = [(fld.hessian(R), sR, k + 1) for R, sR in zip([4.0, 1.0], sp)]
-        x, w = surrogate.training_pairs(pf, tables, per_slab=per)
+        x, w = surrogate.training_pairs(pf, tables, per_slab=per, method=method)
         xs.append(x)
         ws.append(w)
         del fld, pf
@@ -424,17 +439,17 @@ def measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R
             f.write(blob)
     training = {"pairs": int(n_pairs), "steps": train_steps, "batch": 16384, "bf16_forward": True,
                 "seconds": round(train_s, 1), "final_loss": hist[-1][1] if hist else None}
-    return _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, steps, training)
+    return _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, steps, training, method)
 
 
-def _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, steps, training):
+def _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, steps, training, method):
     import numpy as np
 
     from paper_2510_02873_amd import _abi
     om = cfg["cosmo"].omega_m
     n_side = round(n ** (1.0 / 3.0))
     last = len(radii) - 1
-    scol = P.Collapse([(a, D, om)], precision=P.PINO_SURROGATE, mlp_blob=blob)
+    scol = P.Collapse([(a, D, om)], method=method, precision=P.PINO_SURROGATE, mlp_blob=blob)
     Fs, Rs, As = scol.outputs(n)
     items = [scol.item(slabs[r], Fs, Rs, As if r == last else None, radius_index=r, sigma_R=sig[r])
              for r in range(len(radii))]
@@ -462,7 +477,8 @@ def _time_surrogate(P, blob, slabs, radii, sig, n, a, D, cfg, stream, F64, R64, 
            "rel_Dc_vs_fp64_field": {"max": float(rel.max()), "p99.9": float(np.percentile(rel, 99.9)),
                                     "mean": float(rel.mean())},
            "index_mismatch_frac": float((Rs != R64).double().mean().item()),
-           "training": training}
+           "training": training,
+           "condition": "LCDM LPT coefficients" if method == P.PINO_CLASSIC_LCDM else "EdS LPT coefficients"}
     scol.close()
     log(f"surrogate+certify {res['value']:.3e} evals/s, fallback {res['fallback_fraction_of_consulted']:.3f} of "
         f"consulted, full solve {res['full_solve_fraction_of_all']:.3f} of all, max rel D_c vs fp64 "

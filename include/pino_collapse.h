@@ -80,18 +80,19 @@ typedef enum {
  *                       are integrated on the device at init for each growth
  *                       table's omega_m (0 < omega_m <= 1; flat, no
  *                       radiation) at its knots and interpolated in D.  FP64
- *                       only; Classic per-radius evals only (no batch plan). */
+ *                       or PINO_SURROGATE (not PINO_MIXED); per-radius evals
+ *                       only (no batch plan). */
 typedef enum { PINO_CLASSIC = 0, PINO_TABULATED = 1, PINO_CLASSIC_LCDM = 2 } pino_method;
 
 /* Arithmetic of the evaluation.
  *   PINO_FP64      : FP64 Hessians, FP64 throughout.
- *   PINO_MIXED     : FP32 Hessians.  Classic: eigenvalues and interpolation
- *                    in FP32, FP64 for nearly degenerate eigenvalues and for
- *                    the final polish of the collapse root.  Tabulated: the
- *                    Hessians widened to FP64 for the eigenvalues and the
- *                    cell search, the table read from an FP32 copy built on
- *                    the device each radius (F and the spline second
- *                    derivatives rounded to FP32), the interpolation in FP64.
+ *   PINO_MIXED     : FP32 Hessians, eigenvalues and interpolation in FP32,
+ *                    FP64 for nearly degenerate eigenvalues.  Classic: FP64
+ *                    for the final polish of the collapse root.  Tabulated:
+ *                    the cell search in FP32 copies of the scaled knots, the
+ *                    table read from an FP32 copy built on the device each
+ *                    radius (F and the spline second derivatives rounded to
+ *                    FP32), spline and bilinear interpolation in FP32.
  *                    a(D) in FP32 for both.
  *   PINO_SURROGATE : FP64 Hessians and FP64 eigenvalues; a small network
  *                    (BF16 matrix-core inference) predicts the collapse
@@ -102,7 +103,9 @@ typedef enum { PINO_CLASSIC = 0, PINO_TABULATED = 1, PINO_CLASSIC_LCDM = 2 } pin
  *                    the workgroup that visited them, which then gives them
  *                    the full FP64 solve in the same launch (items are
  *                    processed in chunks of 2^24 particles, the queue's
- *                    size).  Classic only; weights from pino_mlp.h. */
+ *                    size).  Classic or Classic-LCDM (the network then
+ *                    predicts the LCDM condition's root; its omega_m input
+ *                    matters); weights from pino_mlp.h. */
 typedef enum { PINO_FP64 = 0, PINO_MIXED = 1, PINO_SURROGATE = 2 } pino_precision;
 
 /* eval flags */

@@ -76,8 +76,10 @@ pino_status pino_mlp_free(pino_mlp *m);
 
 /* Network inputs and training target for one item of a context (any
  * precision): x [n][4] (device), w [n] (device, may be NULL) = 1/(l1 D_c)
- * from the full FP64 solve, or 0 where the particle never collapses or the
- * network is not consulted (l1 < 0.1 max|l|).  omega_m comes from the
+ * from the full FP64 solve of the context's collapse condition (EdS or,
+ * for PINO_CLASSIC_LCDM contexts, LCDM time coefficients), or 0 where the
+ * particle never collapses or the network is not consulted
+ * (l1 < 0.1 max|l|).  omega_m comes from the
  * item's growth table.  At most 2^28 particles per call (PINO_ERR_ARG
  * otherwise). */
 pino_status pino_collapse_features(pino_ctx *ctx, const pino_item *item, float *x, float *w, void *hip_stream);

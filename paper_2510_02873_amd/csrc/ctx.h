@@ -101,6 +101,9 @@ struct pino_ctx {
     // the growth knots (stride 6 * nk_max): the LCDM growth ratios of the
     // LPT terms and their natural-spline second derivatives in D
     double* d_kap = nullptr;
+    // per cosmology, bounds on |d k / d ln D| of the three ratio splines over
+    // the whole table (the surrogate's LCDM certificate)
+    std::vector<double> kslope;
     // launch shape of the LCDM kernel: its LDS (knots, index and ratio rows)
     // limits the resident blocks per CU, so the grid is capped at what fits
     int lcdm_block = 512;

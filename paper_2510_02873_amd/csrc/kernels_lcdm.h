@@ -80,7 +80,9 @@ __device__ __forceinline__ LptState lpt_rk4(const LptState& y, double x, double 
 
 // One thread per cosmology c: growth knots at growth + c * 3 nk_max ([D | a |
 // M], a from offset nk[c]), ratios written to kap + c * 6 nk_max as
-// [k2 | k3a | k3b] (nk[c] each; the spline second derivatives follow).
+// [k2 | k3a | k3b] (nk[c] each, contiguous; the spline second derivatives
+// [m2 | m3a | m3b] follow, so the six rows of a cosmology are the 6 nk[c]
+// doubles the collapse kernels stage).
 constexpr double kLptStep = 1e-3;
 
 __global__ void __launch_bounds__(64) k_lpt_growth(const double* __restrict__ growth, const int* __restrict__ nk,
@@ -107,8 +109,8 @@ __global__ void __launch_bounds__(64) k_lpt_growth(const double* __restrict__ gr
             y = lpt_rk4(y, x0 + h * j, h, om);
         x = xe;
         out[k] = y.d2 / (-(3.0 / 7.0) * y.d1 * y.d1);
-        out[nk_max + k] = y.d3a / (-(1.0 / 3.0) * y.d1 * y.d1 * y.d1);
-        out[2 * nk_max + k] = y.d3b / ((10.0 / 21.0) * y.d1 * y.d1 * y.d1);
+        out[n + k] = y.d3a / (-(1.0 / 3.0) * y.d1 * y.d1 * y.d1);
+        out[2 * n + k] = y.d3b / ((10.0 / 21.0) * y.d1 * y.d1 * y.d1);
     }
 }
 

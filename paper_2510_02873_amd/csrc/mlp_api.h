@@ -121,8 +121,9 @@ pino_status surrogate_lds_limit(pino_ctx* c, size_t need)
 {
     if (need <= 65536)
         return PINO_OK;
-    const hipError_t e = hipFuncSetAttribute((const void*)pino::k_surrogate,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+    const void* fn = c->method == PINO_CLASSIC_LCDM ? (const void*)pino::k_surrogate<true>
+                                                     : (const void*)pino::k_surrogate<false>;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
     if (e != hipSuccess) {
         c->broken = true;
         c->err = std::string("surrogate LDS limit: ") + hipGetErrorString(e);
@@ -173,7 +174,12 @@ pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemA
                              int, int)
 {
     const int block = kSurrogateBlock;
-    const size_t lds = pino::surrogate_lds_bytes(a0.nk, a0.gi.nb);
+    const bool lcdm = c->method == PINO_CLASSIC_LCDM;
+    const size_t lds = pino::surrogate_lds_bytes(a0.nk, a0.gi.nb, lcdm);
+    const double* kap = lcdm ? c->d_kap + (size_t)it.cosmo * 6 * c->nk_max : nullptr;
+    pino::KappaSlope ks{};
+    if (lcdm)
+        ks = pino::KappaSlope{c->kslope[3 * it.cosmo], c->kslope[3 * it.cosmo + 1], c->kslope[3 * it.cosmo + 2]};
     auto* cnt = reinterpret_cast<unsigned long long*>(c->d_counters);
     const auto* net = static_cast<const pino::NetFrags*>(c->d_mlp);
     const int64_t cap_blocks = std::min<int64_t>((int64_t)c->cu_count * c->blocks_per_cu, kQueueBlocks);
@@ -189,8 +195,12 @@ pino_status launch_surrogate(pino_ctx* c, const pino_item& it, const pino::ItemA
         // a block visits at most ceil(n / stride) groups of `block` particles
         const int64_t stride = grid * block;
         const int64_t seg = (a.n + stride - 1) / stride * block;
-        hipLaunchKernelGGL(pino::k_surrogate, dim3((unsigned)grid), dim3(block), lds, st, a, net, it.sigma_R,
-                           c->omega[it.cosmo], c->certify_rtol, cnt, c->d_queue, seg);
+        if (lcdm)
+            hipLaunchKernelGGL(pino::k_surrogate<true>, dim3((unsigned)grid), dim3(block), lds, st, a, net,
+                               it.sigma_R, c->omega[it.cosmo], c->certify_rtol, cnt, c->d_queue, seg, kap, ks);
+        else
+            hipLaunchKernelGGL(pino::k_surrogate<false>, dim3((unsigned)grid), dim3(block), lds, st, a, net,
+                               it.sigma_R, c->omega[it.cosmo], c->certify_rtol, cnt, c->d_queue, seg, kap, ks);
         const pino_status ps = launch_fail(c, "surrogate launch");
         if (ps != PINO_OK)
             return ps;

@@ -202,7 +202,9 @@ bool lds_fits(const pino_config* cfg, std::string& why)
     for (int k = 0; k < cfg->n_cosmo; ++k)
         nk_max = std::max(nk_max, (int)cfg->growth[k].n);
     if (cfg->method == PINO_CLASSIC_LCDM) {
-        const size_t need = lcdm_lds_bytes(nk_max, index_bins(nk_max));
+        const size_t need = cfg->precision == PINO_SURROGATE
+                                ? surrogate_lds_bytes(nk_max, index_bins(nk_max), true)
+                                : lcdm_lds_bytes(nk_max, index_bins(nk_max));
         if (need > kLdsMax) {
             why = "growth knots and LCDM coefficients need " + std::to_string(need) + " bytes of LDS, more than 160 KiB";
             return false;
@@ -395,10 +397,32 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
         PINO_HIP(c, e);
         for (int k = 0; k < cfg->n_cosmo; ++k) {
             double* kp = c->d_kap + (size_t)k * 6 * nk_max;
-            hipLaunchKernelGGL(k_spline_build, dim3(1), dim3(64), 0, 0, c->d_growth + (size_t)k * 3 * nk_max,
-                               c->nk[k], kp, (int64_t)nk_max, 1, kp + 3 * nk_max, (int64_t)nk_max, 1,
-                               c->d_tmp + (size_t)k * 3 * nk_max, 3);
+            const int n = c->nk[k];
+            hipLaunchKernelGGL(k_spline_build, dim3(1), dim3(64), 0, 0, c->d_growth + (size_t)k * 3 * nk_max, n, kp,
+                               (int64_t)n, 1, kp + 3 * n, (int64_t)n, 1, c->d_tmp + (size_t)k * 3 * nk_max, 3);
             PINO_HIP(c, hipGetLastError());
+        }
+        // bounds on |d k / d ln D| for the surrogate's certificate: on
+        // interval i, |S'| <= |slope_i| + h_i/3 (|M_i| + |M_{i+1}|) and
+        // D <= D_{i+1}; outside the knots the ratios are constant
+        c->kslope.assign(3 * (size_t)cfg->n_cosmo, 0.0);
+        std::vector<double> rows(6 * (size_t)nk_max);
+        for (int k = 0; k < cfg->n_cosmo; ++k) {
+            const int n = c->nk[k];
+            const double* D = cfg->growth[k].D;
+            PINO_HIP(c, hipMemcpy(rows.data(), c->d_kap + (size_t)k * 6 * nk_max, 6 * (size_t)n * sizeof(double),
+                                  hipMemcpyDeviceToHost));
+            for (int j = 0; j < 3; ++j) {
+                const double* K = rows.data() + (size_t)j * n;
+                const double* M = rows.data() + (size_t)(3 + j) * n;
+                double m = 0.0;
+                for (int i = 0; i + 1 < n; ++i) {
+                    const double h = D[i + 1] - D[i];
+                    const double d = std::fabs((K[i + 1] - K[i]) / h) + h / 3.0 * (std::fabs(M[i]) + std::fabs(M[i + 1]));
+                    m = std::max(m, D[i + 1] * d);
+                }
+                c->kslope[3 * (size_t)k + j] = 1.01 * m;
+            }
         }
         const size_t need = lcdm_lds_bytes(nk_max, index_bins(nk_max));
         if (need > kLdsBudget) {
@@ -464,7 +488,7 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
         c->certify_rtol = cfg->certify_rtol > 0.0 ? cfg->certify_rtol : 5e-7;
         pino_status st = mlp_upload(c, cfg->mlp, cfg->mlp_bytes);
         if (st == PINO_OK)
-            st = surrogate_lds_limit(c, surrogate_lds_bytes(nk_max, c->nb_max));
+            st = surrogate_lds_limit(c, surrogate_lds_bytes(nk_max, c->nb_max, cfg->method == PINO_CLASSIC_LCDM));
         if (st != PINO_OK)
             return st;
     }
@@ -611,8 +635,8 @@ pino_status pino_collapse_init(const pino_config* cfg, pino_ctx** out)
         g_init_error = why;
         return PINO_ERR_UNSUPPORTED;
     }
-    if (cfg->method == PINO_CLASSIC_LCDM && cfg->precision != PINO_FP64) {
-        g_init_error = "the LCDM method runs in FP64 only";
+    if (cfg->method == PINO_CLASSIC_LCDM && cfg->precision == PINO_MIXED) {
+        g_init_error = "the LCDM method runs in FP64 or with the surrogate, not in mixed precision";
         return PINO_ERR_UNSUPPORTED;
     }
     pino_ctx* c = new (std::nothrow) pino_ctx();
@@ -738,8 +762,8 @@ pino_status pino_collapse_lpt_coefficients(pino_ctx* ctx, int32_t cosmo, double*
     const int n = ctx->nk[cosmo];
     const double* src = ctx->d_kap + (size_t)cosmo * 6 * ctx->nk_max;
     PINO_HIP(ctx, hipMemcpy(k2, src, n * sizeof(double), hipMemcpyDeviceToHost));
-    PINO_HIP(ctx, hipMemcpy(k3a, src + ctx->nk_max, n * sizeof(double), hipMemcpyDeviceToHost));
-    PINO_HIP(ctx, hipMemcpy(k3b, src + 2 * ctx->nk_max, n * sizeof(double), hipMemcpyDeviceToHost));
+    PINO_HIP(ctx, hipMemcpy(k3a, src + n, n * sizeof(double), hipMemcpyDeviceToHost));
+    PINO_HIP(ctx, hipMemcpy(k3b, src + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost));
     return PINO_OK;
 }
 
@@ -781,9 +805,19 @@ pino_status pino_collapse_features(pino_ctx* ctx, const pino_item* item, float* 
     for (int k = 0; k < 6; ++k)
         a.h[k] = static_cast<const double*>(it.h[k]);
     a.n = it.n;
+    // the growth knots and index (global memory) for the LCDM ratio splines
+    a.nk = ctx->nk[it.cosmo];
+    a.growth = ctx->d_growth + (size_t)it.cosmo * 3 * ctx->nk_max;
+    a.gi.idx = ctx->d_gidx + (size_t)it.cosmo * 2 * ctx->nb_max;
+    a.gi.nb = ctx->nb[it.cosmo];
+    a.gi.L0 = ctx->gL0[it.cosmo];
+    a.gi.S = ctx->gS[it.cosmo];
+    a.gi.ok = ctx->gok[it.cosmo];
+    const double* kap =
+        ctx->method == PINO_CLASSIC_LCDM ? ctx->d_kap + (size_t)it.cosmo * 6 * ctx->nk_max : nullptr;
     const bool f32 = ctx->precision == PINO_MIXED;
     hipLaunchKernelGGL(k_features, dim3((unsigned)((it.n + 255) / 256)), dim3(256), 0,
-                       static_cast<hipStream_t>(hip_stream), a, f32, it.sigma_R, ctx->omega[it.cosmo], x, w);
+                       static_cast<hipStream_t>(hip_stream), a, f32, it.sigma_R, ctx->omega[it.cosmo], kap, x, w);
     PINO_HIP(ctx, hipGetLastError());
     return PINO_OK;
 }

@@ -17,16 +17,19 @@ from . import _abi
 from .runner import Collapse
 
 
-def training_pairs(fields, growth_tables, device=0, per_slab=None, stream=None):
+def training_pairs(fields, growth_tables, device=0, per_slab=None, stream=None, method=_abi.PINO_CLASSIC):
     """fields: iterable of (hessian (6, n) tensor on the device, sigma_R,
     cosmology index); returns (x [m][4] float32, w [m] float32) device
-    tensors of the particles where the network is consulted (w > 0)."""
+    tensors of the particles where the network is consulted (w > 0).  The
+    targets solve the collapse condition of `method` (PINO_CLASSIC, or
+    PINO_CLASSIC_LCDM with FP64 fields: then they depend on each table's
+    omega_m, and so does the network's fourth input)."""
     col = None
     xs, ws = [], []
     for h, sigma, cosmo in fields:
         if col is None:
             prec = _abi.PINO_FP64 if h.dtype == torch.float64 else _abi.PINO_MIXED
-            col = Collapse(growth_tables, precision=prec, device=device)
+            col = Collapse(growth_tables, method=method, precision=prec, device=device)
         n = h.shape[1]
         x = torch.empty((n, 4), dtype=torch.float32, device=h.device)
         w = torch.empty(n, dtype=torch.float32, device=h.device)

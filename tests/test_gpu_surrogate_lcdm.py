@@ -1,0 +1,194 @@
+"""The surrogate + certify path on the flat-LCDM collapse condition
+(PINO_SURROGATE with PINO_CLASSIC_LCDM) against the oracle's LCDM solve,
+through the C ABI.
+
+Here the network's fourth input, Omega_m, carries information: the training
+targets come from the LCDM condition of each table's cosmology.  The
+certificate (Newton step on G with the ratio splines, bracket of the root,
+and no earlier root via the frozen-ratio cubic and the ratios' slope bounds)
+accepts a prediction only within certify_rtol of G's first root, so every
+output is gated at 1e-6 relative on D_c and a_coll, with the radius index
+exact outside near-ties and nearly tangent roots; constant networks that
+predict far from the root must fall back, never be accepted."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.test_gpu_lcdm import _lcdm_ref
+
+pytestmark = pytest.mark.gpu
+
+OMEGAS = (0.25, 0.3, 0.35)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2510_02873_amd as P
+    from paper_2510_02873_amd import _abi
+    return P, _abi
+
+
+@pytest.fixture(scope="module")
+def lcdm_net(P):
+    """A network trained by the library's kernels on LCDM targets from 96^3
+    FP64 fields of three cosmologies (Omega_m 0.25, 0.3, 0.35)."""
+    Pk, _ = P
+    from paper_2510_02873_amd import surrogate
+    cosmos = [synth.Cosmology(om, 0.8) for om in OMEGAS]
+    tables = [(*synth.growth_table(c.omega_m), c.omega_m) for c in cosmos]
+    fields = []
+    for k, c in enumerate(cosmos):
+        fld = synth.fields.field(96, 150.0, 41 + k, c, device="cuda")
+        for R in (6.0, 3.0, 1.5, 0.8):
+            fields.append((fld.hessian(R).double(), synth.grid_sigma_gauss(96, 150.0, R, c), k))
+    x, w = surrogate.training_pairs(fields, tables, method=Pk.PINO_CLASSIC_LCDM)
+    print(f"LCDM training pairs: {x.shape[0]}", flush=True)
+    blob, _, hist = surrogate.train(x, w, steps=3000, batch=8192, lr_max=3e-3, seed=2, log_every=1000)
+    print("loss history", hist, flush=True)
+    assert hist[-1][1] < 0.2 * hist[0][1]
+    return blob
+
+
+def _c1():
+    cfg = synth.config("C1")
+    om = cfg["cosmo"].omega_m
+    a, D = synth.growth_table(om)
+    fld = synth.fields.field(cfg["n_side"], cfg["box"], cfg["seed"], cfg["cosmo"], device="cuda")
+    slabs = [fld.hessian(R).double().contiguous() for R in cfg["radii"]]
+    sig = [synth.grid_sigma_gauss(cfg["n_side"], cfg["box"], R, cfg["cosmo"]) for R in cfg["radii"]]
+    return slabs, sig, a, D, om
+
+
+def _run(Pk, A, blob, slabs, sig, a, D, om):
+    with Pk.Collapse([(a, D, om)], method=Pk.PINO_CLASSIC_LCDM, precision=Pk.PINO_SURROGATE,
+                     mlp_blob=blob) as col:
+        n = slabs[0].shape[1]
+        Fm, Rm, ac = col.outputs(n)
+        last = len(slabs) - 1
+        for r, (h, s) in enumerate(zip(slabs, sig)):
+            col.apply(h, r, Fm, Rm, ac if r == last else None, reset=(r == 0), finalize=(r == last), sigma_R=s)
+        stats = A.pino_collapse_surrogate_stats(col.ctx)
+        return (Fm.cpu().numpy(), Rm.cpu().numpy(), ac.cpu().numpy()), stats
+
+
+def _gate(ref, got, skip, label):
+    Fr, Rr, Ar = ref
+    F, R, Ac = got
+    assert np.array_equal(F > 0, Fr > 0), label
+    big = Fr >= 1e-6
+    rel = np.abs(1 / F[big] - 1 / Fr[big]) * Fr[big]
+    fin = np.isfinite(Ar)
+    assert np.array_equal(np.isfinite(Ac), fin), label
+    rel_a = np.abs(Ac[fin] - Ar[fin]) / Ar[fin]
+    ok_index = (R == Rr) | skip
+    print(f"{label}: D_c max rel {rel.max() if rel.size else 0:.2e}, a_coll max rel "
+          f"{rel_a.max() if rel_a.size else 0:.2e}, index mismatches outside near-ties {int(np.sum(~ok_index))}",
+          flush=True)
+    assert rel.size == 0 or rel.max() <= 1e-6, label
+    assert rel_a.size == 0 or rel_a.max() <= 1e-6, label
+    assert np.all(ok_index), label
+
+
+def _skip_mask(orc, host, a, D, om, base_skip):
+    """base_skip plus near-ties at the certificate's resolution: the two best
+    radii within 2e-6."""
+    Fs = []
+    for h in host:
+        n = h.shape[1]
+        Fr, Rr = np.zeros(n), np.full(n, -1, np.int32)
+        orc.update_radius(h, 0, orc.Growth(a, D, om), Fr, Rr, None, reset=True, method=orc.CLASSIC_LCDM)
+        Fs.append(Fr)
+    srt = np.sort(np.stack(Fs), axis=0)
+    second = srt[-2] if srt.shape[0] > 1 else np.zeros_like(srt[-1])
+    return base_skip | (np.abs(srt[-1] - second) <= 2e-6 * srt[-1])
+
+
+def test_lcdm_features_vs_oracle(P, orc):
+    """Network inputs and LCDM targets w = 1/(l1 D_c) of pino_collapse_features
+    on an LCDM context against the oracle's LCDM solve."""
+    Pk, A = P
+    a, D = synth.growth_table(0.3)
+    fld = synth.fields.field(32, 100.0, 1, synth.Cosmology(), device="cuda")
+    h = fld.hessian(2.0).double().contiguous()
+    sig = synth.grid_sigma_gauss(32, 100.0, 2.0)
+    n = h.shape[1]
+    with Pk.Collapse([(a, D, 0.3)], method=Pk.PINO_CLASSIC_LCDM) as col:
+        x = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        w = torch.empty(n, dtype=torch.float32, device="cuda")
+        F = torch.empty(1, dtype=torch.float64, device="cuda")
+        R = torch.empty(1, dtype=torch.int32, device="cuda")
+        A.pino_collapse_features(col.ctx, A.make_item(h, F, R, sigma_R=sig, n=n), x, w)
+        torch.cuda.synchronize()
+    host = h.cpu().numpy()
+    lam, _ = orc.points(host)
+    Fr, Rr = np.zeros(n), np.full(n, -1, np.int32)
+    orc.update_radius(host, 0, orc.Growth(a, D, 0.3), Fr, Rr, None, reset=True, method=orc.CLASSIC_LCDM)
+    consult = (lam[:, 0] > 0) & (lam[:, 0] >= 0.1 * np.abs(lam[:, 2]))
+    wr = np.where(consult & (Fr > 0), Fr / np.where(lam[:, 0] > 0, lam[:, 0], 1), 0.0)
+    wg = w.cpu().numpy()
+    assert np.allclose(x.cpu().numpy()[:, 3], (0.3 - 0.3) * 20.0)
+    assert np.array_equal(wg > 0, wr > 0)
+    m = wr > 0
+    assert np.allclose(wg[m], wr[m], rtol=1e-6)
+    # the targets differ from the Einstein-de Sitter condition's
+    with Pk.Collapse([(a, D, 0.3)]) as col:
+        w0 = torch.empty(n, dtype=torch.float32, device="cuda")
+        A.pino_collapse_features(col.ctx, A.make_item(h, F, R, sigma_R=sig, n=n), x, w0)
+        torch.cuda.synchronize()
+    shift = np.abs(w0.cpu().numpy()[m] / wg[m] - 1)
+    print(f"LCDM vs EdS targets: median shift {np.median(shift):.2e}, max {shift.max():.2e}", flush=True)
+    assert np.median(shift) > 1e-5
+
+
+def test_lcdm_surrogate_parity_and_gain(P, orc, lcdm_net):
+    """C1 (32^3 x 25 radii, Omega_m = 0.3) through the LCDM surrogate path
+    against the oracle's LCDM solve on the same FP64 Hessians; the gain over
+    the same certificate without a trained network (constant Zel'dovich
+    guess) is the certified fraction."""
+    Pk, A = P
+    from paper_2510_02873_amd import surrogate
+    slabs, sig, a, D, om = _c1()
+    host = [h.cpu().numpy() for h in slabs]
+    ref, skip, n_tang = _lcdm_ref(orc, host, a, D, om)
+    skip = _skip_mask(orc, host, a, D, om, skip)
+    got, stats = _run(Pk, A, lcdm_net, slabs, sig, a, D, om)
+    n = slabs[0].shape[1]
+    tot = stats["certified"] + stats["fallback"] + stats["gated_solved"] + stats["gated_zero"]
+    assert tot == n * len(slabs)
+    consulted = stats["certified"] + stats["fallback"]
+    c1 = stats["certified"] / consulted
+    print(f"LCDM surrogate C1: certified {stats['certified']} fallback {stats['fallback']} gated_solved "
+          f"{stats['gated_solved']} gated_zero {stats['gated_zero']}; certified fraction {c1:.3f}; "
+          f"nearly tangent roots {n_tang}", flush=True)
+    _gate(ref, got, skip, "LCDM surrogate C1")
+    got0, stats0 = _run(Pk, A, surrogate.constant_blob(1.0), slabs, sig, a, D, om)
+    _gate(ref, got0, skip, "LCDM certificate from the Zel'dovich guess")
+    c0 = stats0["certified"] / (stats0["certified"] + stats0["fallback"])
+    print(f"certified fraction: trained network {c1:.3f} vs Zel'dovich guess {c0:.3f}", flush=True)
+    assert c1 > c0 + 0.2
+
+
+@pytest.mark.parametrize("w", [0.02, 0.3, 0.8, 1.0, 1.3, 4.0, 40.0])
+def test_lcdm_certificate_never_accepts_a_wrong_root(P, orc, w):
+    """Constant networks predicting w everywhere, on special spectra (diagonal,
+    repeated, planar, strongly anisotropic) and random ones over four decades
+    of scale: whatever is accepted is within the certified bound of the
+    oracle's first root, and the rest falls back to the full solve."""
+    Pk, A = P
+    from paper_2510_02873_amd import surrogate
+    a, D = synth.growth_table(0.3)
+    rows = []
+    for lam in [(1, 1, 1), (2, 0, 0), (1, 1, 0), (3, 3, -1), (0.5, -0.5, -0.5), (40.0, 3.0, -2.0),
+                (1e-3, 0, 0), (0.05, 0.01, -0.02), (8.0, 7.9, 7.8), (2.0, -3.0, -4.0), (1.0, -0.9, -5.0)]:
+        rows.append([lam[0], lam[1], lam[2], 0, 0, 0])
+    rng = np.random.default_rng(int(w * 1000) + 5)
+    rows += list(rng.normal(size=(4000, 6)) * 10.0 ** rng.uniform(-2, 2, size=(4000, 1)))
+    H = np.ascontiguousarray(np.array(rows).T)
+    n = H.shape[1]
+    ref, skip, _ = _lcdm_ref(orc, [H], a, D, 0.3)
+    got, stats = _run(Pk, A, surrogate.constant_blob(w), [torch.from_numpy(H).cuda()], [1.0], a, D, 0.3)
+    print(f"constant w = {w}: certified {stats['certified']} of {stats['certified'] + stats['fallback']} "
+          f"consulted", flush=True)
+    _gate(ref, got, skip, f"constant network w = {w}")
