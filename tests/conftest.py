@@ -38,3 +38,26 @@ def trained_net():
     blob, params, hist = surrogate.train(x, w, steps=3000, batch=8192, lr_max=3e-3, seed=1, log_every=1000)
     print("loss history", hist, flush=True)
     return blob, params, hist
+
+
+@pytest.fixture(scope="session")
+def trained_lcdm_net():
+    """Blob of a network trained by the library's kernels on LCDM targets from
+    96^3 FP64 fields of three cosmologies (Omega_m 0.25, 0.3, 0.35), whose
+    Omega_m input therefore carries information."""
+    import synth
+    import paper_2510_02873_amd as P
+    from paper_2510_02873_amd import surrogate
+    cosmos = [synth.Cosmology(om, 0.8) for om in (0.25, 0.3, 0.35)]
+    tables = [(*synth.growth_table(c.omega_m), c.omega_m) for c in cosmos]
+    fields = []
+    for k, c in enumerate(cosmos):
+        fld = synth.fields.field(96, 150.0, 41 + k, c, device="cuda")
+        for R in (6.0, 3.0, 1.5, 0.8):
+            fields.append((fld.hessian(R).double(), synth.grid_sigma_gauss(96, 150.0, R, c), k))
+    x, w = surrogate.training_pairs(fields, tables, method=P.PINO_CLASSIC_LCDM)
+    print(f"LCDM training pairs: {x.shape[0]}", flush=True)
+    blob, _, hist = surrogate.train(x, w, steps=3000, batch=8192, lr_max=3e-3, seed=2, log_every=1000)
+    print("loss history", hist, flush=True)
+    assert hist[-1][1] < 0.2 * hist[0][1]
+    return blob

@@ -52,6 +52,34 @@ def test_ellipsoid_table_vs_oracle(pkg, orc, om, sigma):
     assert rel.max() <= F_TOL
 
 
+@pytest.mark.parametrize("sigma", [0.12, 2.43])
+def test_ellipsoid_table_full_size_sampled(pkg, orc, sigma):
+    """The bench's table, 64 x 64 x 128 nodes (524288 threads in one launch),
+    at the bench's smallest and largest sigma: 40 seeded nodes and the eight
+    corners against the oracle's integration of the same node."""
+    from paper_2510_02873_amd import _abi
+    knots = _knots(64, 64, 128)
+    a, D = synth.growth_table(0.3)
+    with pkg.Collapse([(a, D, 0.3)], method=pkg.PINO_TABULATED, table_knots=knots) as col:
+        F = torch.empty(64 * 64 * 128, dtype=torch.float64, device="cuda")
+        _abi.pino_collapse_ellipsoid_table(col.ctx, 0, sigma, F)
+        torch.cuda.synchronize()
+        got = F.cpu().numpy().reshape(64, 64, 128)
+    xk, yk, dk = (np.asarray(k) * sigma for k in knots)
+    rng = np.random.default_rng(int(sigma * 100))
+    nodes = [tuple(int(v) for v in (rng.integers(64), rng.integers(64), rng.integers(128))) for _ in range(40)]
+    nodes += [(i, j, k) for i in (0, 63) for j in (0, 63) for k in (0, 127)]
+    worst = 0.0
+    for i, j, k in nodes:
+        ref = orc.ellipsoid_table([xk[i]], [yk[j]], [dk[k]], 0.3)[0, 0, 0]
+        assert (got[i, j, k] > 0) == (ref > 0), (i, j, k)
+        if ref > 0:
+            worst = max(worst, abs(got[i, j, k] / ref - 1))
+    print(f"ellipsoid table 64x64x128 sigma={sigma}: {len(nodes)} sampled nodes, "
+          f"{int(np.sum(got > 0))} collapsing of {got.size}, max rel {worst:.2e}", flush=True)
+    assert worst <= F_TOL
+
+
 def test_ellipsoid_spheres(pkg, orc):
     """The x = y = 0 row of the table is a sphere: in Einstein-de Sitter its
     linear density at collapse is (3/20)(12 pi)^(2/3)."""

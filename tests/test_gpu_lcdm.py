@@ -37,6 +37,27 @@ def test_lpt_coefficients_vs_oracle(pkg, orc, om, nk):
     assert worst <= 1e-9
 
 
+def test_lcdm_cosmologies_with_different_knot_counts(pkg, orc):
+    """One context holding two cosmologies whose growth tables have different
+    knot counts (300 and 512): the ratio rows of each are read with its own
+    count (regression: rows laid out with the larger count were read with
+    the smaller), so both the coefficients and the collapse of items of
+    either cosmology match the oracle."""
+    from paper_2510_02873_amd import _abi
+    cfg, slabs, _, _ = c1_inputs()
+    hs = [h.cuda() for h in slabs[:6]]
+    tabs = [(0.35, 300), (0.27, 512)]
+    growth = [(*synth.growth_table(om, nk), om) for om, nk in tabs]
+    with pkg.Collapse(growth, method=pkg.PINO_CLASSIC_LCDM) as col:
+        for k, (om, nk) in enumerate(tabs):
+            got = _abi.pino_collapse_lpt_coefficients(col.ctx, k, nk)
+            ref = orc.lpt_growth(om, growth[k][0])
+            assert max(float(np.max(np.abs(g - r))) for g, r in zip(got, ref)) <= 1e-9
+            res = run_gpu_radii(col, hs, cosmo=k)
+            refc, skip, _ = _lcdm_ref(orc, hs, growth[k][0], growth[k][1], om)
+            compare(refc, res, tie_mask=skip, label=f"LCDM cosmology {k} (Omega_m {om}, {nk} knots)")
+
+
 def _lcdm_ref(orc, slabs, a, D, om):
     g = orc.Growth(a, D, om)
     host = [h.cpu().numpy() if torch.is_tensor(h) else np.asarray(h) for h in slabs]

@@ -7,8 +7,9 @@ FP64.  Gates: mixed, the per-particle FP32 bound of the mixed tests against
 the oracle on the FP32 inputs (its error against the FP64 field is
 reported); surrogate, 1e-6 relative on D_c and a_coll after certification
 against the oracle on the FP64 field.  The
-Tabulated workload (256^3 x 25 radii) and the batched 64-realisation one are
-checked the same way, on seeded samples of particles."""
+Tabulated and LCDM workloads (256^3 x 25 radii; LCDM plain and through the
+surrogate) and the batched 64-realisation one are checked the same way, on
+seeded samples of particles."""
 
 import numpy as np
 import pytest
@@ -173,6 +174,77 @@ def test_256cube_25radii_tabulated_sampled(orc):
     st = compare(ref64, g64, tie_mask=near_tie_mask(per_radius(s64)), label="tabulated 256^3 sample")
     print("tabulated 256^3 x 25 sample (FP64)", st, flush=True)
     _check_mixed_tab(ref32, g32, per_radius(s32), _tab32_bound(orc, tabs, s32), "tabulated 256^3 sample (mixed)")
+
+
+def test_256cube_25radii_lcdm_sampled(orc, trained_lcdm_net):
+    """The LCDM workload at full size (256^3 x 25 radii, the bench's fields and
+    launch shapes): the plain LCDM kernel and the surrogate on the LCDM
+    condition, gated on a seeded 20k-particle sample against the oracle's
+    LCDM solve: plain, 1e-9 relative on D_c and a_coll; surrogate, 1e-6 (its
+    certified bound); radius index exact outside near-ties (2e-6 for the
+    surrogate) and nearly tangent roots."""
+    import paper_2510_02873_amd as P
+    from tests._helpers import compare
+    from tests.test_gpu_lcdm import _lcdm_ref
+    cfg = synth.config("C2")
+    n_side, box, radii, cosmo = cfg["n_side"], cfg["box"], cfg["radii"], cfg["cosmo"]
+    n = n_side ** 3
+    om = cosmo.omega_m
+    a, D = synth.growth_table(om, cfg["n_growth"])
+    sig = synth.grid_sigma_gauss(n_side, box, radii, cosmo)
+    fld = synth.fields.field(n_side, box, cfg["seed"], cosmo, device="cuda")
+    rng = np.random.default_rng(9876)
+    idx = np.concatenate([np.sort(rng.choice(n, size=20000, replace=False)), [0, n - 1]])
+    tidx = torch.from_numpy(idx).cuda()
+    sample = []
+    print(f"256^3 x {len(radii)} LCDM: n={n}", flush=True)
+    with P.Collapse([(a, D, om)], method=P.PINO_CLASSIC_LCDM) as cp, \
+            P.Collapse([(a, D, om)], method=P.PINO_CLASSIC_LCDM, precision=P.PINO_SURROGATE,
+                       mlp_blob=trained_lcdm_net) as cs:
+        F1, R1, A1 = cp.outputs(n)
+        F2, R2, A2 = cs.outputs(n)
+        last = len(radii) - 1
+        for r, R in enumerate(radii):
+            h = fld.hessian(R)
+            sample.append(h[:, tidx].cpu().numpy())
+            cp.apply(h, r, F1, R1, A1 if r == last else None, reset=(r == 0), finalize=(r == last))
+            cs.apply(h, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last),
+                     sigma_R=sig[r])
+            del h
+            if r % 10 == 9:
+                torch.cuda.synchronize()
+                print(f"  radius {r + 1}/{len(radii)} done", flush=True)
+        torch.cuda.synchronize()
+        gp = tuple(t[tidx].cpu().numpy() for t in (F1, R1, A1))
+        gs = tuple(t[tidx].cpu().numpy() for t in (F2, R2, A2))
+        from paper_2510_02873_amd import _abi
+        stats = _abi.pino_collapse_surrogate_stats(cs.ctx)
+    ref, skip, n_tang = _lcdm_ref(orc, sample, a, D, om)
+    st = compare(ref, gp, tie_mask=skip, label="LCDM 256^3 sample")
+    print(f"LCDM 256^3 x 25 sample (plain): {st}; nearly tangent roots {n_tang}", flush=True)
+    # the surrogate: certified bound, near-ties at that resolution
+    g = orc.Growth(a, D, om)
+    per_r = []
+    for h in sample:
+        Fr, Rr = np.zeros(h.shape[1]), np.full(h.shape[1], -1, np.int32)
+        orc.update_radius(h, 0, g, Fr, Rr, None, reset=True, method=orc.CLASSIC_LCDM)
+        per_r.append(Fr)
+    srt = np.sort(np.stack(per_r), axis=0)
+    tie = skip | (np.abs(srt[-1] - srt[-2]) <= 2e-6 * srt[-1])
+    Fr, Rr, Ar = ref
+    F, Rg, Ag = gs
+    assert np.array_equal(F > 0, Fr > 0)
+    big = Fr >= 1e-6
+    rel = np.abs(1 / F[big] - 1 / Fr[big]) * Fr[big]
+    fin = np.isfinite(Ar)
+    assert np.array_equal(np.isfinite(Ag), fin)
+    rel_a = np.abs(Ag[fin] - Ar[fin]) / Ar[fin]
+    consulted = stats["certified"] + stats["fallback"]
+    print(f"LCDM surrogate 256^3 x 25 sample: D_c max rel {rel.max():.2e}, a_coll max rel {rel_a.max():.2e}, "
+          f"index mismatches outside near-ties {int(np.sum((Rg != Rr) & ~tie))}; certified fraction "
+          f"{stats['certified'] / consulted:.3f} of consulted (all particles)", flush=True)
+    assert rel.max() <= 1e-6 and rel_a.max() <= 1e-6
+    assert np.all((Rg == Rr) | tie)
 
 
 def test_c4_batched_full_size_sampled(orc):
