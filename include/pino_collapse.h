@@ -236,6 +236,22 @@ pino_status pino_collapse_free(pino_ctx *ctx);
 pino_status pino_collapse_ellipsoid_table(pino_ctx *ctx, int32_t cosmo, double sigma_R, double *table_F,
                                           void *hip_stream);
 
+/* The same table under a modified-gravity option (the Tabulated method is
+ * the one meant for modified gravity, Sec. 3, where the LPT condition does
+ * not apply): the gravity of the density perturbations -- the ellipsoid's
+ * excess and internal tide, the external tide and the linear growth that
+ * normalises D -- is scaled by mu(a) = 1 + mu0 / E(a)^2, E^2 = omega_m a^-3
+ * + 1 - omega_m (in flat LCDM, 1 + mu0 Omega_L(a)/Omega_L today: standard
+ * gravity early, the departure growing as the cosmological constant takes
+ * over); the background expansion is unchanged.  mu0 = 0 gives
+ * pino_collapse_ellipsoid_table bit for bit.  PINO_ERR_ARG also when mu0 is
+ * not finite, not above -(1 - omega_m) (mu must stay positive), or not 0
+ * with omega_m = 1.  The growth table of the context that inverts D_c
+ * should be the one of the same option.  The option's D(a = 1) is
+ * integrated on the host at each call with mu0 != 0 (a few ms). */
+pino_status pino_collapse_ellipsoid_table_mg(pino_ctx *ctx, int32_t cosmo, double sigma_R, double mu0,
+                                             double *table_F, void *hip_stream);
+
 /* The LCDM time coefficients of a PINO_CLASSIC_LCDM context at the knots of
  * growth table `cosmo`: k2, k3a, k3b (host arrays of that table's n
  * doubles, written) are the second-order, third-order determinant-type and

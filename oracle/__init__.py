@@ -82,10 +82,12 @@ def lib():
         L.orc_g_lcdm.restype = ctypes.c_double
         L.orc_ell_alpha.argtypes = [_D, ctypes.c_int]
         L.orc_ell_alpha.restype = ctypes.c_double
-        L.orc_ellipsoid_F.argtypes = [_D] + [ctypes.c_double] * 5 + [_D]
+        L.orc_ellipsoid_F.argtypes = [_D] + [ctypes.c_double] * 6 + [_D]
         L.orc_ellipsoid_F.restype = ctypes.c_double
-        L.orc_ellipsoid_axes.argtypes = [_D] + [ctypes.c_double] * 4 + [_D, _D]
-        L.orc_ellipsoid_table.argtypes = [ctypes.c_int] * 3 + [_D] * 3 + [ctypes.c_double] * 5 + [_D]
+        L.orc_ellipsoid_axes.argtypes = [_D] + [ctypes.c_double] * 5 + [_D, _D]
+        L.orc_ellipsoid_table.argtypes = [ctypes.c_int] * 3 + [_D] * 3 + [ctypes.c_double] * 6 + [_D]
+        L.orc_ell_growth1.argtypes = [ctypes.c_double] * 4
+        L.orc_ell_growth1.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -227,29 +229,38 @@ def ell_alpha(x, i):
     return lib().orc_ell_alpha(_p(_f64(x)), int(i))
 
 
-def ellipsoid_F(lam, omega_m, step=ELL_STEP, kappa=ELL_KAPPA, a_i=ELL_A_I, a_stop=ELL_A_STOP):
-    """(F = 1/D_c, a_c) of the homogeneous ellipsoid with eigenvalues lam."""
+def ellipsoid_F(lam, omega_m, step=ELL_STEP, kappa=ELL_KAPPA, a_i=ELL_A_I, a_stop=ELL_A_STOP, mu0=0.0):
+    """(F = 1/D_c, a_c) of the homogeneous ellipsoid with eigenvalues lam;
+    mu0: the modified-gravity option, perturbations' gravity scaled by
+    mu(a) = 1 + mu0 / E(a)^2 (0: general relativity)."""
     ac = ctypes.c_double()
-    F = lib().orc_ellipsoid_F(_p(_f64(lam)), float(omega_m), float(a_i), float(a_stop), float(step), float(kappa),
-                              ctypes.byref(ac))
+    F = lib().orc_ellipsoid_F(_p(_f64(lam)), float(omega_m), float(mu0), float(a_i), float(a_stop), float(step),
+                              float(kappa), ctypes.byref(ac))
     return F, ac.value
 
 
-def ellipsoid_axes(lam, omega_m, a_out, step=ELL_STEP, a_i=ELL_A_I):
+def ellipsoid_axes(lam, omega_m, a_out, step=ELL_STEP, a_i=ELL_A_I, mu0=0.0):
     """(axes x_i = R_i/a, D/D1) of the ellipsoid at a_out."""
     x = np.empty(3)
     d = ctypes.c_double()
-    lib().orc_ellipsoid_axes(_p(_f64(lam)), float(omega_m), float(a_i), float(a_out), float(step), _p(x),
-                             ctypes.byref(d))
+    lib().orc_ellipsoid_axes(_p(_f64(lam)), float(omega_m), float(mu0), float(a_i), float(a_out), float(step),
+                             _p(x), ctypes.byref(d))
     return x, d.value
 
 
-def ellipsoid_table(xk, yk, dk, omega_m, step=ELL_STEP, kappa=ELL_KAPPA, a_i=ELL_A_I, a_stop=ELL_A_STOP):
+def ellipsoid_growth1(omega_m, mu0=0.0, step=ELL_STEP, a_i=ELL_A_I):
+    """D(a = 1) of the growing mode started as D = a at a_i (the
+    normalisation of the ellipsoid's linear growth), with the same mu."""
+    return lib().orc_ell_growth1(float(omega_m), float(mu0), float(a_i), float(step))
+
+
+def ellipsoid_table(xk, yk, dk, omega_m, step=ELL_STEP, kappa=ELL_KAPPA, a_i=ELL_A_I, a_stop=ELL_A_STOP,
+                    mu0=0.0):
     """F over the nodes of knots (already scaled), shaped (nx, ny, nd)."""
     xk, yk, dk = _f64(xk), _f64(yk), _f64(dk)
     F = np.empty((len(xk), len(yk), len(dk)))
-    lib().orc_ellipsoid_table(len(xk), len(yk), len(dk), _p(xk), _p(yk), _p(dk), float(omega_m), float(a_i),
-                              float(a_stop), float(step), float(kappa), _p(F))
+    lib().orc_ellipsoid_table(len(xk), len(yk), len(dk), _p(xk), _p(yk), _p(dk), float(omega_m), float(mu0),
+                              float(a_i), float(a_stop), float(step), float(kappa), _p(F))
     return F
 
 

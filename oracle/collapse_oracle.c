@@ -770,17 +770,22 @@ double orc_g_lcdm(const double lam[3], int nk, const double *D, const double *k2
 /* an expanding flat LCDM background with the external tide of linear theory */
 /* (the form of Bond & Myers 1996).  For semi-axes R_i = a x_i (unit          */
 /* Lagrangian radius), with 1 + delta = 1/(x1 x2 x3):                         */
-/*   d2R_i/dt2 = -(3/2) Om a^-3 R_i [(1 + delta)/3 + (alpha_i - 2/3) delta/2  */
-/*               + (D/D1) (l_i - (l1 + l2 + l3)/3)] + (1 - Om) R_i,           */
+/*   d2R_i/dt2 = -(3/2) Om a^-3 R_i [1/3 + mu(a) (delta/3                    */
+/*               + (alpha_i - 2/3) delta/2 + (D/D1) (l_i - (l1+l2+l3)/3))]    */
+/*               + (1 - Om) R_i,                                             */
 /*   alpha_i = |x1 x2 x3| int_0^inf dtau / ((x_i^2 + tau)^(3/2)              */
 /*                                        sqrt((x_j^2 + tau)(x_k^2 + tau))), */
-/* D the linear growing mode and D1 its value at a = 1.                       */
+/* D the linear growing mode and D1 its value at a = 1.  mu(a) scales the     */
+/* gravity of the density perturbations (the background is unchanged), a     */
+/* modified-gravity option: mu = 1 + mu0 / E(a)^2 (in flat LCDM, 1 + mu0     */
+/* Omega_L(a)/Omega_L), so gravity is standard at early times; mu0 = 0 is    */
+/* general relativity.  The growth equation carries the same mu.              */
 /*                                                                          */
 /* The oracle does NOT integrate that form.  It integrates the equivalent     */
 /* comoving system in s = ln a (eight ODEs; ' = d/ds, Om(a) = Om a^-3/E^2):   */
-/*   x_i'' = -(2 - 1.5 Om(a)) x_i' - 1.5 Om(a) x_i [delta/3                   */
+/*   x_i'' = -(2 - 1.5 Om(a)) x_i' - 1.5 Om(a) mu(a) x_i [delta/3             */
 /*            + (alpha_i - 2/3) delta/2 + (D/D1)(l_i - (l1+l2+l3)/3)],        */
-/*   D''   = -(2 - 1.5 Om(a)) D' + 1.5 Om(a) D,                               */
+/*   D''   = -(2 - 1.5 Om(a)) D' + 1.5 Om(a) mu(a) D,                         */
 /* with classical RK4 at a fixed step in s, alpha_i by the trapezoid rule in  */
 /* v = ln tau (step 0.5 over the range where the integrand is above 1e-17 of  */
 /* its scale; the integrand is analytic within |Im v| < pi, where this rule   */
@@ -821,8 +826,14 @@ double orc_ell_alpha(const double x[3], int i)
 }
 
 typedef struct {
-    double om, D1, lext[3];
+    double om, mu0, D1, lext[3];
 } ell_par;
+
+/* mu(a) of the modified-gravity option at a^-3 = a3 */
+static double ell_mu(double om, double mu0, double a3)
+{
+    return 1.0 + mu0 / (om * a3 + 1.0 - om);
+}
 
 /* state y = (x1, x2, x3, x1', x2', x3', D, D') in s = ln a */
 static void ell_rhs(const ell_par *P, double s, const double y[8], double dy[8])
@@ -830,6 +841,7 @@ static void ell_rhs(const ell_par *P, double s, const double y[8], double dy[8])
     double a3 = exp(-3.0 * s);
     double oma = P->om * a3 / (P->om * a3 + 1.0 - P->om);
     double damp = 2.0 - 1.5 * oma;
+    double mu = ell_mu(P->om, P->mu0, a3);
     double x[3] = {y[0], y[1], y[2]};
     double delta = 1.0 / (x[0] * x[1] * x[2]) - 1.0;
     double dn = y[6] / P->D1;
@@ -838,10 +850,10 @@ static void ell_rhs(const ell_par *P, double s, const double y[8], double dy[8])
         dy[i] = y[3 + i];
         /* uniform excess delta/3 plus internal tide (alpha - 2/3) delta/2,
          * written as their sum alpha delta/2 */
-        dy[3 + i] = -damp * y[3 + i] - 1.5 * oma * x[i] * (0.5 * al * delta + dn * P->lext[i]);
+        dy[3 + i] = -damp * y[3 + i] - 1.5 * oma * mu * x[i] * (0.5 * al * delta + dn * P->lext[i]);
     }
     dy[6] = y[7];
-    dy[7] = -damp * y[7] + 1.5 * oma * y[6];
+    dy[7] = -damp * y[7] + 1.5 * oma * mu * y[6];
 }
 
 static void ell_rk4(const ell_par *P, double s, double h, const double y[8], double out[8])
@@ -860,7 +872,7 @@ static void ell_rk4(const ell_par *P, double s, double h, const double y[8], dou
 
 /* D(a = 1) of the growing mode started as D = a at a_i, RK4 in s with the
  * same step as the ellipsoid (the normalisation both use) */
-double orc_ell_growth1(double om, double a_i, double h)
+double orc_ell_growth1(double om, double mu0, double a_i, double h)
 {
     double s = log(a_i);
     int n = (int)ceil(-s / h);
@@ -874,7 +886,7 @@ double orc_ell_growth1(double om, double a_i, double h)
         oma = om * exp(-3.0 * (sv)) / (om * exp(-3.0 * (sv)) + 1.0 - om); \
         damp = 2.0 - 1.5 * oma;                                            \
         kv[0] = yv[1];                                                     \
-        kv[1] = -damp * yv[1] + 1.5 * oma * yv[0];
+        kv[1] = -damp * yv[1] + 1.5 * oma * ell_mu(om, mu0, exp(-3.0 * (sv))) * yv[0];
         GROW(ss, y, k[0]);
         t[0] = y[0] + 0.5 * hh * k[0][0]; t[1] = y[1] + 0.5 * hh * k[0][1];
         GROW(ss + 0.5 * hh, t, k[1]);
@@ -899,12 +911,13 @@ double orc_ell_growth1(double om, double a_i, double h)
  * doubles; an axis whose remaining time x / |x'| falls below 1e-12 (in ln a)
  * is taken as collapsed there.  *a_c receives the collapse scale factor (or
  * a_stop). */
-double orc_ellipsoid_F(const double lam[3], double om, double a_i, double a_stop, double h, double kappa,
-                       double *a_c)
+double orc_ellipsoid_F(const double lam[3], double om, double mu0, double a_i, double a_stop, double h,
+                       double kappa, double *a_c)
 {
     ell_par P;
     P.om = om;
-    P.D1 = orc_ell_growth1(om, a_i, h);
+    P.mu0 = mu0;
+    P.D1 = orc_ell_growth1(om, mu0, a_i, h);
     double dl = lam[0] + lam[1] + lam[2];
     for (int i = 0; i < 3; ++i)
         P.lext[i] = lam[i] - dl / 3.0;
@@ -969,12 +982,13 @@ double orc_ellipsoid_F(const double lam[3], double om, double a_i, double a_stop
 
 /* The axes x_i = R_i/a of the ellipsoid at scale factor a_out (no collapse
  * check; for early-time checks).  Same integration as orc_ellipsoid_F. */
-void orc_ellipsoid_axes(const double lam[3], double om, double a_i, double a_out, double h, double x_out[3],
-                        double *D_out)
+void orc_ellipsoid_axes(const double lam[3], double om, double mu0, double a_i, double a_out, double h,
+                        double x_out[3], double *D_out)
 {
     ell_par P;
     P.om = om;
-    P.D1 = orc_ell_growth1(om, a_i, h);
+    P.mu0 = mu0;
+    P.D1 = orc_ell_growth1(om, mu0, a_i, h);
     double dl = lam[0] + lam[1] + lam[2];
     for (int i = 0; i < 3; ++i)
         P.lext[i] = lam[i] - dl / 3.0;
@@ -1003,7 +1017,7 @@ void orc_ellipsoid_axes(const double lam[3], double om, double a_i, double a_out
  * l1 = (d + 2x + y)/3, l2 = (d - x + y)/3, l3 = (d - x - 2y)/3:
  * F[(ix * ny + iy) * nd + id] over the knots xk, yk, dk (already scaled). */
 void orc_ellipsoid_table(int nx, int ny, int nd, const double *xk, const double *yk, const double *dk, double om,
-                         double a_i, double a_stop, double h, double kappa, double *F)
+                         double mu0, double a_i, double a_stop, double h, double kappa, double *F)
 {
 #pragma omp parallel for schedule(dynamic, 1) collapse(2)
     for (int ix = 0; ix < nx; ++ix)
@@ -1011,6 +1025,6 @@ void orc_ellipsoid_table(int nx, int ny, int nd, const double *xk, const double 
             for (int id = 0; id < nd; ++id) {
                 double x = xk[ix], yv = yk[iy], d = dk[id];
                 double lam[3] = {(d + 2.0 * x + yv) / 3.0, (d - x + yv) / 3.0, (d - x - 2.0 * yv) / 3.0};
-                F[((size_t)ix * ny + iy) * nd + id] = orc_ellipsoid_F(lam, om, a_i, a_stop, h, kappa, NULL);
+                F[((size_t)ix * ny + iy) * nd + id] = orc_ellipsoid_F(lam, om, mu0, a_i, a_stop, h, kappa, NULL);
             }
 }

@@ -84,6 +84,9 @@ def lib():
         L.pino_collapse_ellipsoid_table.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
                                                     ctypes.c_void_p, ctypes.c_void_p]
         L.pino_collapse_ellipsoid_table.restype = ctypes.c_int
+        L.pino_collapse_ellipsoid_table_mg.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                                       ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        L.pino_collapse_ellipsoid_table_mg.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -173,6 +176,14 @@ def pino_collapse_ellipsoid_table(ctx, cosmo, sigma_R, table_F, stream=None):
     ellipsoid F at the context's table knots scaled by sigma_R."""
     handle = stream.cuda_stream if stream is not None and hasattr(stream, "cuda_stream") else stream
     _check(lib().pino_collapse_ellipsoid_table(ctx, int(cosmo), float(sigma_R), table_F.data_ptr(), handle), ctx)
+
+
+def pino_collapse_ellipsoid_table_mg(ctx, cosmo, sigma_R, mu0, table_F, stream=None):
+    """pino_collapse_ellipsoid_table under the modified-gravity option
+    mu(a) = 1 + mu0 / E(a)^2 for the perturbations' gravity."""
+    handle = stream.cuda_stream if stream is not None and hasattr(stream, "cuda_stream") else stream
+    _check(lib().pino_collapse_ellipsoid_table_mg(ctx, int(cosmo), float(sigma_R), float(mu0), table_F.data_ptr(),
+                                                  handle), ctx)
 
 
 def pino_collapse_lpt_coefficients(ctx, cosmo, n):

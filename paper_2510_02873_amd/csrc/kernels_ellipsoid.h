@@ -17,6 +17,13 @@
 // growing mode and D1 its value at a = 1 (the eigenvalues are linear
 // quantities of today).
 //
+// Modified-gravity option: the gravity of the density perturbations (the
+// ellipsoid's excess, its internal tide and the external tide, and the
+// linear growth) is scaled by mu(a) = 1 + mu0 / E(a)^2, which in flat LCDM
+// is 1 + mu0 Omega_L(a)/Omega_L: standard at early times, departing as the
+// cosmological constant takes over.  The background is unchanged.  mu0 = 0
+// is general relativity (the scaling is then an exact multiplication by 1).
+//
 // The axes are carried as their displacement from the unperturbed sphere,
 // psi_i = R_i - a (early on a perturbation of 1e-7 would drown in the
 // rounding of R itself); the background's own acceleration cancels and
@@ -89,7 +96,7 @@ struct EllState {
 };
 
 struct EllPar {
-    double om, ol, D1, lext[3];
+    double om, ol, mu0, D1, lext[3];
 };
 
 // The right-hand side.  Axis 0 has the largest eigenvalue and is the first
@@ -117,15 +124,18 @@ __host__ __device__ inline EllState ell_rhs(const EllState& y, const EllPar& P)
     const double g = 1.5 * P.om * ia3;
     const double lin = P.ol - g * (1.0 / 3.0);
     const double dn = y.D / P.D1;
+    // the perturbations' gravity, scaled by mu = 1 + mu0 / E^2 (exactly g
+    // when mu0 = 0); the background term lin is unchanged
+    const double gm = g * (1.0 + P.mu0 / (E * E));
     EllState d;
     for (int i = 0; i < 3; ++i) {
         const double R = y.a + y.P[i];
         d.P[i] = y.W[i];
-        d.W[i] = lin * y.P[i] - g * R * (0.5 * al[i] * delta + dn * P.lext[i]);
+        d.W[i] = lin * y.P[i] - gm * R * (0.5 * al[i] * delta + dn * P.lext[i]);
     }
     d.a = y.a * E;
     d.D = y.Dd;
-    d.Dd = -2.0 * E * y.Dd + g * y.D;
+    d.Dd = -2.0 * E * y.Dd + gm * y.D;
     return d;
 }
 
@@ -167,19 +177,20 @@ __host__ __device__ inline double ell_rmin(const EllState& y)
 }
 
 // D(a = 1) of the growing mode started as D = a at a_i: RK4 in s = ln a of
-// D'' = -(2 - 1.5 Om(a)) D' + 1.5 Om(a) D in steps of 1e-4 (host side, at
-// the call; it only normalises D)
-inline double ell_growth_today(double om)
+// D'' = -(2 - 1.5 Om(a)) D' + 1.5 Om(a) mu(a) D in steps of 1e-4 (host side,
+// at the call; it only normalises D)
+inline double ell_growth_today(double om, double mu0)
 {
     const double s0 = std::log(kEllAi);
     const int n = (int)std::ceil(-s0 / 1e-4);
     const double h = -s0 / n;
     double d = kEllAi, v = kEllAi;
-    auto f = [om](double s, double dd, double vv, double& kd, double& kv) {
+    auto f = [om, mu0](double s, double dd, double vv, double& kd, double& kv) {
         const double a3 = std::exp(-3.0 * s);
-        const double oma = om * a3 / (om * a3 + 1.0 - om);
+        const double e2 = om * a3 + 1.0 - om;
+        const double oma = om * a3 / e2;
         kd = vv;
-        kv = -(2.0 - 1.5 * oma) * vv + 1.5 * oma * dd;
+        kv = -(2.0 - 1.5 * oma) * vv + 1.5 * oma * (1.0 + mu0 / e2) * dd;
     };
     for (int m = 0; m < n; ++m) {
         const double s = s0 + m * h;
@@ -194,12 +205,14 @@ inline double ell_growth_today(double om)
     return d;
 }
 
-// F = 1/D_c of the ellipsoid with eigenvalues l0 >= l1 >= l2, or 0.
-__host__ __device__ inline double ellipsoid_F(double l0, double l1, double l2, double om, double D1)
+// F = 1/D_c of the ellipsoid with eigenvalues l0 >= l1 >= l2, or 0; mu0:
+// the modified-gravity option (0: general relativity), D1 its growth today.
+__host__ __device__ inline double ellipsoid_F(double l0, double l1, double l2, double om, double mu0, double D1)
 {
     EllPar P;
     P.om = om;
     P.ol = 1.0 - om;
+    P.mu0 = mu0;
     P.D1 = D1;
     const double third = (l0 + l1 + l2) * (1.0 / 3.0);
     P.lext[0] = l0 - third;
@@ -277,7 +290,8 @@ __host__ __device__ inline double ellipsoid_F(double l0, double l1, double l2, d
 // thread (id * nx + ix) * ny + iy so that a wave holds nodes of one delta,
 // out F[(ix * ny + iy) * nd + id].
 __global__ void __launch_bounds__(256) k_ellipsoid_table(const double* __restrict__ knots, int nx, int ny, int nd,
-                                                        double sigma, double om, double D1, double* __restrict__ F)
+                                                        double sigma, double om, double mu0, double D1,
+                                                        double* __restrict__ F)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nodes = (int64_t)nx * ny * nd;
@@ -290,7 +304,7 @@ __global__ void __launch_bounds__(256) k_ellipsoid_table(const double* __restric
     const double l0 = (d + 2.0 * x + yv) * (1.0 / 3.0);
     const double l1 = (d - x + yv) * (1.0 / 3.0);
     const double l2 = (d - x - 2.0 * yv) * (1.0 / 3.0);
-    F[((int64_t)ix * ny + iy) * nd + id] = ellipsoid_F(l0, l1, l2, om, D1);
+    F[((int64_t)ix * ny + iy) * nd + id] = ellipsoid_F(l0, l1, l2, om, mu0, D1);
 }
 
 }  // namespace pino

@@ -713,8 +713,8 @@ const char* pino_collapse_last_error(const pino_ctx* ctx)
     return ctx->err.c_str();
 }
 
-pino_status pino_collapse_ellipsoid_table(pino_ctx* ctx, int32_t cosmo, double sigma_R, double* table_F,
-                                          void* hip_stream)
+pino_status pino_collapse_ellipsoid_table_mg(pino_ctx* ctx, int32_t cosmo, double sigma_R, double mu0,
+                                             double* table_F, void* hip_stream)
 {
     if (!ctx) {
         g_init_error = "ctx is NULL";
@@ -732,17 +732,35 @@ pino_status pino_collapse_ellipsoid_table(pino_ctx* ctx, int32_t cosmo, double s
         ctx->err = "the ellipsoid table needs 0 < omega_m <= 1 (flat, no radiation)";
         return PINO_ERR_ARG;
     }
+    // mu(a) = 1 + mu0 / E^2 stays positive for mu0 > -(1 - omega_m); without
+    // a cosmological constant 1/E^2 = a^3 grows without bound, so only 0
+    if (!std::isfinite(mu0) || (om < 1.0 ? !(mu0 > -(1.0 - om)) : mu0 != 0.0)) {
+        ctx->err = "mu0 must be finite and > -(1 - omega_m) (and 0 when omega_m = 1)";
+        return PINO_ERR_ARG;
+    }
     PINO_HIP(ctx, hipSetDevice(ctx->device));
-    if (ctx->ell_D1.empty())
-        ctx->ell_D1.assign(ctx->n_cosmo, 0.0);
-    if (!(ctx->ell_D1[cosmo] > 0.0))
-        ctx->ell_D1[cosmo] = ell_growth_today(om);
+    double D1;
+    if (mu0 == 0.0) {
+        if (ctx->ell_D1.empty())
+            ctx->ell_D1.assign(ctx->n_cosmo, 0.0);
+        if (!(ctx->ell_D1[cosmo] > 0.0))
+            ctx->ell_D1[cosmo] = ell_growth_today(om, 0.0);
+        D1 = ctx->ell_D1[cosmo];
+    } else {
+        D1 = ell_growth_today(om, mu0);  // a few ms on the host
+    }
     const int64_t nodes = (int64_t)ctx->nx * ctx->ny * ctx->nd;
     hipLaunchKernelGGL(k_ellipsoid_table, dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0,
                        static_cast<hipStream_t>(hip_stream), ctx->d_tknots, ctx->nx, ctx->ny, ctx->nd, sigma_R, om,
-                       ctx->ell_D1[cosmo], table_F);
+                       mu0, D1, table_F);
     PINO_HIP(ctx, hipGetLastError());
     return PINO_OK;
+}
+
+pino_status pino_collapse_ellipsoid_table(pino_ctx* ctx, int32_t cosmo, double sigma_R, double* table_F,
+                                          void* hip_stream)
+{
+    return pino_collapse_ellipsoid_table_mg(ctx, cosmo, sigma_R, 0.0, table_F, hip_stream);
 }
 
 pino_status pino_collapse_lpt_coefficients(pino_ctx* ctx, int32_t cosmo, double* k2, double* k3a, double* k3b)

@@ -25,7 +25,7 @@ void orc_update_radius(int64_t n, const double *hxx, const double *hyy, const do
 int orc_lpt_growth(double om, int nk, const double *ak, double *k2, double *k3a, double *k3b);
 double orc_collapse_D_lcdm(const double lam[3], int nk, const double *D, const double *k2, const double *m2,
                            const double *k3a, const double *m3a, const double *k3b, const double *m3b, int *found);
-double orc_ellipsoid_F(const double lam[3], double om, double a_i, double a_stop, double h, double kappa,
+double orc_ellipsoid_F(const double lam[3], double om, double mu0, double a_i, double a_stop, double h, double kappa,
                        double *a_c);
 double orc_growth_D(double om, double a);
 
@@ -96,8 +96,9 @@ int main(void)
     /* ellipsoid: a sphere and an ellipsoid with a coarse step */
     {
         double sph[3] = {1, 1, 1}, ell[3] = {1.0, 0.5, -0.2}, ac;
-        (void)orc_ellipsoid_F(sph, 1.0, 1e-4, 10.0, 5e-2, 0.1, &ac);
-        (void)orc_ellipsoid_F(ell, 0.3, 1e-4, 10.0, 5e-2, 0.1, &ac);
+        (void)orc_ellipsoid_F(sph, 1.0, 0.0, 1e-4, 10.0, 5e-2, 0.1, &ac);
+        (void)orc_ellipsoid_F(ell, 0.3, 0.0, 1e-4, 10.0, 5e-2, 0.1, &ac);
+        (void)orc_ellipsoid_F(ell, 0.3, 0.4, 1e-4, 10.0, 5e-2, 0.1, &ac);
     }
     printf("ok\n");
     return 0;

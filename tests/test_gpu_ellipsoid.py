@@ -137,6 +137,95 @@ def test_tabulated_with_ellipsoid_tables(pkg, orc):
     print("Tabulated (ellipsoid tables) vs oracle", st, "near ties", int(close.sum()), flush=True)
 
 
+@pytest.mark.parametrize("mu0", [0.4, -0.3])
+def test_ellipsoid_table_mg_vs_oracle(pkg, orc, mu0):
+    """The modified-gravity option (perturbations' gravity scaled by
+    mu(a) = 1 + mu0 / E(a)^2) against the oracle's integration with the same
+    option, node for node; mu0 = 0 through the same entry point equals the
+    standard table bit for bit."""
+    from paper_2510_02873_amd import _abi
+    knots = _knots(6, 5, 10)
+    a, D = synth.growth_table(0.3, mu0=mu0)
+    n = 6 * 5 * 10
+    with pkg.Collapse([(a, D, 0.3)], method=pkg.PINO_TABULATED, table_knots=knots) as col:
+        F = torch.empty(n, dtype=torch.float64, device="cuda")
+        F0 = torch.empty(n, dtype=torch.float64, device="cuda")
+        Fp = torch.empty(n, dtype=torch.float64, device="cuda")
+        _abi.pino_collapse_ellipsoid_table_mg(col.ctx, 0, 1.3, mu0, F)
+        _abi.pino_collapse_ellipsoid_table_mg(col.ctx, 0, 1.3, 0.0, F0)
+        _abi.pino_collapse_ellipsoid_table(col.ctx, 0, 1.3, Fp)
+        torch.cuda.synchronize()
+        assert torch.equal(F0, Fp)
+        got = F.cpu().numpy().reshape(6, 5, 10)
+    xk, yk, dk = (np.asarray(k) * 1.3 for k in knots)
+    ref = orc.ellipsoid_table(xk, yk, dk, 0.3, mu0=mu0)
+    assert np.array_equal(got > 0, ref > 0)
+    pos = ref > 0
+    rel = np.abs(got[pos] / ref[pos] - 1)
+    shift = np.abs(got[pos] / F0.cpu().numpy().reshape(6, 5, 10)[pos] - 1)
+    print(f"MG ellipsoid table mu0={mu0}: max rel vs oracle {rel.max():.2e}; F moved from general relativity by "
+          f"median {np.median(shift):.2e}", flush=True)
+    assert rel.max() <= F_TOL
+    # F = 1/D_c in the option's own linear growth moves little (the linear
+    # density at collapse depends weakly on a scale-independent mu), but
+    # far above the tolerance
+    assert np.median(shift) > 2e-5
+
+
+def test_tabulated_with_mg_tables(pkg, orc):
+    """C1 through the Tabulated method with modified-gravity tables (mu0 =
+    0.4) and the growth table of the same option, against the oracle's
+    Tabulated method on its own tables of that option."""
+    from paper_2510_02873_amd import _abi
+    from tests._helpers import c1_inputs, run_gpu_radii
+    mu0 = 0.4
+    cfg, slabs, _, _ = c1_inputs()
+    om = cfg["cosmo"].omega_m
+    a, D = synth.growth_table(om, mu0=mu0)
+    sig = synth.grid_sigma_gauss(cfg["n_side"], cfg["box"], cfg["radii"], cfg["cosmo"])
+    knots = _knots(5, 4, 12)
+    tabs_o = []
+    for sR in sig:
+        xk, yk, dk = (np.asarray(k) * sR for k in knots)
+        tabs_o.append(orc.Table(xk, yk, dk, orc.ellipsoid_table(xk, yk, dk, om, mu0=mu0)))
+    with pkg.Collapse([(a, D, om)], method=pkg.PINO_TABULATED, table_knots=knots) as col:
+        tabs_g = []
+        for sR in sig:
+            F = torch.empty(5 * 4 * 12, dtype=torch.float64, device="cuda")
+            _abi.pino_collapse_ellipsoid_table_mg(col.ctx, 0, sR, mu0, F)
+            tabs_g.append(F)
+        got = run_gpu_radii(col, [h.cuda() for h in slabs], sigmas=sig, tables=tabs_g)
+    g = orc.Growth(a, D)
+    ref = orc.collapse([h.numpy() for h in slabs], g, method=orc.TABULATED, tables=tabs_o)
+    per_r = []
+    for r, h in enumerate(slabs):
+        n = h.shape[1]
+        f, rr = np.zeros(n), np.full(n, -1, np.int32)
+        orc.update_radius(h.numpy(), 0, g, f, rr, None, reset=True, method=orc.TABULATED, table=tabs_o[r])
+        per_r.append(f)
+    srt = np.sort(np.array(per_r), axis=0)
+    close = np.abs(srt[-1] - srt[-2]) <= 4e-6 * srt[-1]
+    # the tables agree node for node to ~1e-8; the interpolant is linear in
+    # them, but where F is near 0 (a collapse a thousand times later than
+    # today) its chord and second-derivative terms cancel, so there the gate
+    # is absolute (node errors of 1e-8 move such F by ~1e-10)
+    Fr, Rr, Ar = ref
+    F, R, A = got
+    small = Fr < 1e-3
+    assert np.array_equal(F > 0, Fr > 0)
+    assert np.all(np.abs(F[small] - Fr[small]) <= 1e-9)
+    big = ~small
+    rel = np.abs(1 / F[big] - 1 / Fr[big]) * Fr[big]
+    fin = np.isfinite(Ar)
+    assert np.array_equal(np.isfinite(A), fin)
+    rel_a = np.abs(A[fin] - Ar[fin]) / Ar[fin]
+    print(f"Tabulated (MG ellipsoid tables, mu0 = 0.4) vs oracle: D_c max rel {rel.max():.2e} (F >= 1e-3), "
+          f"|dF| max {np.abs(F[small] - Fr[small]).max() if small.any() else 0:.2e} ({int(small.sum())} with "
+          f"F < 1e-3), a_coll max rel {rel_a.max():.2e}, near ties {int(close.sum())}", flush=True)
+    assert rel.max() <= 1e-6 and rel_a.max() <= 1e-6
+    assert np.all((R == Rr) | close | small)
+
+
 def test_ellipsoid_table_args(pkg):
     from paper_2510_02873_amd import _abi
     a, D = synth.growth_table(0.3)
@@ -148,3 +237,14 @@ def test_ellipsoid_table_args(pkg):
         for cosmo, s in ((1, 1.0), (0, 0.0), (0, float("nan"))):
             with pytest.raises(pkg.PinoError):
                 _abi.pino_collapse_ellipsoid_table(col.ctx, cosmo, s, F)
+        # the modified-gravity option: mu must stay positive, and 0 without
+        # a cosmological constant
+        for mu0 in (-0.8, float("nan"), float("inf")):
+            with pytest.raises(pkg.PinoError):
+                _abi.pino_collapse_ellipsoid_table_mg(col.ctx, 0, 1.0, mu0, F)
+    a1, D1 = synth.growth_table(1.0)
+    with pkg.Collapse([(a1, D1, 1.0)], method=pkg.PINO_TABULATED, table_knots=_knots(2, 2, 4)) as col:
+        with pytest.raises(pkg.PinoError):
+            _abi.pino_collapse_ellipsoid_table_mg(col.ctx, 0, 1.0, 0.1, F)
+        _abi.pino_collapse_ellipsoid_table_mg(col.ctx, 0, 1.0, 0.0, torch.empty(16, dtype=torch.float64,
+                                                                                 device="cuda"))

@@ -14,7 +14,15 @@ Tabulated table), CPU only.
   * early times: the axes follow the Zel'dovich solution 1 - l_i D (an error
     in the sign or the trace of the external tide shows here), and a sphere
     follows the third-order series 1 - u - (3/7) u^2 - (23/63) u^3, u = l D;
-  * the oracle's step converges: halving it moves F by < 2e-8.
+  * the oracle's step converges: halving it moves F by < 2e-8;
+  * the modified-gravity option (perturbations' gravity scaled by
+    mu(a) = 1 + mu0 / E(a)^2): mu0 = 0 is the general-relativity result bit
+    for bit; the linear growth against scipy's integration of
+    D'' + (2 - 1.5 Om(a)) D' = 1.5 Om(a) mu(a) D; a top hat against scipy's
+    mass shell with the perturbation's gravity scaled,
+    d2R/dt2 = -(Om/2) a^-3 R (1 + mu delta) + (1 - Om) R, 1 + delta = (a/R)^3;
+    from the same initial perturbation, stronger gravity (mu0 > 0) collapses
+    every ellipsoid earlier.
 """
 
 import numpy as np
@@ -128,3 +136,98 @@ def test_oracle_step_converged(orc):
 def test_no_collapse_of_underdense_ellipsoids(orc):
     F, ac = orc.ellipsoid_F([-0.1, -0.3, -0.5], 0.3)
     assert F == 0.0 and ac == orc.ELL_A_STOP
+
+
+def _mu(om, mu0, a):
+    return 1.0 + mu0 / (om / a ** 3 + 1.0 - om)
+
+
+def _mg_growth(om, mu0):
+    """Growing mode of D'' + (2 - 1.5 Om(a)) D' - 1.5 Om(a) mu(a) D = 0 in
+    s = ln a (scipy, dense), started in the EdS mode D = a at a = 1e-8
+    (mu - 1 ~ 1e-24 there); returns D(a) for scalar a."""
+    def rhs(s, y):
+        a = np.exp(s)
+        oma = om / a ** 3 / (om / a ** 3 + 1.0 - om)
+        return [y[1], -(2.0 - 1.5 * oma) * y[1] + 1.5 * oma * _mu(om, mu0, a) * y[0]]
+    s0 = np.log(1e-8)
+    sol = solve_ivp(rhs, [s0, np.log(12.0)], [1e-8, 1e-8], method="DOP853", rtol=1e-13, atol=1e-30,
+                    dense_output=True)
+    return lambda a: sol.sol(np.log(a))[0]
+
+
+def _mg_sphere_reference(lam, om, mu0, a_s=1e-3):
+    """Top hat of linear eigenvalue lam in flat LCDM with the perturbation's
+    gravity scaled by mu(a): scipy mass shell in cosmic time,
+    d2R/dt2 = -(Om/2) a^-3 R (1 + mu delta) + (1 - Om) R, 1 + delta = (a/R)^3,
+    started at a_s in the third-order spherical growing mode (mu - 1 ~ 1e-9
+    there), until R = 1e-7 a; D from _mg_growth, normalised at a = 1."""
+    ol = 1 - om
+    E = lambda a: np.sqrt(om / a ** 3 + ol)
+    D = _mg_growth(om, mu0)
+    D1 = D(1.0)
+    eps = 1e-6
+    u = lam * D(a_s) / D1
+    dlnD = (np.log(D(a_s * (1 + eps))) - np.log(D(a_s * (1 - eps)))) / (2 * eps)
+    du = u * dlnD * E(a_s)                   # du/dt = u (dlnD/dlna) H
+    R0 = a_s * (1 - u - 3.0 / 7.0 * u ** 2 - 23.0 / 63.0 * u ** 3)
+    V0 = a_s * E(a_s) * R0 / a_s + a_s * (-1 - 6.0 / 7.0 * u - 23.0 / 21.0 * u ** 2) * du
+
+    def rhs(t, y):
+        a, R, V = y
+        delta = (a / R) ** 3 - 1.0
+        return [a * E(a), V, -0.5 * om / a ** 3 * R * (1.0 + _mu(om, mu0, a) * delta) + ol * R]
+
+    ev = lambda t, y: y[1] - 1e-7 * y[0]
+    ev.terminal = True
+    sol = solve_ivp(rhs, [0, 50], [a_s, R0, V0], method="DOP853", rtol=1e-13, atol=1e-30, events=ev)
+    a_c = sol.y_events[0][0][0]
+    return D1 / D(a_c), a_c
+
+
+def test_mg_zero_is_general_relativity(orc):
+    for lam in ([1.0, 0.5, -0.2], [2.0, 2.0, 2.0], [0.3, -0.1, -0.4]):
+        assert orc.ellipsoid_F(lam, 0.3, mu0=0.0) == orc.ellipsoid_F(lam, 0.3)
+    assert orc.ellipsoid_growth1(0.3, 0.0) == orc.ellipsoid_growth1(0.3)
+
+
+@pytest.mark.parametrize("mu0", [0.5, -0.3])
+def test_mg_linear_growth_vs_scipy(orc, mu0):
+    # the oracle's D(1) of the mode started as D = a at 1e-7, against scipy's
+    ref = _mg_growth(0.3, mu0)(1.0)
+    got = orc.ellipsoid_growth1(0.3, mu0)
+    assert abs(got / ref - 1) <= 1e-8, (got, ref)
+    # gravity stronger today: more growth (and weaker: less)
+    assert (got > orc.ellipsoid_growth1(0.3)) == (mu0 > 0)
+
+
+@pytest.mark.parametrize("mu0", [0.5, -0.3])
+def test_mg_sphere_vs_mass_shell(orc, mu0):
+    for lam in (0.8, 2.0):
+        F_ref, a_ref = _mg_sphere_reference(lam, 0.3, mu0)
+        F, ac = orc.ellipsoid_F([lam] * 3, 0.3, mu0=mu0)
+        assert abs(F / F_ref - 1) <= 3e-7 * lam, (lam, F, F_ref)
+        assert abs(ac / a_ref - 1) <= 3e-7 * lam
+
+
+def test_mg_stronger_gravity_collapses_earlier(orc):
+    # the same initial perturbation (the eigenvalues are linear amplitudes
+    # today, so they scale with the option's own D(1)): stronger gravity of
+    # the perturbations collapses every ellipsoid earlier
+    d0 = orc.ellipsoid_growth1(0.3)
+    for lam in ([1.0, 0.5, -0.2], [0.8, 0.8, 0.8], [2.0, -0.5, -1.0]):
+        acs = [orc.ellipsoid_F(np.asarray(lam) * orc.ellipsoid_growth1(0.3, m) / d0, 0.3, mu0=m)[1]
+               for m in (-0.3, 0.0, 0.5)]
+        assert acs[0] > acs[1] > acs[2], (lam, acs)
+
+
+def test_synth_mg_growth_table_vs_scipy():
+    """The growth table the generator writes for the modified-gravity option
+    (the table that inverts D_c) against scipy's integration of the same
+    equation."""
+    import synth
+    for mu0 in (0.4, -0.3):
+        a, D = synth.growth_table(0.3, mu0=mu0)
+        ref = _mg_growth(0.3, mu0)
+        Dr = np.array([ref(x) for x in a]) / ref(1.0)
+        assert np.max(np.abs(D / Dr - 1)) <= 1e-9
