@@ -751,7 +751,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 (the per-particle "
+        print(json.dumps({"error": "this benchmark measures one GPU; --gpus must be 1 (the per-particle "
                                    "collapse path has no cross-GPU step, see the design notes on sharding)"}))
         sys.exit(2)
 

@@ -6,7 +6,7 @@ relative squared error over samples with target w > 0.  Written out layer by
 layer in numpy float64, forward and backward by the chain rule.
 
 bf16=True evaluates the network under the surrogate's BF16 rounding rule (a
-choice of this build, stated on its own; the paper has no network): the
+design choice stated on its own here; the paper has no network): the
 weights of the two 64 x 64 layers and the inputs of those layers and of the
 output layer (the ReLU outputs of layers 1, 2 and 3) are rounded to BF16
 (8 significant bits, round to nearest, ties to even); layer 1's weights and
