@@ -51,14 +51,13 @@ struct KappaSlope {
     double k2, k3a, k3b;
 };
 
-__device__ __forceinline__ double lcdm_G(double u, double il1, double b, double ca, double cb, KappaPiece& pc,
-                                         const double* g, const double* kap, int nk, const GrowthIndex& gi,
-                                         double& P, double& Q)
+// G at u with a fresh lookup of the ratios (the spline piece is not kept in
+// registers across the certificate: beside the network's weights it spilled)
+__device__ __forceinline__ double lcdm_G(double u, double il1, double b, double ca, double cb, const double* g,
+                                         const double* kap, int nk, const GrowthIndex& gi, double& P, double& Q)
 {
     const double D = u * il1;
-    if (!piece_holds(pc, D))
-        pc = kappa_piece(g, kap, nk, D, gi);
-    const Kappa k = kappa_eval(pc, D);
+    const Kappa k = kappa_eval(kappa_piece(g, kap, nk, D, gi), D);
     P = k.k2 * b;
     Q = k.k3a * ca + k.k3b * cb;
     return 1.0 + u * (-1.0 + u * (P + Q * u));
@@ -72,8 +71,7 @@ __device__ __forceinline__ bool certify_lcdm(double l1, double il1, double b, do
         return false;
     const double u0 = rcp2(y);
     const double D0 = u0 * il1;
-    KappaPiece pc = kappa_piece(g, kap, nk, D0, gi);
-    const Kappa k = kappa_eval(pc, D0);
+    const Kappa k = kappa_eval(kappa_piece(g, kap, nk, D0, gi), D0);
     const double P0 = k.k2 * b;
     const double Q0 = k.k3a * ca + k.k3b * cb;
     const double G0 = 1.0 + u0 * (-1.0 + u0 * (P0 + Q0 * u0));
@@ -85,8 +83,8 @@ __device__ __forceinline__ bool certify_lcdm(double l1, double il1, double b, do
     if (!(lo > 0.0) || !isfinite(u1))
         return false;
     double Pl, Ql, Ph, Qh;
-    const double Glo = lcdm_G(lo, il1, b, ca, cb, pc, g, kap, nk, gi, Pl, Ql);
-    const double Ghi = lcdm_G(hi, il1, b, ca, cb, pc, g, kap, nk, gi, Ph, Qh);
+    const double Glo = lcdm_G(lo, il1, b, ca, cb, g, kap, nk, gi, Pl, Ql);
+    const double Ghi = lcdm_G(hi, il1, b, ca, cb, g, kap, nk, gi, Ph, Qh);
     const bool bracket = Glo > 4.0 * g_bound(CubicU{Pl, Ql}, lo) && Ghi < -4.0 * g_bound(CubicU{Ph, Qh}, hi);
     const double es = ks.k2 * fabs(b) * lo + (ks.k3a * fabs(ca) + ks.k3b * fabs(cb)) * (lo * lo);
     if (!(es * lo < 1.0) || !(es < 1.0))
