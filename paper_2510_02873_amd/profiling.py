@@ -82,8 +82,13 @@ def kernel_digest(kernel, lib_path=None):
     st = symtab[0]
     strtab = heads[st[6]]
     # the name as a whole mangled component (length prefix, then the end of
-    # the nested name or a template argument list), so k_x does not match k_x_1
-    pat = re.compile(r"\d" + re.escape(kernel) + r"[EI]")
+    # the nested name or a template argument list), so k_x does not match k_x_1;
+    # "k_x<true>" / "k_x<false>" name one instance of a bool template
+    inst = re.fullmatch(r"(\w+)<(true|false)>", kernel)
+    if inst:
+        pat = re.compile(r"\d" + re.escape(inst.group(1)) + r"ILb" + ("1" if inst.group(2) == "true" else "0") + "E")
+    else:
+        pat = re.compile(r"\d" + re.escape(kernel) + r"[EI]")
     found = {}
     for k in range(st[5] // 24):
         st_name, st_info, _, st_shndx, st_value, st_size = struct.unpack_from("<IBBHQQ", co, st[4] + 24 * k)
