@@ -215,13 +215,48 @@ __device__ __forceinline__ double cubic_top_w(const CubicU& k)
     return w;
 }
 
-// Newton steps on G after the frozen-ratio root: that root is within about
-// 1e-5 of G's, so two steps reach the rounding level (a third moves D_c by
+// Newton steps on G.  From the Einstein-de Sitter root (within the LCDM
+// correction, under 1 %, of G's root) three steps reach the rounding level;
+// from the frozen-ratio root (within about 1e-5) two do (a third moves D_c by
 // under 1e-15 relative over 256^3 particles x 25 radii).
+constexpr int kLcdmNewtonFromEds = 3;
 constexpr int kLcdmNewton = 2;
+
+// n Newton steps on G from u; returns false if the last step still moved u
+// by more than 1e-7 of it (with quadratic convergence the error left after
+// a step of 1e-7 is of order 1e-14 times G''/G' u), or G does not cross
+// downward there (the first root of G, which starts at G(0) = 1, is a
+// downward crossing).
+__device__ __forceinline__ bool lcdm_newton(double& u, int n, double il1, double b, double ca, double cb,
+                                            const double* g, const double* kap, int nk, const GrowthIndex& gi)
+{
+    KappaPiece pc = kappa_piece(g, kap, nk, u * il1, gi);
+    double du = 0.0, dG = -1.0;
+    for (int it = 0; it < n; ++it) {
+        const double Dq = u * il1;
+        if (!piece_holds(pc, Dq))
+            pc = kappa_piece(g, kap, nk, Dq, gi);
+        const Kappa k = kappa_eval(pc, Dq);
+        const double P = k.k2 * b;
+        const double Q = k.k3a * ca + k.k3b * cb;
+        const double G = 1.0 + u * (-1.0 + u * (P + Q * u));
+        dG = -1.0 + u * (2.0 * P + 3.0 * Q * u) + (u * u) * il1 * (k.d2 * b + u * (k.d3a * ca + k.d3b * cb));
+        du = G * rcp2(dG);
+        u -= du;
+    }
+    return fabs(du) <= 1e-7 * fabs(u) && dG < 0.0;
+}
 
 // F = 1/D_c with the LCDM coefficients, 0 without collapse.  g: the growth
 // knots [D | a | M] (D used), kap: the ratio rows (LDS).
+//
+// Fast path: Newton on G from the first root u_e of the Einstein-de Sitter
+// cubic, accepted when it converged to a downward crossing within 5 % of
+// u_e (the ratios move by about 1 % over the table, so G's first root is
+// that close to u_e unless G is nearly tangent there).  Otherwise (or with
+// no EdS root) the robust path: the cubic with the ratios frozen at D_e (or
+// at the last knot) gives the first root of a cubic within about 1e-5 of G,
+// then Newton steps.
 __device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const double* g, const double* kap, int nk,
                                          const GrowthIndex& gi)
 {
@@ -233,27 +268,20 @@ __device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const d
     const double b = (-3.0 / 14.0) * sg;
     const double ca = pi * (1.0 / 9.0);
     const double cb = -(sg * (1.0 / 56.0) + pi * (2.0 / 56.0) + (17.0 / 168.0) * (sg * sg));
-    // first root of the Einstein-de Sitter cubic; without one, of the cubic
-    // with the ratios of the last knot (the largest)
     double w = cubic_top_w(CubicU{b, ca + cb});
+    if (w > 0.0) {
+        const double ue = rcp2(w);
+        double u = ue;
+        if (lcdm_newton(u, kLcdmNewtonFromEds, il1, b, ca, cb, g, kap, nk, gi) && fabs(u - ue) <= 0.05 * ue)
+            return l1 * rcp2(u);
+    }
     const double De = w > 0.0 ? rcp2(l1 * w) : g[nk - 1];
-    Kappa k = kappa_eval(kappa_piece(g, kap, nk, De, gi), De);
+    const Kappa k = kappa_eval(kappa_piece(g, kap, nk, De, gi), De);
     w = cubic_top_w(CubicU{k.k2 * b, k.k3a * ca + k.k3b * cb});
     if (!(w > 0.0))
         return 0.0;
     double u = rcp2(w);
-    KappaPiece pc = kappa_piece(g, kap, nk, u * il1, gi);
-    for (int it = 0; it < kLcdmNewton; ++it) {
-        const double Dq = u * il1;
-        if (!piece_holds(pc, Dq))
-            pc = kappa_piece(g, kap, nk, Dq, gi);
-        k = kappa_eval(pc, Dq);
-        const double P = k.k2 * b;
-        const double Q = k.k3a * ca + k.k3b * cb;
-        const double G = 1.0 + u * (-1.0 + u * (P + Q * u));
-        const double dG = -1.0 + u * (2.0 * P + 3.0 * Q * u) + (u * u) * il1 * (k.d2 * b + u * (k.d3a * ca + k.d3b * cb));
-        u -= G * rcp2(dG);
-    }
+    lcdm_newton(u, kLcdmNewton, il1, b, ca, cb, g, kap, nk, gi);
     return u > 0.0 ? l1 * rcp2(u) : 0.0;
 }
 
