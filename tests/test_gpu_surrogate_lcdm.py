@@ -173,3 +173,29 @@ def test_lcdm_certificate_never_accepts_a_wrong_root(P, orc, w):
     print(f"constant w = {w}: certified {stats['certified']} of {stats['certified'] + stats['fallback']} "
           f"consulted", flush=True)
     _gate(ref, got, skip, f"constant network w = {w}")
+
+
+@pytest.mark.parametrize("nk", [1024, 511])
+def test_lcdm_surrogate_large_and_odd_growth_tables(P, orc, nk):
+    """Growth tables of 1024 knots (knots, index, weight fragments and the
+    six ratio rows need about 115 KB of LDS, past the default 64 KiB) and of
+    an odd knot count (ratio rows of odd length, so every other row starts
+    off a 16-byte boundary): the LCDM surrogate with the Zel'dovich-guess network matches
+    the oracle's LCDM solve within the certified 1e-6 on four C1 radii.  A
+    table of 2048 knots needs more LDS than a workgroup has and is refused
+    at init."""
+    Pk, A = P
+    from paper_2510_02873_amd import surrogate
+    slabs, sig, _, _, om = _c1()
+    slabs, sig = slabs[::6], sig[::6]
+    a, D = synth.growth_table(om, nk)
+    host = [h.cpu().numpy() for h in slabs]
+    ref, skip, _ = _lcdm_ref(orc, host, a, D, om)
+    skip = _skip_mask(orc, host, a, D, om, skip)
+    got, _ = _run(Pk, A, surrogate.constant_blob(1.0), slabs, sig, a, D, om)
+    _gate(ref, got, skip, f"LCDM surrogate with {nk} growth knots")
+    a2, D2 = synth.growth_table(om, 2048)
+    with pytest.raises(Pk.PinoError) as e:
+        Pk.Collapse([(a2, D2, om)], method=Pk.PINO_CLASSIC_LCDM, precision=Pk.PINO_SURROGATE,
+                    mlp_blob=surrogate.constant_blob(1.0))
+    assert e.value.status == Pk.PINO_ERR_UNSUPPORTED
