@@ -211,7 +211,7 @@ def _check_mixed_tab(ref, got, per_r, b, label):
 
 
 def test_mixed_tabulated_c1(pkg, orc):
-    """Mixed-precision Tabulated at C1 (32^3 x 25 radii, 64 x 64 x 128 tables):
+    """Mixed-precision Tabulated at C1 (32^3 x 4 radii, 64 x 64 x 128 tables):
     against the oracle on the same (FP32) inputs, F within the bound set by
     the FP32 table, radius index exact outside near-ties, a_coll within that
     bound plus the FP32 spline."""

@@ -124,7 +124,7 @@ def test_lcdm_features_vs_oracle(P, orc):
 
 
 def test_lcdm_surrogate_parity_and_gain(P, orc, lcdm_net):
-    """C1 (32^3 x 25 radii, Omega_m = 0.3) through the LCDM surrogate path
+    """C1 (32^3 x 4 radii, Omega_m = 0.3) through the LCDM surrogate path
     against the oracle's LCDM solve on the same FP64 Hessians; the gain over
     the same certificate without a trained network (constant Zel'dovich
     guess) is the certified fraction."""
