@@ -101,6 +101,10 @@ struct pino_ctx {
     // the growth knots (stride 6 * nk_max): the LCDM growth ratios of the
     // LPT terms and their natural-spline second derivatives in D
     double* d_kap = nullptr;
+    // the same splines as power-form coefficients per interval
+    // (kappa_poly_doubles(nk_max) per cosmology), when they fit in LDS
+    double* d_kpoly = nullptr;
+    bool lcdm_poly = false;
     // per cosmology, bounds on |d k / d ln D| of the three ratio splines over
     // the whole table (the surrogate's LCDM certificate)
     std::vector<double> kslope;

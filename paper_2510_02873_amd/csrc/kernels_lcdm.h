@@ -114,11 +114,63 @@ __global__ void __launch_bounds__(64) k_lpt_growth(const double* __restrict__ gr
     }
 }
 
-// LDS: the growth knots and index of stage_growth, then the six ratio rows
-// [k2 | k3a | k3b | m2 | m3a | m3b] of the item's cosmology (nk each).
+// LDS: the growth knots and index of stage_growth, then (from a 16-byte
+// boundary) the ratio splines of the item's cosmology: the six rows
+// [k2 | k3a | k3b | m2 | m3a | m3b] (nk each), or their power-form
+// coefficients (kappa_poly_doubles(nk), k_kappa_poly).
+__host__ __device__ inline size_t lcdm_table_offset(int nk, int nb)
+{
+    return (growth_lds_bytes(nk, nb) + 15) / 16 * 16;
+}
+
+__host__ __device__ inline size_t kappa_poly_doubles(int nk)
+{
+    return 12 * ((size_t)nk + 1);
+}
+
 __host__ __device__ inline size_t lcdm_lds_bytes(int nk, int nb)
 {
-    return growth_lds_bytes(nk, nb) + 6 * (size_t)nk * sizeof(double);
+    return lcdm_table_offset(nk, nb) + 6 * (size_t)nk * sizeof(double);
+}
+
+__host__ __device__ inline size_t lcdm_poly_lds_bytes(int nk, int nb)
+{
+    return lcdm_table_offset(nk, nb) + kappa_poly_doubles(nk) * sizeof(double);
+}
+
+// Power-form coefficients of the ratio splines, one thread per slot.  On
+// [D_i, D_{i+1}], with h = D_{i+1} - D_i and s = D - D_i, the natural spline
+// through (k_i, M_i) and (k_{i+1}, M_{i+1}) is
+//   k_i + ((k_{i+1} - k_i)/h - h (2 M_i + M_{i+1})/6) s + (M_i/2) s^2
+//       + ((M_{i+1} - M_i)/(6 h)) s^3.
+// cf: slot i < n - 1 (interval i) at 12 i as [k2: c0 c1 c2 c3 | k3a: ... |
+// k3b: ...]; slot n - 1 holds the constant piece at and above the last knot
+// (c0 = the end value, c1 = c2 = c3 = 0), slot n the one at and below the
+// first; kappa_poly_doubles(n) doubles.
+__global__ void __launch_bounds__(256) k_kappa_poly(const double* __restrict__ D, const double* __restrict__ kap,
+                                                   int n, double* __restrict__ cf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n)
+        return;
+    double* c = cf + 12 * i;
+    if (i < n - 1) {
+        const double h = D[i + 1] - D[i];
+        for (int j = 0; j < 3; ++j) {
+            const double k0 = kap[j * n + i], k1 = kap[j * n + i + 1];
+            const double m0 = kap[(3 + j) * n + i], m1 = kap[(3 + j) * n + i + 1];
+            c[4 * j] = k0;
+            c[4 * j + 1] = (k1 - k0) / h - h * (2.0 * m0 + m1) / 6.0;
+            c[4 * j + 2] = 0.5 * m0;
+            c[4 * j + 3] = (m1 - m0) / (6.0 * h);
+        }
+    } else {
+        const int e = i == n - 1 ? n - 1 : 0;
+        for (int j = 0; j < 3; ++j) {
+            c[4 * j] = kap[j * n + e];
+            c[4 * j + 1] = c[4 * j + 2] = c[4 * j + 3] = 0.0;
+        }
+    }
 }
 
 // The three ratios and their derivatives in D.
@@ -203,6 +255,92 @@ __device__ __forceinline__ Kappa kappa_eval(const KappaPiece& p, double Dq)
     return r;
 }
 
+// Where a solve reads the ratio splines.  KapRows: the six rows at the
+// knots, a piece rebuilt from them at each lookup (the layout every table
+// size fits).  KapPoly: the power-form coefficients of k_kappa_poly, so that
+// a lookup reads one interval's 96 contiguous bytes and a step costs five
+// FMAs per ratio.  D: the growth knots (D row); both in LDS or global memory.
+struct KapRows {
+    const double* D;
+    const double* kap;
+    int nk;
+    GrowthIndex gi;
+};
+
+struct KapPoly {
+    const double* D;
+    const double* cf;  // 16-byte aligned
+    int nk;
+    GrowthIndex gi;
+};
+
+__device__ __forceinline__ KappaPiece piece_at(const KapRows& r, double Dq)
+{
+    return kappa_piece(r.D, r.kap, r.nk, Dq, r.gi);
+}
+
+// One slot of KapPoly: an interval (c[j] the coefficients of ratio j in
+// s = D - lo) or a constant piece outside the knots (c[j][1..3] = 0), with
+// the interval test of KappaPiece.
+struct PolyPiece {
+    double lo, hi;
+    double c[3][4];
+    int kind;  // as KappaPiece
+};
+
+__device__ __forceinline__ bool piece_holds(const PolyPiece& p, double Dq)
+{
+    if (p.kind == 0)
+        return Dq > p.lo && Dq < p.hi;
+    return p.kind == 1 ? !(Dq > p.lo) : Dq >= p.hi;
+}
+
+__device__ __forceinline__ PolyPiece piece_at(const KapPoly& r, double Dq)
+{
+    const double* D = r.D;
+    const int nk = r.nk;
+    PolyPiece p;
+    int i;
+    if (!(Dq > D[0]) || !(Dq < D[nk - 1])) {
+        const bool above = Dq > D[0];
+        p.kind = above ? 2 : 1;
+        p.lo = D[0];
+        p.hi = D[nk - 1];
+        i = above ? nk - 1 : nk;
+    } else {
+        i = r.gi.ok ? locate_indexed(D, nk, Dq, r.gi) : locate(D, nk, Dq);
+        p.kind = 0;
+        p.lo = D[i];
+        p.hi = D[i + 1];
+    }
+    // every slot is read the same way, so the coefficients need no merge
+    // of two branches
+    const d2v* q = reinterpret_cast<const d2v*>(r.cf + 12 * i);
+    for (int j = 0; j < 3; ++j) {
+        const d2v x = q[2 * j], y = q[2 * j + 1];
+        p.c[j][0] = x.x;
+        p.c[j][1] = x.y;
+        p.c[j][2] = y.x;
+        p.c[j][3] = y.y;
+    }
+    return p;
+}
+
+// the ratios and their derivatives at Dq: Horner's scheme, the derivative
+// from the same partial sums (synthetic division)
+__device__ __forceinline__ Kappa kappa_eval(const PolyPiece& p, double Dq)
+{
+    const double s = p.kind == 0 ? Dq - p.lo : 0.0;
+    double v[3], d[3];
+    for (int j = 0; j < 3; ++j) {
+        const double b2 = fma(p.c[j][3], s, p.c[j][2]);
+        const double b1 = fma(b2, s, p.c[j][1]);
+        v[j] = fma(b1, s, p.c[j][0]);
+        d[j] = fma(fma(p.c[j][3], s, b2), s, b1);
+    }
+    return Kappa{v[0], v[1], v[2], d[0], d[1], d[2]};
+}
+
 // w = 1/u of the first positive root of the cubic k (the Classic solver),
 // <= 0 without one
 __device__ __forceinline__ double cubic_top_w(const CubicU& k)
@@ -227,15 +365,16 @@ constexpr int kLcdmNewton = 2;
 // a step of 1e-7 is of order 1e-14 times G''/G' u), or G does not cross
 // downward there (the first root of G, which starts at G(0) = 1, is a
 // downward crossing).
+template <class Src>
 __device__ __forceinline__ bool lcdm_newton(double& u, int n, double il1, double b, double ca, double cb,
-                                            const double* g, const double* kap, int nk, const GrowthIndex& gi)
+                                            const Src& src)
 {
-    KappaPiece pc = kappa_piece(g, kap, nk, u * il1, gi);
+    auto pc = piece_at(src, u * il1);
     double du = 0.0, dG = -1.0;
     for (int it = 0; it < n; ++it) {
         const double Dq = u * il1;
         if (!piece_holds(pc, Dq))
-            pc = kappa_piece(g, kap, nk, Dq, gi);
+            pc = piece_at(src, Dq);
         const Kappa k = kappa_eval(pc, Dq);
         const double P = k.k2 * b;
         const double Q = k.k3a * ca + k.k3b * cb;
@@ -247,8 +386,8 @@ __device__ __forceinline__ bool lcdm_newton(double& u, int n, double il1, double
     return fabs(du) <= 1e-7 * fabs(u) && dG < 0.0;
 }
 
-// F = 1/D_c with the LCDM coefficients, 0 without collapse.  g: the growth
-// knots [D | a | M] (D used), kap: the ratio rows (LDS).
+// F = 1/D_c with the LCDM coefficients, 0 without collapse; src: the growth
+// knots and ratio splines (KapRows or KapPoly).
 //
 // Fast path: Newton on G from the first root u_e of the Einstein-de Sitter
 // cubic, accepted when it converged to a downward crossing within 5 % of
@@ -257,8 +396,8 @@ __device__ __forceinline__ bool lcdm_newton(double& u, int n, double il1, double
 // no EdS root) the robust path: the cubic with the ratios frozen at D_e (or
 // at the last knot) gives the first root of a cubic within about 1e-5 of G,
 // then Newton steps.
-__device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const double* g, const double* kap, int nk,
-                                         const GrowthIndex& gi)
+template <class Src>
+__device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const Src& src)
 {
     if (!(l1 > 0.0))
         return 0.0;
@@ -272,42 +411,53 @@ __device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const d
     if (w > 0.0) {
         const double ue = rcp2(w);
         double u = ue;
-        if (lcdm_newton(u, kLcdmNewtonFromEds, il1, b, ca, cb, g, kap, nk, gi) && fabs(u - ue) <= 0.05 * ue)
+        if (lcdm_newton(u, kLcdmNewtonFromEds, il1, b, ca, cb, src) && fabs(u - ue) <= 0.05 * ue)
             return l1 * rcp2(u);
     }
-    const double De = w > 0.0 ? rcp2(l1 * w) : g[nk - 1];
-    const Kappa k = kappa_eval(kappa_piece(g, kap, nk, De, gi), De);
+    const double De = w > 0.0 ? rcp2(l1 * w) : src.D[src.nk - 1];
+    const Kappa k = kappa_eval(piece_at(src, De), De);
     w = cubic_top_w(CubicU{k.k2 * b, k.k3a * ca + k.k3b * cb});
     if (!(w > 0.0))
         return 0.0;
     double u = rcp2(w);
-    lcdm_newton(u, kLcdmNewton, il1, b, ca, cb, g, kap, nk, gi);
+    lcdm_newton(u, kLcdmNewton, il1, b, ca, cb, src);
     return u > 0.0 ? l1 * rcp2(u) : 0.0;
 }
 
 // Per-radius kernels of the LCDM method, with the update of update_max.
-// Blocks of up to 512 lanes: the LDS a block stages (about 45 KB for 512
-// knots) allows three blocks per CU, so larger blocks keep more waves
-// resident.
+// Blocks of up to 512 lanes: the LDS a block stages (about 70 KB with the
+// power-form coefficients of 512 knots) allows two blocks per CU, as many
+// as the registers do.  POLY: the ratios from the power-form coefficients
+// (kap_all: kappa_poly_doubles(nk) doubles), else from the six rows.
+template <bool POLY>
+struct KapSrc {
+    using type = KapRows;
+};
+template <>
+struct KapSrc<true> {
+    using type = KapPoly;
+};
 
-__device__ __forceinline__ double lcdm_of(const Hess64& h, const double* g, const double* kap, int nk,
-                                          const GrowthIndex& gi)
+template <class Src>
+__device__ __forceinline__ double lcdm_of(const Hess64& h, const Src& src)
 {
     double l1, s, pp;
     eig_top(h, l1, s, pp);
-    return lcdm_F(l1, s, pp, g, kap, nk, gi);
+    return lcdm_F(l1, s, pp, src);
 }
 
 // One particle per lane over a grid-stride loop (arrays not 16-byte
 // aligned), the next element's loads issued before the current element's
 // arithmetic.
+template <bool POLY>
 __global__ void __launch_bounds__(512) k_classic_lcdm_1(ItemArgs a, const double* __restrict__ kap_all)
 {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     const GrowthIndex gi = stage_growth(lds, a);
-    double* kap = lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
-    stage(kap, kap_all, 6 * a.nk);
+    double* kap = lds + lcdm_table_offset(a.nk, a.gi.nb) / sizeof(double);
+    stage(kap, kap_all, POLY ? (int)kappa_poly_doubles(a.nk) : 6 * a.nk);
     __syncthreads();
+    const typename KapSrc<POLY>::type src{lds, kap, (int)a.nk, gi};
     const uint32_t n = (uint32_t)a.n;
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,7 +475,7 @@ __global__ void __launch_bounds__(512) k_classic_lcdm_1(ItemArgs a, const double
             hn = load_h64(a, next);
             fn = a.reset ? 0.0 : *elem(a.Fmax, next);
         }
-        update_max(a, lds, gi, i, lcdm_of(h, lds, kap, a.nk, gi), fm);
+        update_max(a, lds, gi, i, lcdm_of(h, src), fm);
     }
 }
 
@@ -333,13 +483,15 @@ __global__ void __launch_bounds__(512) k_classic_lcdm_1(ItemArgs a, const double
 // solves per lane, whose dependent FP64 chains the scheduler interleaves,
 // and whole-line paired loads and stores.  Alignment as k_classic_f64 (host
 // check); an odd last element is done by one lane at the end.
+template <bool POLY>
 __global__ void __launch_bounds__(512) k_classic_lcdm(ItemArgs a, const double* __restrict__ kap_all)
 {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     const GrowthIndex gi = stage_growth(lds, a);
-    double* kap = lds + growth_lds_bytes(a.nk, a.gi.nb) / sizeof(double);
-    stage(kap, kap_all, 6 * a.nk);
+    double* kap = lds + lcdm_table_offset(a.nk, a.gi.nb) / sizeof(double);
+    stage(kap, kap_all, POLY ? (int)kappa_poly_doubles(a.nk) : 6 * a.nk);
     __syncthreads();
+    const typename KapSrc<POLY>::type src{lds, kap, (int)a.nk, gi};
     const uint32_t n = (uint32_t)a.n;
     const uint32_t np = n / 2;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -360,14 +512,14 @@ __global__ void __launch_bounds__(512) k_classic_lcdm(ItemArgs a, const double* 
             if (!a.reset)
                 fn = *reinterpret_cast<const d2v*>(elem(a.Fmax, 2 * next));
         }
-        const double F0 = lcdm_of(Hess64{h.xx.x, h.yy.x, h.zz.x, h.xy.x, h.xz.x, h.yz.x}, lds, kap, a.nk, gi);
-        const double F1 = lcdm_of(Hess64{h.xx.y, h.yy.y, h.zz.y, h.xy.y, h.xz.y, h.yz.y}, lds, kap, a.nk, gi);
+        const double F0 = lcdm_of(Hess64{h.xx.x, h.yy.x, h.zz.x, h.xy.x, h.xz.x, h.yz.x}, src);
+        const double F1 = lcdm_of(Hess64{h.xx.y, h.yy.y, h.zz.y, h.xy.y, h.xz.y, h.yz.y}, src);
         update_pair(a, lds, gi, p, F0, F1, fm);
     }
     if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t i = n - 1;
         const double fm = a.reset ? 0.0 : *elem(a.Fmax, i);
-        update_max(a, lds, gi, i, lcdm_of(load_h64(a, i), lds, kap, a.nk, gi), fm);
+        update_max(a, lds, gi, i, lcdm_of(load_h64(a, i), src), fm);
     }
 }
 

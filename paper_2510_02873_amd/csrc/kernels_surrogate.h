@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         eig_top(load_h64(a, i), l1, s, pp);
         double F;
         if constexpr (LCDM)
-            F = lcdm_F(l1, s, pp, lds, kap, a.nk, gi);
+            F = lcdm_F(l1, s, pp, KapRows{lds, kap, (int)a.nk, gi});
         else
             F = classic_F(l1, s, pp);
         if (F > *elem(a.Fmax, i)) {
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(256) k_features(ItemArgs a, bool f32, double s
     if (W) {
         double F = 0.0;
         if (consult)
-            F = kap ? lcdm_F(l1, s, pp, a.growth, kap, a.nk, a.gi) : classic_F(l1, s, pp);
+            F = kap ? lcdm_F(l1, s, pp, KapRows{a.growth, kap, (int)a.nk, a.gi}) : classic_F(l1, s, pp);
         W[i] = F > 0.0 ? (float)(F / l1) : 0.0f;
     }
 }

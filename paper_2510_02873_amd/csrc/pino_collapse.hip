@@ -271,7 +271,7 @@ void free_all(pino_ctx* c)
     if (!c)
         return;
     void* ptrs[] = {c->d_growth, c->d_growth32, c->d_gidx, c->d_tknots, c->d_tidx, c->d_tcoef, c->d_tab, c->d_tab32,
-                    c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_kap};
+                    c->d_tmp, c->d_mlp, c->d_counters, c->d_queue, c->d_kap, c->d_kpoly};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -285,6 +285,7 @@ void free_all(pino_ctx* c)
     c->d_counters = nullptr;
     c->d_queue = nullptr;
     c->d_kap = nullptr;
+    c->d_kpoly = nullptr;
     c->order.destroy();
 }
 
@@ -424,12 +425,27 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
                 c->kslope[3 * (size_t)k + j] = 1.01 * m;
             }
         }
-        const size_t need = lcdm_lds_bytes(nk_max, index_bins(nk_max));
+        // the collapse kernels read the power-form coefficients where they
+        // fit in LDS (up to about 1200 knots), else the six rows
+        const size_t need_poly = lcdm_poly_lds_bytes(nk_max, index_bins(nk_max));
+        c->lcdm_poly = need_poly <= kLdsMax;
+        if (c->lcdm_poly) {
+            const size_t stride = kappa_poly_doubles(nk_max);
+            PINO_HIP(c, hipMalloc((void**)&c->d_kpoly, (size_t)cfg->n_cosmo * stride * sizeof(double)));
+            for (int k = 0; k < cfg->n_cosmo; ++k) {
+                const int n = c->nk[k];
+                hipLaunchKernelGGL(k_kappa_poly, dim3((n + 256) / 256), dim3(256), 0, 0,
+                                   c->d_growth + (size_t)k * 3 * nk_max, c->d_kap + (size_t)k * 6 * nk_max, n,
+                                   c->d_kpoly + (size_t)k * stride);
+                PINO_HIP(c, hipGetLastError());
+            }
+        }
+        const size_t need = c->lcdm_poly ? need_poly : lcdm_lds_bytes(nk_max, index_bins(nk_max));
+        const void* paired = c->lcdm_poly ? (const void*)k_classic_lcdm<true> : (const void*)k_classic_lcdm<false>;
+        const void* single = c->lcdm_poly ? (const void*)k_classic_lcdm_1<true> : (const void*)k_classic_lcdm_1<false>;
         if (need > kLdsBudget) {
-            PINO_HIP(c, hipFuncSetAttribute((const void*)k_classic_lcdm, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)need));
-            PINO_HIP(c, hipFuncSetAttribute((const void*)k_classic_lcdm_1,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+            PINO_HIP(c, hipFuncSetAttribute(paired, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+            PINO_HIP(c, hipFuncSetAttribute(single, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
         }
         if (const char* env = std::getenv("PINO_LCDM_BLOCK")) {
             const int v = std::atoi(env);
@@ -437,7 +453,7 @@ pino_status init_impl(const pino_config* cfg, pino_ctx* c)
                 c->lcdm_block = v;
         }
         int resident = 0;
-        PINO_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_classic_lcdm, c->lcdm_block, need));
+        PINO_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, paired, c->lcdm_block, need));
         c->lcdm_resident = std::max(1, resident);
     }
 
@@ -583,12 +599,20 @@ pino_status launch_item(pino_ctx* c, const pino_item& it, uint32_t flags, hipStr
                 const int64_t lanes = al ? (a.n + 1) / 2 : a.n;
                 const int lg = (int)std::max<int64_t>(
                     1, std::min<int64_t>((lanes + lb - 1) / lb, (int64_t)c->cu_count * c->lcdm_resident));
-                const double* kap = c->d_kap + (size_t)it.cosmo * 6 * c->nk_max;
-                const size_t llds = lcdm_lds_bytes(a.nk, a.gi.nb);
-                if (al) {
-                    hipLaunchKernelGGL(k_classic_lcdm, dim3(lg), dim3(lb), llds, st, a, kap);
+                if (c->lcdm_poly) {
+                    const double* kp = c->d_kpoly + (size_t)it.cosmo * kappa_poly_doubles(c->nk_max);
+                    const size_t llds = lcdm_poly_lds_bytes(a.nk, a.gi.nb);
+                    if (al)
+                        hipLaunchKernelGGL(k_classic_lcdm<true>, dim3(lg), dim3(lb), llds, st, a, kp);
+                    else
+                        hipLaunchKernelGGL(k_classic_lcdm_1<true>, dim3(lg), dim3(lb), llds, st, a, kp);
                 } else {
-                    hipLaunchKernelGGL(k_classic_lcdm_1, dim3(lg), dim3(lb), llds, st, a, kap);
+                    const double* kap = c->d_kap + (size_t)it.cosmo * 6 * c->nk_max;
+                    const size_t llds = lcdm_lds_bytes(a.nk, a.gi.nb);
+                    if (al)
+                        hipLaunchKernelGGL(k_classic_lcdm<false>, dim3(lg), dim3(lb), llds, st, a, kap);
+                    else
+                        hipLaunchKernelGGL(k_classic_lcdm_1<false>, dim3(lg), dim3(lb), llds, st, a, kap);
                 }
             } else if (c->method == PINO_CLASSIC) {
                 if (al) {
