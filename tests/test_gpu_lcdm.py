@@ -171,6 +171,40 @@ def test_lcdm_unaligned_matches_aligned(pkg, orc, n):
             label=f"LCDM unaligned n={n}")
 
 
+@pytest.mark.parametrize("nk", [1024, 2048])
+def test_lcdm_large_tables_both_layouts(pkg, orc, nk):
+    """The collapse kernels read the ratio splines as power-form coefficients
+    per interval where those fit in LDS (1024 knots: about 139 KB) and as the
+    (k, M) rows at the knots past that (2048 knots: the coefficients would
+    need 254 KB, the rows need 156 KB).  Either way the paired and the
+    one-per-lane kernels agree bit for bit and match the oracle on three C1
+    radii."""
+    cfg, slabs, _, _ = c1_inputs()
+    om = cfg["cosmo"].omega_m
+    a, D = synth.growth_table(om, nk)
+    n = 4001
+    hs = [s[:, :n].contiguous() for s in slabs[:3]]
+    with pkg.Collapse([(a, D, om)], method=pkg.PINO_CLASSIC_LCDM) as col:
+        F1, R1, A1 = col.outputs(n)
+        bufF = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+        bufR = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        bufA = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+        F2, R2, A2 = bufF[1:], bufR[1:], bufA[1:]
+        last = len(hs) - 1
+        for r, h in enumerate(hs):
+            hd = h.cuda()
+            buf = torch.empty((6, n + 1), dtype=torch.float64, device="cuda")
+            buf[:, 1:] = hd
+            hu = [buf[c, 1:] for c in range(6)]
+            col.apply(hd, r, F1, R1, A1 if r == last else None, reset=(r == 0), finalize=(r == last))
+            col.apply(hu, r, F2, R2, A2 if r == last else None, reset=(r == 0), finalize=(r == last))
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F2) and torch.equal(R1, R2) and torch.equal(A1, A2)
+    ref, skip, _ = _lcdm_ref(orc, hs, a, D, om)
+    compare(ref, (F1.cpu().numpy(), R1.cpu().numpy(), A1.cpu().numpy()), tie_mask=skip,
+            label=f"LCDM with {nk} growth knots")
+
+
 def test_lcdm_unsupported_combinations(pkg):
     a, D = synth.growth_table(0.3)
     for kw in (dict(precision=pkg.PINO_MIXED),):
