@@ -112,13 +112,18 @@ def test_lcdm_eds_equals_classic(pkg, orc):
     assert np.array_equal(R1, R0)
 
 
-def test_lcdm_special_and_ragged(pkg, orc):
+@pytest.mark.parametrize("nk", [512, 2048])
+def test_lcdm_special_and_ragged(pkg, orc, nk):
     """Diagonal, spherical, planar, repeated and zero spectra, NaN input, and
-    item sizes that leave partial waves."""
-    a, D = synth.growth_table(0.3)
+    item sizes that leave partial waves; collapse before the first growth
+    knot (lambda_1 of 900-2000, D_c below D_0 = 1.3e-3) and after the last
+    one, where the ratios are held at their end values.  512 knots read the
+    ratio splines as power-form coefficients, 2048 as the (k, M) rows."""
+    a, D = synth.growth_table(0.3, nk)
     rows = []
     for lam in [(1, 1, 1), (2, 0, 0), (1, 1, 0), (3, 3, -1), (0.5, -0.5, -0.5), (40.0, 3.0, -2.0), (-1, -2, -3),
-                (0, 0, 0), (1e-3, 0, 0), (0.05, 0.01, -0.02), (8.0, 7.9, 7.8)]:
+                (0, 0, 0), (1e-3, 0, 0), (0.05, 0.01, -0.02), (8.0, 7.9, 7.8), (2000.0, 10.0, -5.0),
+                (900.0, 899.0, 898.0), (1500.0, -700.0, -700.0)]:
         rows.append([lam[0], lam[1], lam[2], 0, 0, 0])
     rng = np.random.default_rng(8)
     rows += list(rng.normal(size=(300, 6)) * rng.uniform(0.1, 3.0, size=(300, 1)))
@@ -132,7 +137,7 @@ def test_lcdm_special_and_ragged(pkg, orc):
         orc.update_radius(h, 0, g, F, R, A, reset=True, method=orc.CLASSIC_LCDM)
         with pkg.Collapse([(a, D, 0.3)], method=pkg.PINO_CLASSIC_LCDM) as col:
             got = run_gpu_radii(col, [torch.from_numpy(h).cuda()])
-        compare((F, R, A), got, label=f"LCDM special n={n}")
+        compare((F, R, A), got, label=f"LCDM special n={n} ({nk} knots)")
     # NaN never updates the maximum
     hn = np.full((6, 3), np.nan)
     with pkg.Collapse([(a, D, 0.3)], method=pkg.PINO_CLASSIC_LCDM) as col:
