@@ -825,29 +825,39 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in radii]
-          for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_start.record(stream)
     for k in range(args.steps):
-        step(ev[k])
+        step()
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_end)
-    launch_ms = np.array([[e[0].elapsed_time(e[1]) for e in ev[k]] for k in range(args.steps)])
     log(f"timed {args.steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.2f} ms)")
+
+    # the spread of single launches, from as many steps again after the
+    # timed region with an event pair around every launch (those events put
+    # a few microseconds between launches, about 3 % of a step, so they stay
+    # out of the timed region)
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in radii]
+          for _ in range(args.steps)]
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    launch_ms = np.array([[e[0].elapsed_time(e[1]) for e in ev[k]] for k in range(args.steps)])
 
     evals_per_step = n * len(radii)
     ms_per_step = total_ms / args.steps
     value = evals_per_step / (ms_per_step * 1e-3)
 
     # roofline of the collapse kernel: algorithmic bytes of each launch over
-    # its measured duration, averaged over launches
-    mean_launch_ms = float(launch_ms.mean())
+    # its mean duration in the timed region (a step is the 25 launches of
+    # this kernel back to back, so the timed region over the launch count is
+    # that mean, gaps between launches included)
+    mean_launch_ms = total_ms / (args.steps * len(radii))
     mean_bytes = float(np.mean(bytes_per_launch))
     achieved_gbs = mean_bytes / (mean_launch_ms * 1e-3) / 1e9
     # measured HBM traffic and FP64 FLOPs per launch (scaled rocprofv3
@@ -863,9 +873,11 @@ def main():
                 "traffic": None if traffic is None else round(traffic / 1e9, 4),
                 "traffic_unit": "GB per launch",
                 "kernel": "k_classic_f64", "mean_launch_us": round(mean_launch_ms * 1e3, 2),
-                "median_launch_us": round(float(np.median(launch_ms)) * 1e3, 2),
-                "min_launch_us": round(float(launch_ms.min()) * 1e3, 2),
-                "launch_rsd": round(float(launch_ms.std() / launch_ms.mean()), 4),
+                "mean_launch_from": "timed region (HIP events on the kernel's stream) / launches",
+                "per_launch_events": {"mean_us": round(float(launch_ms.mean()) * 1e3, 2),
+                                      "median_us": round(float(np.median(launch_ms)) * 1e3, 2),
+                                      "min_us": round(float(launch_ms.min()) * 1e3, 2),
+                                      "rsd": round(float(launch_ms.std() / launch_ms.mean()), 4)},
                 "bytes_per_launch": int(mean_bytes), "update_fraction": round(
                     float(np.mean([u / n for u in updates[1:]])), 4)}
     if traffic is not None:
