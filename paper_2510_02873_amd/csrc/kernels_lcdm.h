@@ -21,11 +21,15 @@
 //   G(u) = 1 - u + k2(D) b u^2 + (k3a(D) ca + k3b(D) cb) u^3,
 // with b, ca + cb = c the Einstein-de Sitter coefficients of lpt_cubic split
 // into the determinant-type part ca = pp / (9 l1^2) and the mixed part cb.
-// The root: the Einstein-de Sitter cubic's first root gives D_e; the cubic
-// with the ratios frozen at D_e gives u1 (its first root, same solver); three
-// Newton steps on G itself (ratio derivatives from the splines) finish it.
-// The ratios move by about 1 % over the whole table, so u1 is within ~1e-5 of
-// the root and the Newton steps reach the rounding level.
+// The root: the Einstein-de Sitter cubic's first root u_e starts three
+// Newton steps on G itself (ratio derivatives from the splines); the ratios
+// move by about 1 % over the whole table, so u_e is that close to G's first
+// root and the steps reach the rounding level.  Where they do not settle on a
+// downward crossing near u_e, the cubic with the ratios frozen at D_e gives
+// u1 (its first root, within ~1e-5 of G's) and two Newton steps finish it.
+// The collapse kernels read the ratio splines in power form per interval
+// (k_kappa_poly) where that fits in LDS, else as values and second
+// derivatives at the knots; both describe the same cubic pieces.
 #pragma once
 
 #include "kernels_fp64.h"
