@@ -357,6 +357,30 @@ __device__ __forceinline__ double cubic_top_w(const CubicU& k)
     return w;
 }
 
+// Start of the Newton steps on G: the first positive root w = 1/u_e of the
+// Einstein-de Sitter cubic k to about 1e-5, which is all a start ~1 % from
+// G's root needs: the FP32 estimate of top_root_w and one FP64 Halley step
+// (top_root_w takes two, for a root to the rounding level), with its test
+// that w is the cubic's largest root.  false if the step did not settle or
+// the test fails.
+__device__ __forceinline__ bool eds_start_w(const CubicU& k, double& w)
+{
+    w = (double)top_root_guess(k.b, k.c);
+    const double q = ((w - 1.0) * w + k.b) * w + k.c;
+    const double q1 = (3.0 * w - 2.0) * w + k.b;
+    const double q2 = 6.0 * w - 2.0;
+    const double step = (2.0 * q * q1) * rcp1(2.0 * q1 * q1 - q * q2);
+    w -= step;
+    bool ok = fabs(step) <= 1e-5 * fabs(w) && w > 0.0;
+    const float e = (float)(1.0 - 3.0 * k.b);
+    if (e > 0.0f) {
+        const double wc = (double)((1.0f + sqrtf(e)) * (1.0f / 3.0f));
+        const double qc = ((wc - 1.0) * wc + k.b) * wc + k.c;
+        ok = ok && (w >= wc * (1.0 + 1e-6) || qc > 0.0);
+    }
+    return ok;
+}
+
 // Newton steps on G.  From the Einstein-de Sitter root (within the LCDM
 // correction, under 1 %, of G's root) three steps reach the rounding level;
 // from the frozen-ratio root (within about 1e-5) two do (a third moves D_c by
@@ -394,12 +418,13 @@ __device__ __forceinline__ bool lcdm_newton(double& u, int n, double il1, double
 // knots and ratio splines (KapRows or KapPoly).
 //
 // Fast path: Newton on G from the first root u_e of the Einstein-de Sitter
-// cubic, accepted when it converged to a downward crossing within 5 % of
-// u_e (the ratios move by about 1 % over the table, so G's first root is
-// that close to u_e unless G is nearly tangent there).  Otherwise (or with
-// no EdS root) the robust path: the cubic with the ratios frozen at D_e (or
-// at the last knot) gives the first root of a cubic within about 1e-5 of G,
-// then Newton steps.
+// cubic (eds_start_w), accepted when it converged to a downward crossing
+// within 5 % of u_e (the ratios move by about 1 % over the table, so G's
+// first root is that close to u_e unless G is nearly tangent there).
+// Otherwise (or with no EdS root) the robust path: the EdS root to the
+// rounding level, then the cubic with the ratios frozen at D_e (or at the
+// last knot) gives the first root of a cubic within about 1e-5 of G, then
+// Newton steps.
 template <class Src>
 __device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const Src& src)
 {
@@ -411,13 +436,14 @@ __device__ __forceinline__ double lcdm_F(double l1, double s, double pp, const S
     const double b = (-3.0 / 14.0) * sg;
     const double ca = pi * (1.0 / 9.0);
     const double cb = -(sg * (1.0 / 56.0) + pi * (2.0 / 56.0) + (17.0 / 168.0) * (sg * sg));
-    double w = cubic_top_w(CubicU{b, ca + cb});
-    if (w > 0.0) {
+    double w;
+    if (eds_start_w(CubicU{b, ca + cb}, w)) {
         const double ue = rcp2(w);
         double u = ue;
         if (lcdm_newton(u, kLcdmNewtonFromEds, il1, b, ca, cb, src) && fabs(u - ue) <= 0.05 * ue)
             return l1 * rcp2(u);
     }
+    w = cubic_top_w(CubicU{b, ca + cb});
     const double De = w > 0.0 ? rcp2(l1 * w) : src.D[src.nk - 1];
     const Kappa k = kappa_eval(piece_at(src, De), De);
     w = cubic_top_w(CubicU{k.k2 * b, k.k3a * ca + k.k3b * cb});
