@@ -108,7 +108,7 @@ struct pino_ctx {
     // per cosmology, bounds on |d k / d ln D| of the three ratio splines over
     // the whole table (the surrogate's LCDM certificate)
     std::vector<double> kslope;
-    // launch shape of the LCDM kernel: its LDS (knots, index and ratio rows)
+    // launch shape of the LCDM kernel: its LDS (knots, index and ratio splines)
     // limits the resident blocks per CU, so the grid is capped at what fits
     int lcdm_block = 512;
     int lcdm_resident = 1;
