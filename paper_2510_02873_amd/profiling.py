@@ -246,6 +246,40 @@ def kernel_table(trace, out, command, pattern=r"pino::|k_probe"):
     print("\n".join(lines))
 
 
+def counter_table(pmc, out, command, kernels, evals_per_launch=None):
+    """Median per dispatch of every counter of one rocprofv3 --pmc run, one
+    row per kernel (with its digest), and per 64 evaluations when the
+    launches' evaluation count is given.  The median, so that a few smaller
+    dispatches of the same kernel (a benchmark's table fills) do not move
+    the figure of its full-size launches."""
+    rows = _csv(pmc, "counter_collection.csv")
+    names = sorted({r["Counter_Name"] for r in rows})
+    lines = ["# rocprofv3 counters per kernel", f"command: {command}", "",
+             "kernel | kernel_digest | dispatches | " + " | ".join(f"{n} (median)" for n in names)]
+    per64 = []
+    for k in kernels:
+        vals = {}
+        for n in names:
+            v = [x for x, _ in _counter(rows, n, k)]
+            vals[n] = float(np.median(v)) if v else None
+        count = len(_counter(rows, names[0], k)) if names else 0
+        try:
+            dig = kernel_digest(k)
+        except (KeyError, ValueError):
+            dig = "-"
+        lines.append(f"{k} | {dig} | {count} | " + " | ".join("-" if vals[n] is None else f"{vals[n]:.4e}"
+                                                              for n in names))
+        if evals_per_launch:
+            per64.append(f"{k}: " + ", ".join(f"{n} {vals[n] * 64.0 / evals_per_launch:.2f}"
+                                              for n in names if vals[n] is not None))
+    if per64:
+        lines += ["", f"per 64 evaluations ({evals_per_launch:.0f} evaluations per launch):"] + per64
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def read_profile(path):
     """The key: value figures of a summary (floats where they parse), or {}."""
     if not os.path.exists(path):
@@ -279,6 +313,12 @@ def main():
     t.add_argument("--trace", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--command", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("--pmc", required=True, help="rocprofv3 --pmc output directory")
+    c.add_argument("--kernels", required=True, help="comma-separated kernel names")
+    c.add_argument("--evals-per-launch", type=float, default=None)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", default="")
     d = sub.add_parser("digest")
     d.add_argument("kernel")
     a = ap.parse_args()
@@ -287,6 +327,9 @@ def main():
         return
     if a.cmd == "table":
         kernel_table(a.trace, a.out, a.command)
+        return
+    if a.cmd == "counters":
+        counter_table(a.pmc, a.out, a.command, a.kernels.split(","), a.evals_per_launch)
         return
     summarize(a.kernel, a.trace, a.fetch, a.write, a.calib_mib, a.out, a.command, a.flops, a.evals_per_launch,
               a.extra)

@@ -43,3 +43,24 @@ def test_committed_headline_summary_parses():
 
 def test_read_profile_missing_file_is_empty():
     assert profiling.read_profile(os.path.join(ROOT, "profiles", "no_such_file.txt")) == {}
+
+
+def test_counter_table_takes_the_median_per_kernel(tmp_path):
+    """The counters subcommand reads one --pmc run's CSV and reports, per
+    kernel named exactly (k_x does not take k_x_1's rows), the median per
+    dispatch and the figure per 64 evaluations."""
+    from paper_2510_02873_amd import profiling
+    d = tmp_path / "pmc" / "host"
+    d.mkdir(parents=True)
+    rows = [("pino::k_x(int)", "C_A", v) for v in (10.0, 1000.0, 1000.0)]
+    rows += [("pino::k_x_1(int)", "C_A", 5.0), ("pino::k_x(int)", "C_B", 64.0)]
+    with open(d / "run_counter_collection.csv", "w") as f:
+        f.write("Kernel_Name,Counter_Name,Counter_Value\n")
+        for k, c, v in rows:
+            f.write(f'"{k}",{c},{v}\n')
+    out = tmp_path / "t.txt"
+    profiling.counter_table(str(tmp_path / "pmc"), str(out), "cmd", ["k_x"], evals_per_launch=128)
+    text = out.read_text()
+    line = [ln for ln in text.splitlines() if ln.startswith("k_x |")][0]
+    assert "| 3 |" in line and "1.0000e+03" in line and "6.4000e+01" in line
+    assert "k_x: C_A 500.00, C_B 32.00" in text
