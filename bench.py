@@ -113,6 +113,31 @@ def measure_extras(P, col, slabs, radii, n, a, D, cfg, n_side, stream, Fmax, Rma
                     "roofline": step_roofline(step_bytes(24), ms)}
     mcol.close()
 
+    # the same FP64 workload through the batched persistent launch: the 25
+    # radii are resident anyway, so one launch per step carries each particle
+    # through all of them with the running maximum in registers (48 B per
+    # evaluation plus 20 B per particle); its outputs must equal the
+    # per-radius evals' bit for bit
+    try:
+        from paper_2510_02873_amd import _abi
+        Fb, Rb, Ab = col.outputs(n)
+        bat = _abi.Batch(col.ctx, [{"h": slabs, "Fmax": Fb, "Rmax": Rb, "a_coll": Ab, "cosmo": 0}],
+                         flags=P.PINO_EVAL_RESET | P.PINO_EVAL_FINALIZE, autotune=True)
+        gs = torch.cuda.Stream()
+        with torch.cuda.stream(gs):
+            ms = _time_steps(lambda: bat.graph_launch(gs), steps, gs)
+        out["batched_same_fields"] = {
+            "value": round(n * len(radii) / (ms * 1e-3), 1), "unit": "evals/s", "ms_per_step": round(ms, 4),
+            "dtype": "f64", "workload": f"same {n_side}^3 x {len(radii)} fields, all radii resident",
+            "launch": "one persistent kernel per step, HIP graph replay", "autotuned": bat.config(),
+            "identical_to_per_radius": bool(torch.equal(Fb, F64) and torch.equal(Rb, R64) and torch.equal(Ab, A64)),
+            "vs_per_radius_throughput": round(plain_ms / ms, 4) if plain_ms else None,
+            "roofline": step_roofline(n * (48 * len(radii) + 20), ms)}
+        bat.close()
+        del Fb, Rb, Ab
+    except RuntimeError as e:
+        out["batched_same_fields"] = {"error": str(e)[:300]}
+
     out["surrogate"] = measure_surrogate(P, slabs, radii, sig, n, a, D, cfg, n_side, stream, F64, R64, steps,
                                          train_steps, blob_path, blob_out)
     out["_blob"] = out["surrogate"].pop("blob")
